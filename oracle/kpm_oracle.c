@@ -1,0 +1,294 @@
+/*
+ * kpm_oracle.c -- plain CPU oracle for the Kernel Polynomial Method (KPM)
+ * density-of-states path of Kreutzer, Hager, Wellein, Pieper, Alvermann and
+ * Fehske, "Performance Engineering of the Kernel Polynomial Method on
+ * Large-Scale CPU-GPU Systems" (arXiv:1410.5242).
+ *
+ * TEST INFRASTRUCTURE. Only the test suite, the smoke check and the CPU
+ * baseline leg of the benchmark load this library. It includes nothing from
+ * the GPU library and the GPU library includes nothing from it.
+ *
+ * Everything is IEEE double / double complex in compressed row storage (CRS).
+ * There is no blocking, fusion or reordering beyond what the paper's
+ * algorithms state: each step is written the obvious way so that it can be
+ * checked against the paper by eye. The only parallelism is an OpenMP
+ * "parallel for" over independent matrix rows in the sparse products; every
+ * reduction (dot product, Gershgorin extremum) is a sequential loop.
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef double complex zc;
+
+/* ------------------------------------------------------------------------- */
+/* Dirac matrices of the topological-insulator Hamiltonian (eq. "Ham").      */
+/* Orbital index o = 2*tau + s: the first Kronecker factor (tau) is the      */
+/* outer one.  Gamma^1 = tau_z (x) s_0, Gamma^{2,3,4} = tau_x (x) s_{x,y,z}. */
+/* Gamma^0 is the 4x4 identity (the onsite potential multiplies it).         */
+/* ------------------------------------------------------------------------- */
+static void pauli(int which, zc p[2][2])
+{
+    /* which: 0 = identity, 1 = x, 2 = y, 3 = z */
+    p[0][0] = p[0][1] = p[1][0] = p[1][1] = 0;
+    switch (which) {
+    case 0: p[0][0] = 1; p[1][1] = 1; break;
+    case 1: p[0][1] = 1; p[1][0] = 1; break;
+    case 2: p[0][1] = -I; p[1][0] = I; break;
+    case 3: p[0][0] = 1; p[1][1] = -1; break;
+    }
+}
+
+static void kron2(zc a[2][2], zc b[2][2], zc out[4][4])
+{
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j)
+            for (int k = 0; k < 2; ++k)
+                for (int l = 0; l < 2; ++l)
+                    out[2 * i + k][2 * j + l] = a[i][j] * b[k][l];
+}
+
+/* gamma(a): a = 0..4 as in eq. "Ham" (a = 0 is the identity). */
+static void gamma_matrix(int a, zc g[4][4])
+{
+    zc tau[2][2], sig[2][2];
+    if (a == 0) { pauli(0, tau); pauli(0, sig); }
+    else if (a == 1) { pauli(3, tau); pauli(0, sig); }
+    else { pauli(1, tau); pauli(a - 1, sig); }
+    kron2(tau, sig, g);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Hamiltonian builder (eq. "Ham"), CRS with columns sorted and duplicate    */
+/* (row, col) pairs summed.                                                  */
+/*                                                                           */
+/* Site n = x + Lx*(y + Ly*z); row index 4*n + o.                            */
+/* Hopping term  -t * Psi^dag_{n+e_j} (Gamma^1 - i Gamma^{j+1})/2 Psi_n      */
+/* puts the block T_j = -t (Gamma^1 - i Gamma^{j+1}) / 2 at                  */
+/* (rows of n+e_j, columns of n); its Hermitian conjugate puts T_j^dagger at */
+/* (rows of n, columns of n+e_j).  Onsite block: V_n * Gamma^0 + 2 Gamma^1.  */
+/* A neighbour outside a non-periodic side is dropped (open boundary).       */
+/* An entry is structural when its Gamma pattern is nonzero, independent of */
+/* t and V_n, and the diagonal is always stored.                            */
+/* ------------------------------------------------------------------------- */
+typedef struct { int64_t col; zc v; } entry;
+
+static int cmp_entry(const void* pa, const void* pb)
+{
+    const entry* a = (const entry*)pa;
+    const entry* b = (const entry*)pb;
+    return (a->col > b->col) - (a->col < b->col);
+}
+
+static int64_t wrap(int64_t x, int64_t L, int periodic, int* ok)
+{
+    if (x >= 0 && x < L) { *ok = 1; return x; }
+    if (!periodic) { *ok = 0; return 0; }
+    *ok = 1;
+    return ((x % L) + L) % L;
+}
+
+/* Returns the number of stored entries, or -1 if cap is too small or the
+ * arguments are invalid.  With rowptr == NULL only the count is returned. */
+int64_t oracle_ti_build(int Lx, int Ly, int Lz, const int* periodic, double t,
+                        const double* pot, int64_t* rowptr, int32_t* col,
+                        double* val_ri, int64_t cap)
+{
+    if (Lx <= 0 || Ly <= 0 || Lz <= 0) return -1;
+    const int64_t L[3] = {Lx, Ly, Lz};
+    const int64_t nsite = (int64_t)Lx * Ly * Lz;
+    zc g[5][4][4];
+    for (int a = 0; a < 5; ++a) gamma_matrix(a, g[a]);
+    zc T[3][4][4];      /* T_j = -t (Gamma^1 - i Gamma^{j+1}) / 2 */
+    int Tpat[3][4][4];  /* structural pattern of Gamma^1 - i Gamma^{j+1} */
+    for (int j = 0; j < 3; ++j)
+        for (int o = 0; o < 4; ++o)
+            for (int p = 0; p < 4; ++p) {
+                zc pat = g[1][o][p] - I * g[j + 2][o][p];
+                Tpat[j][o][p] = (pat != 0);
+                T[j][o][p] = -t * pat / 2.0;
+            }
+    entry buf[64];
+    int64_t nnz = 0;
+    if (rowptr) rowptr[0] = 0;
+    for (int64_t n = 0; n < nsite; ++n) {
+        const int64_t xyz[3] = {n % Lx, (n / Lx) % Ly, n / ((int64_t)Lx * Ly)};
+        for (int o = 0; o < 4; ++o) {
+            int cnt = 0;
+            /* onsite block: V_n Gamma^0 + 2 Gamma^1 (diagonal always stored) */
+            for (int p = 0; p < 4; ++p) {
+                zc v = pot[n] * g[0][o][p] + 2.0 * g[1][o][p];
+                if (p == o || v != 0) { buf[cnt].col = 4 * n + p; buf[cnt].v = v; ++cnt; }
+            }
+            for (int j = 0; j < 3; ++j) {
+                /* row (n, o) as the n+e_j side: partner site m = n - e_j,
+                 * entry T_j[o][p] at column (m, p). */
+                int ok;
+                int64_t c[3] = {xyz[0], xyz[1], xyz[2]};
+                c[j] = wrap(xyz[j] - 1, L[j], periodic[j], &ok);
+                if (ok) {
+                    int64_t m = c[0] + Lx * (c[1] + Ly * c[2]);
+                    for (int p = 0; p < 4; ++p)
+                        if (Tpat[j][o][p]) { buf[cnt].col = 4 * m + p; buf[cnt].v = T[j][o][p]; ++cnt; }
+                }
+                /* row (n, o) as the n side of the conjugate term: partner
+                 * m = n + e_j, entry (T_j^dagger)[o][p] = conj(T_j[p][o]). */
+                c[0] = xyz[0]; c[1] = xyz[1]; c[2] = xyz[2];
+                c[j] = wrap(xyz[j] + 1, L[j], periodic[j], &ok);
+                if (ok) {
+                    int64_t m = c[0] + Lx * (c[1] + Ly * c[2]);
+                    for (int p = 0; p < 4; ++p)
+                        if (Tpat[j][p][o]) { buf[cnt].col = 4 * m + p; buf[cnt].v = conj(T[j][p][o]); ++cnt; }
+                }
+            }
+            qsort(buf, (size_t)cnt, sizeof(entry), cmp_entry);
+            int out = 0;
+            for (int k = 0; k < cnt; ++k) {
+                if (out > 0 && buf[out - 1].col == buf[k].col) buf[out - 1].v += buf[k].v;
+                else buf[out++] = buf[k];
+            }
+            if (rowptr) {
+                if (nnz + out > cap) return -1;
+                for (int k = 0; k < out; ++k) {
+                    col[nnz + k] = (int32_t)buf[k].col;
+                    val_ri[2 * (nnz + k)] = creal(buf[k].v);
+                    val_ri[2 * (nnz + k) + 1] = cimag(buf[k].v);
+                }
+                rowptr[4 * n + o + 1] = nnz + out;
+            }
+            nnz += out;
+        }
+    }
+    return nnz;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Gershgorin circles: every eigenvalue lies in some disc centred at Re H_ii */
+/* with radius sum_{j != i} |H_ij|.  Returns the outer bounds.               */
+/* ------------------------------------------------------------------------- */
+void oracle_gershgorin(int64_t N, const int64_t* rowptr, const int32_t* col,
+                       const double* val_ri, double* emin, double* emax)
+{
+    double lo = INFINITY, hi = -INFINITY;
+    for (int64_t i = 0; i < N; ++i) {
+        double c = 0.0, r = 0.0;
+        for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+            zc h = val_ri[2 * k] + I * val_ri[2 * k + 1];
+            if (col[k] == i) c += creal(h);
+            else r += cabs(h);
+        }
+        if (c - r < lo) lo = c - r;
+        if (c + r > hi) hi = c + r;
+    }
+    *emin = lo;
+    *emax = hi;
+}
+
+/* y = Htilde x for an N x R block stored row-major (element (i, r) at
+ * i*R + r), Htilde = (H - b)/a. */
+static void apply_htilde(int64_t N, const int64_t* rowptr, const int32_t* col,
+                         const double* val_ri, double a, double b, int R,
+                         const zc* x, zc* y)
+{
+    #pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < N; ++i) {
+        for (int r = 0; r < R; ++r) {
+            zc s = 0;
+            for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+                zc h = val_ri[2 * k] + I * val_ri[2 * k + 1];
+                s += h * x[(int64_t)col[k] * R + r];
+            }
+            y[i * R + r] = (s - b * x[i * R + r]) / a;
+        }
+    }
+}
+
+/* column-wise <x_r | y_r> = sum_i conj(x_ir) y_ir, sequential in i */
+static void block_dot(int64_t N, int R, const zc* x, const zc* y, zc* out)
+{
+    for (int r = 0; r < R; ++r) out[r] = 0;
+    for (int64_t i = 0; i < N; ++i)
+        for (int r = 0; r < R; ++r)
+            out[r] += conj(x[i * R + r]) * y[i * R + r];
+}
+
+/* ------------------------------------------------------------------------- */
+/* KPM moments by the blocked algorithm (Alg. "kpm_improved_blocked",        */
+/* recurrence eq. "eq:kpm_iter").                                            */
+/*   nu_0 = v0, nu_1 = Htilde nu_0, nu_{m+1} = 2 Htilde nu_m - nu_{m-1}      */
+/*   eta_{2m} = <nu_m | nu_m>,  eta_{2m+1} = <nu_{m+1} | nu_m>               */
+/* M/2 sweeps in total (the initialisation sweep and M/2-1 recurrence        */
+/* sweeps) give eta_0 .. eta_{M-1}.  eta is [M][R] complex, stored as        */
+/* interleaved (re, im) doubles.  v0 is [N][R] complex, row-major.           */
+/* ------------------------------------------------------------------------- */
+int oracle_kpm_eta(int64_t N, const int64_t* rowptr, const int32_t* col,
+                   const double* val_ri, double a, double b, const double* v0_ri,
+                   int R, int M, double* eta_ri)
+{
+    if (N <= 0 || R <= 0 || M < 2 || (M % 2) != 0 || a == 0.0) return -1;
+    zc* V = (zc*)malloc(sizeof(zc) * (size_t)N * R);
+    zc* W = (zc*)malloc(sizeof(zc) * (size_t)N * R);
+    zc* d = (zc*)malloc(sizeof(zc) * (size_t)R);
+    if (!V || !W || !d) { free(V); free(W); free(d); return -2; }
+    zc* eta = (zc*)eta_ri;
+    for (int64_t i = 0; i < N * R; ++i) V[i] = v0_ri[2 * i] + I * v0_ri[2 * i + 1];
+
+    /* initialisation: W = nu_1 = Htilde nu_0; eta_0, eta_1 */
+    apply_htilde(N, rowptr, col, val_ri, a, b, R, V, W);
+    block_dot(N, R, V, V, d);
+    for (int r = 0; r < R; ++r) eta[0 * R + r] = d[r];
+    block_dot(N, R, W, V, d);
+    for (int r = 0; r < R; ++r) eta[1 * R + r] = d[r];
+
+    zc* U = (zc*)malloc(sizeof(zc) * (size_t)N * R);
+    if (!U) { free(V); free(W); free(d); return -2; }
+    for (int m = 1; m < M / 2; ++m) {
+        zc* tmp = V; V = W; W = tmp;          /* V = nu_m, W = nu_{m-1} */
+        apply_htilde(N, rowptr, col, val_ri, a, b, R, V, U);
+        #pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < N * R; ++i) W[i] = 2.0 * U[i] - W[i];  /* nu_{m+1} */
+        block_dot(N, R, V, V, d);
+        for (int r = 0; r < R; ++r) eta[(2 * m) * R + r] = d[r];
+        block_dot(N, R, W, V, d);
+        for (int r = 0; r < R; ++r) eta[(2 * m + 1) * R + r] = d[r];
+    }
+    free(U); free(V); free(W); free(d);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Second, independent path to the moments: mu_n = <nu_0 | nu_n> for every   */
+/* n < M straight from the recurrence (M-1 products, no doubling identity).  */
+/* out is [R][M] complex (interleaved doubles).                              */
+/* ------------------------------------------------------------------------- */
+int oracle_kpm_direct(int64_t N, const int64_t* rowptr, const int32_t* col,
+                      const double* val_ri, double a, double b, const double* v0_ri,
+                      int R, int M, double* out_ri)
+{
+    if (N <= 0 || R <= 0 || M < 1 || a == 0.0) return -1;
+    zc* nu0 = (zc*)malloc(sizeof(zc) * (size_t)N * R);
+    zc* prev = (zc*)malloc(sizeof(zc) * (size_t)N * R);
+    zc* cur = (zc*)malloc(sizeof(zc) * (size_t)N * R);
+    zc* nxt = (zc*)malloc(sizeof(zc) * (size_t)N * R);
+    zc* d = (zc*)malloc(sizeof(zc) * (size_t)R);
+    if (!nu0 || !prev || !cur || !nxt || !d) {
+        free(nu0); free(prev); free(cur); free(nxt); free(d); return -2;
+    }
+    zc* out = (zc*)out_ri;
+    for (int64_t i = 0; i < N * R; ++i) nu0[i] = v0_ri[2 * i] + I * v0_ri[2 * i + 1];
+    memcpy(cur, nu0, sizeof(zc) * (size_t)N * R);
+    block_dot(N, R, nu0, cur, d);
+    for (int r = 0; r < R; ++r) out[(int64_t)r * M + 0] = d[r];
+    for (int n = 1; n < M; ++n) {
+        apply_htilde(N, rowptr, col, val_ri, a, b, R, cur, nxt);
+        if (n >= 2)
+            for (int64_t i = 0; i < N * R; ++i) nxt[i] = 2.0 * nxt[i] - prev[i];
+        zc* tmp = prev; prev = cur; cur = nxt; nxt = tmp;
+        block_dot(N, R, nu0, cur, d);
+        for (int r = 0; r < R; ++r) out[(int64_t)r * M + n] = d[r];
+    }
+    free(nu0); free(prev); free(cur); free(nxt); free(d);
+    return 0;
+}
