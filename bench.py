@@ -1,0 +1,216 @@
+#!/usr/bin/env python3
+"""Benchmark of the KPM-DOS hot path on one MI355X.
+
+Workload: the topological-insulator Hamiltonian on a periodic 64x64x64
+lattice (N = 1,048,576 rows, 13 stored entries per row), disorder gamma = 1,
+R = 32 random-phase start vectors, M = 2000 Chebyshev moments, complex128
+storage, FP64 scalar products, Jackson-kernel DOS on 4096 energies.
+
+One step = kpm_moments (1000 fused aug_spmmv sweeps, the deterministic
+scalar-product reductions, the eta -> mu identity and the moment check) plus
+kpm_dos, on a Hamiltonian and start block already resident in HBM.  The
+metric is the paper's minimum traffic of the blocked sweep,
+V = Nnz (S_d + S_i) + 3 R S_d N bytes per sweep, divided by the step time.
+
+Prints ONE JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "aug_spmmv HBM GB/s (% peak) & Gflop/s; time-to-DOS at fixed L1 err, plain vs opt"
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+WORKLOADS = {
+    # name: (L, gamma, R, M, dtype, K)
+    "ti64_r32_m2000_c128": ((64, 64, 64), 1.0, 32, 2000, "c128", 4096),
+    "ti128x128x64_r32_m2000_c64": ((128, 128, 64), 2.0, 32, 2000, "c64", 4096),
+}
+SWEEP_KERNEL = "aug_spmmv_kernel"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "aug_spmmv_traffic.json")
+SWEEP_SOURCE = os.path.join(ROOT, "paper_1410_5242_amd", "csrc", "kpm_spmmv.hip")
+
+
+def log(msg: str):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def sweep_bytes(N, nnz, R, Sd, Si=4):
+    """Minimum bytes per blocked sweep: Nnz (S_d + S_i) + 3 R S_d N."""
+    return nnz * (Sd + Si) + 3 * R * Sd * N
+
+
+def sweep_flops(N, R, nnzr=13, Fa=2, Fm=6):
+    """Flops per sweep: R N [Nnzr (Fa + Fm) + ceil(7 Fa / 2) + ceil(9 Fm / 2)]."""
+    return R * N * (nnzr * (Fa + Fm) + math.ceil(7 * Fa / 2) + math.ceil(9 * Fm / 2))
+
+
+def traffic_record(bytes_per_sweep):
+    """HBM bytes per sweep from the committed rocprofv3 counters, if they match this kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    rec = json.load(open(TRAFFIC_FILE))
+    sha = hashlib.sha256(open(SWEEP_SOURCE, "rb").read()).hexdigest()
+    if rec.get("source_sha256") != sha:
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(L, gamma, R, dtype, target_s=15.0):
+    """Time the plain CPU oracle on a bounded number of sweeps of the same workload."""
+    import numpy as np
+    import oracle as O
+    from paper_1410_5242_amd import inputs
+    pot = inputs.potential(L, gamma, 0)
+    Ho = O.ti_hamiltonian(L, pot)
+    a, b = O.scaling(*O.gershgorin(Ho))
+    v0 = inputs.phase_block(Ho.n, R, 0)
+    t0 = time.perf_counter()
+    O.kpm_eta(Ho, a, b, v0, 2)
+    t1 = time.perf_counter() - t0
+    sweeps = int(max(1, min(64, target_s / max(t1, 1e-3))))
+    t0 = time.perf_counter()
+    O.kpm_eta(Ho, a, b, v0, 2 * sweeps)
+    dt = time.perf_counter() - t0
+    Sd = 16  # the oracle always runs in complex128
+    bps = sweep_bytes(Ho.n, 13 * Ho.n, R, Sd)
+    threads = O.lib_threads()
+    return {"value": round(bps * sweeps / dt / 1e9, 3), "unit": "GB/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{sweeps} sweeps (M={2 * sweeps}) of the same lattice, R and seed, complex128, "
+                      f"{dt:.2f} s; Gflop/s {sweep_flops(Ho.n, R) * sweeps / dt / 1e9:.2f}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="ti64_r32_m2000_c128", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-target-s", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU sharding is a design, "
+              f"not built", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1410_5242_amd import inputs, kpm
+
+    L, gamma, R, M, dtype, K = WORKLOADS[args.workload]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    log(f"[bench] workload {args.workload}: L={L} gamma={gamma} R={R} M={M} dtype={dtype}")
+
+    pot = inputs.potential(L, gamma, 0)
+    t0 = time.perf_counter()
+    H = kpm.build_hamiltonian(L, pot, dtype=dtype)
+    build_s = time.perf_counter() - t0
+    N = H.N
+    Sd = 16 if dtype == "c128" else 8
+    V0 = torch.from_numpy(inputs.phase_block(N, R, 0, dtype=np.complex128 if dtype == "c128" else np.complex64)).to(dev)
+    E = torch.from_numpy((H.b + H.a * (-1.0 + (2.0 * np.arange(K) + 1.0) / K))).to(dev)
+    mu = torch.empty((R, M), dtype=torch.float64, device=dev)
+    rho = torch.empty(K, dtype=torch.float64, device=dev)
+    log(f"[bench] built H: N={N} a={H.a:.6f} b={H.b:.6f} ({build_s:.3f} s)")
+
+    def step():
+        kpm.moments(H, V0, M, mu=mu, check=True)
+        kpm.dos(mu, H.a, H.b, E, kernel="jackson", rho=rho)
+
+    for i in range(args.warmup):
+        step()
+        log(f"[bench] warmup {i + 1}/{args.warmup} done")
+    torch.cuda.synchronize()
+
+    kpm.sweep_profile_read()                 # clear
+    kpm.sweep_profile_enable(True)
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for i in range(args.steps):
+        step()
+        log(f"[bench] step {i + 1}/{args.steps} done")
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kpm.sweep_profile_enable(False)
+    n_sweeps, sweep_ms_tot, sweep_ms_min, sweep_ms_max = kpm.sweep_profile_read()
+    ms_per_step = ev0.elapsed_time(ev1) / args.steps
+
+    sweeps_per_step = M // 2
+    nnz = 13 * N
+    bps = sweep_bytes(N, nnz, R, Sd)
+    fps = sweep_flops(N, R)
+    value = bps * sweeps_per_step / (ms_per_step * 1e-3) / 1e9
+    gflops = fps * sweeps_per_step / (ms_per_step * 1e-3) / 1e9
+    sweep_avg_ms = sweep_ms_tot / max(1, n_sweeps)
+    achieved = bps / (sweep_avg_ms * 1e-3) / 1e9
+    rho_h = rho.cpu().numpy()
+    dos_integral = float(rho_h.sum() * 2.0 * H.a / K)
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if dtype == "c128" else "f32 (f64 products)",
+        "data": "synthetic",
+        "config": {
+            "workload": f"KPM-DOS, TI Hamiltonian {L[0]}x{L[1]}x{L[2]} periodic (N={N}, 13 nnz/row), "
+                        f"gamma={gamma}, R={R}, M={M}, {dtype}, Jackson DOS on {K} energies",
+            "sweeps_per_step": sweeps_per_step,
+            "bytes_per_sweep": bps,
+            "flops_per_sweep": fps,
+        },
+        "pct_hbm_peak": round(100.0 * value / HBM_PEAK_GBS, 2),
+        "gflops": round(gflops, 1),
+        "time_to_moments_and_dos_ms": round(ms_per_step, 3),
+        "dos_integral": round(dos_integral, 8),
+        "wall_s": round(wall, 3),
+        "build_ms": round(build_s * 1e3, 1),
+        "roofline": {
+            "bound": "hbm",
+            "kernel": SWEEP_KERNEL,
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic_record(bps),
+            "launches": n_sweeps,
+            "avg_launch_ms": round(sweep_avg_ms, 5),
+            "min_launch_ms": round(sweep_ms_min, 5),
+            "max_launch_ms": round(sweep_ms_max, 5),
+            "algorithmic_bytes_per_launch": bps,
+        },
+    }
+    H.close()
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(L, gamma, R, dtype, args.cpu_target_s)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

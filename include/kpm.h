@@ -1,0 +1,165 @@
+/*
+ * kpm.h -- C ABI of the MI355X (gfx950) Kernel Polynomial Method library.
+ *
+ * The library computes the Chebyshev moments and the density of states (DOS)
+ * of the topological-insulator Hamiltonian of Kreutzer et al., "Performance
+ * Engineering of the Kernel Polynomial Method on Large-Scale CPU-GPU
+ * Systems" (arXiv:1410.5242), with the fused, blocked, augmented sparse
+ * matrix times multiple-vector product ("aug_spmmv") of the paper's
+ * blocked algorithm (Alg. "kpm_improved_blocked") as its hot path.
+ *
+ * Conventions shared by every entry point
+ *  - Every function returns a kpm_status; KPM_OK (0) means success.  On any
+ *    other value kpm_last_error() returns a message for the calling thread.
+ *  - "device" pointers are HIP device allocations on the current device;
+ *    "host" pointers are ordinary host memory.  The caller owns every buffer
+ *    it passes in; the library owns the Hamiltonian handle and its internal
+ *    workspaces (released by kpm_destroy_hamiltonian).
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Work is enqueued on it.  Unless stated otherwise a call returns once the
+ *    work is enqueued; device outputs are valid after the stream is
+ *    synchronised.
+ *  - Complex numbers are stored as interleaved (re, im) pairs of the storage
+ *    precision.  A block of R vectors of length N is row-major ("interleaved"):
+ *    element (i, r) is complex number i*R + r.
+ *  - Scaling: Htilde = (H - b)/a, with b the centre and a the half-width of
+ *    an interval containing the spectrum (the paper writes the same map as
+ *    a(H - b) with a reciprocal a; this ABI uses the half-width form).
+ */
+#ifndef KPM_H
+#define KPM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    KPM_OK = 0,
+    KPM_EINVAL = -1,     /* invalid argument (null pointer, bad size, odd M, ...) */
+    KPM_ENOMEM = -2,     /* device allocation failed or the size is absurd */
+    KPM_EDEVICE = -3,    /* a HIP runtime call failed */
+    KPM_ENOTSUP = -4,    /* valid request that this library does not implement */
+    KPM_ESPECTRUM = -5,  /* moments left [-mu_0, mu_0]: the spectrum is not inside [-1, 1] */
+    KPM_EINTERNAL = -6
+} kpm_status;
+
+/* Storage precision of H and of the vector blocks.  The moment scalar
+ * products and their reductions are always accumulated in FP64. */
+typedef enum { KPM_C128 = 0, KPM_C64 = 1 } kpm_dtype;
+
+/* Damping kernel g_n of the DOS reconstruction. */
+typedef enum { KPM_JACKSON = 0, KPM_DIRICHLET = 1, KPM_LORENTZ = 2 } kpm_kernel;
+
+/* Sweep variants: the full fused sweep and the two diagnostic reductions of
+ * it that the paper uses to split bottlenecks (section "GPU Performance
+ * Model"): without the scalar products, and the plain SpMMV Y = H X. */
+typedef enum { KPM_FULL = 0, KPM_NODOT = 1, KPM_PLAIN = 2 } kpm_variant;
+
+typedef struct {
+    int32_t L[3];            /* lattice sides Lx, Ly, Lz (>= 1) */
+    int32_t periodic[3];     /* nonzero: periodic along that axis (side must be >= 3) */
+    double t;                /* hopping amplitude */
+    const double* potential; /* host [Lx*Ly*Lz] onsite V_n, site n = x + Lx*(y + Ly*z); required */
+    int32_t dtype;           /* kpm_dtype */
+    double margin;           /* half-width factor applied to the Gershgorin interval (e.g. 1.01) */
+    int32_t fixed_scale;     /* nonzero: use a, b below instead of the Gershgorin bound */
+    double a, b;             /* caller-fixed scaling when fixed_scale != 0 (a > 0) */
+} kpm_lattice_desc;
+
+typedef struct kpm_hamiltonian kpm_hamiltonian; /* opaque, library-owned */
+
+/* Build H of eq. "Ham" (section "Application Scenario") on the device:
+ *   H = -t sum_{j,n} (Psi^dag_{n+e_j} (Gamma^1 - i Gamma^{j+1})/2 Psi_n + h.c.)
+ *       + sum_n Psi^dag_n (V_n Gamma^0 + 2 Gamma^1) Psi_n
+ * with Gamma^0 = 1, Gamma^1 = tau_z(x)s_0, Gamma^{2,3,4} = tau_x(x)s_{x,y,z},
+ * orbital o = 2*tau + s, row 4*n + o.  N = 4*Lx*Ly*Lz rows, 13 stored
+ * entries per row (open boundaries pad missing neighbours with explicit
+ * zeros).  Then the Gershgorin interval [E_min, E_max] (section "Problem
+ * Description": a and b from Gershgorin's circle theorem) gives
+ * b = (E_max + E_min)/2 and a = margin (E_max - E_min)/2, unless
+ * desc->fixed_scale.  Synchronises `stream` (the bounds are read back).
+ * Errors: KPM_EINVAL (null desc/potential/out, side <= 0, non-finite
+ * potential or t, margin < 1, a <= 0), KPM_ENOTSUP (a periodic side < 3),
+ * KPM_ENOMEM, KPM_EDEVICE.  *out is NULL on error. */
+kpm_status kpm_build_hamiltonian(const kpm_lattice_desc* desc, void* stream,
+                                 kpm_hamiltonian** out);
+
+/* Sizes and scaling of a built H.  Any output pointer may be NULL.
+ * nnz_stored counts stored entries including padding (= width * N). */
+kpm_status kpm_hamiltonian_info(const kpm_hamiltonian* H, int64_t* N, int64_t* nnz_stored,
+                                int32_t* width, int32_t* dtype, double* a, double* b,
+                                double* emin, double* emax);
+
+/* Copy H to host CRS for inspection: rowptr [N+1], col [nnz], val [2*nnz]
+ * (re, im as double).  Explicit padding zeros are dropped; each row keeps
+ * the library's slot order (diagonal first).  Pass col = val = NULL to get
+ * only rowptr (and so the count).  Synchronous.  Errors: KPM_EINVAL. */
+kpm_status kpm_export_csr(const kpm_hamiltonian* H, int64_t* rowptr, int32_t* col, double* val);
+
+/* Release H and its workspaces (synchronises the device).  NULL is a no-op. */
+void kpm_destroy_hamiltonian(kpm_hamiltonian* H);
+
+/* One augmented sweep (Alg. "kpm_improved_blocked", the fused body):
+ *   W <- alpha * H V + beta * V + gamma * W            (variant FULL / NODOT)
+ *   eta[0][r] = <V_r|V_r>,  eta[1][r] = <W_r|V_r>     (FULL only, new W)
+ *   W <- H V                                           (variant PLAIN)
+ * V, W: device [N][R] blocks of H's dtype, V read-only, W updated in place;
+ * V and W must not overlap.  eta: device [2][R] complex double, written for
+ * FULL when non-NULL (it is reduced on the device, deterministically).
+ * R in {1, 2, 4, 8, 16, 32, 64}.  Errors: KPM_EINVAL, KPM_ENOTSUP. */
+kpm_status kpm_aug_spmmv(const kpm_hamiltonian* H, const void* V, void* W, int32_t R,
+                         double alpha, double beta, double gamma, int32_t variant,
+                         double* eta, void* stream);
+
+/* Chebyshev moments for R start vectors (eq. "eq:kpm_iter", scalar products
+ * eta_{2m} = <nu_m|nu_m>, eta_{2m+1} = <nu_{m+1}|nu_m>, blocked algorithm):
+ * M/2 fused sweeps on the device give eta_0 .. eta_{M-1}, then
+ *   mu_0 = eta_0, mu_1 = Re eta_1, mu_{2m} = 2 eta_{2m} - mu_0,
+ *   mu_{2m+1} = 2 Re eta_{2m+1} - mu_1      (per start vector r).
+ * V0: device [N][R] block in H's dtype (read-only).  mu: device [R][M]
+ * double.  eta_out: optional device [M][R] complex double (raw products).
+ * M even and >= 2, R in {1, 2, 4, 8, 16, 32, 64}.
+ * If `check` is nonzero the call synchronises `stream` and returns
+ * KPM_ESPECTRUM when a moment is non-finite or |mu_n| > mu_0 (1 + 1e-6)
+ * (|<v|T_n(Htilde)|v>| <= <v|v> holds whenever the spectrum of Htilde lies in
+ * [-1, 1]).  Workspaces (two blocks and the partial sums) are cached on H.
+ * Errors: KPM_EINVAL, KPM_ENOTSUP, KPM_ENOMEM, KPM_ESPECTRUM, KPM_EDEVICE. */
+kpm_status kpm_moments(const kpm_hamiltonian* H, const void* V0, int32_t R, int32_t M,
+                       double* mu, double* eta_out, int32_t check, void* stream);
+
+/* Density of states per unit energy from moments (the reconstruction step
+ * the paper leaves to the KPM literature):
+ *   mubar_n = (1/R) sum_r mu[r][n]                 (stochastic trace)
+ *   rho(E) = [g_0 mubar_0 + 2 sum_{n=1}^{M-1} g_n mubar_n T_n(x)]
+ *            / (pi a sqrt(1 - x^2)),  x = (E - b)/a,  rho = 0 for |x| >= 1
+ * so that the integral of rho over E is mubar_0.  g_n: Jackson
+ * ((M-n+1) cos(pi n/(M+1)) + sin(pi n/(M+1)) cot(pi/(M+1)))/(M+1),
+ * Dirichlet 1, Lorentz sinh(kparam (1 - n/M))/sinh(kparam).
+ * mu: device [R][M]; E: device [K]; rho: device [K] (all double).
+ * Errors: KPM_EINVAL (null pointer, R/M/K <= 0, a <= 0, kernel unknown,
+ * Lorentz kparam <= 0). */
+kpm_status kpm_dos(const double* mu, int32_t R, int32_t M, int32_t kernel, double kparam,
+                   double a, double b, const double* E, int32_t K, double* rho, void* stream);
+
+/* Sweep-kernel timing for measurement tools.  While enabled (process-wide,
+ * not thread-safe), every fused sweep launched by kpm_moments and
+ * kpm_aug_spmmv is bracketed by a pair of HIP events on its own stream.
+ * kpm_sweep_profile_read waits for the recorded events, returns the count,
+ * total, minimum and maximum kernel time in milliseconds (any output may be
+ * NULL) and clears the record.  Errors: KPM_EDEVICE. */
+kpm_status kpm_sweep_profile_enable(int32_t enable);
+kpm_status kpm_sweep_profile_read(int64_t* count, double* total_ms, double* min_ms, double* max_ms);
+
+/* Thread-local message for the last failing call on this thread ("" if none). */
+const char* kpm_last_error(void);
+
+/* Library version string. */
+const char* kpm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KPM_H */

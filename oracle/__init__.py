@@ -42,8 +42,15 @@ def lib():
                                      ctypes.c_double, p, ctypes.c_int, ctypes.c_int, p]
         L.oracle_kpm_direct.restype = ctypes.c_int
         L.oracle_kpm_direct.argtypes = L.oracle_kpm_eta.argtypes
+        L.oracle_threads.restype = ctypes.c_int
+        L.oracle_threads.argtypes = []
         _LIB = L
     return _LIB
+
+
+def lib_threads() -> int:
+    """OpenMP threads the oracle's row loops run on."""
+    return int(lib().oracle_threads())
 
 
 def _ptr(a: np.ndarray):

@@ -17,11 +17,15 @@
  */
 #include <complex.h>
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 
 typedef double complex zc;
+
+/* Number of OpenMP threads the row loops use. */
+int oracle_threads(void) { return omp_get_max_threads(); }
 
 /* ------------------------------------------------------------------------- */
 /* Dirac matrices of the topological-insulator Hamiltonian (eq. "Ham").      */

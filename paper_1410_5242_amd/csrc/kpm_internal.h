@@ -1,0 +1,83 @@
+// Internal declarations shared by the host runtime and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "../../include/kpm.h"
+
+namespace kpm {
+
+// Stored entries per matrix row: the diagonal plus two entries per hopping
+// block (same orbital through Gamma^1, partner orbital through Gamma^{j+1})
+// for the six neighbours n -/+ e_j.
+constexpr int kWidth = 13;
+
+// Number of accelerator complex dies (XCDs) the dispatcher deals workgroups
+// to round-robin on gfx950.
+constexpr int kXcds = 8;
+
+struct Workspace {
+    void* vbuf[2] = {nullptr, nullptr};   // two [N][R] blocks
+    size_t vbytes = 0;
+    double* partials = nullptr;            // [slots][grid][3][R]
+    size_t pbytes = 0;
+    double* eta = nullptr;                 // [M][R][2]
+    size_t etabytes = 0;
+    int* flag = nullptr;                   // spectrum check flag (device)
+    int* flag_host = nullptr;              // pinned mirror
+};
+
+}  // namespace kpm
+
+struct kpm_hamiltonian {
+    int dtype = KPM_C128;           // storage precision of val and of vector blocks
+    int64_t nrows = 0;              // N
+    int width = kpm::kWidth;        // slots per row (row-major, diagonal first)
+    void* val = nullptr;            // [N][width] complex (re, im) in dtype
+    int32_t* col = nullptr;         // [N][width]
+    double a = 1.0, b = 0.0;        // Htilde = (H - b)/a
+    double emin = 0.0, emax = 0.0;  // Gershgorin interval
+    int device = 0;
+    kpm::Workspace ws;
+};
+
+namespace kpm {
+
+void set_error(const std::string& msg);
+
+// ---- device launchers (implemented in the .hip files) ----
+
+// Builds the row-major slot arrays and per-block Gershgorin bounds.
+hipError_t launch_build_ti(int Lx, int Ly, int Lz, const int* periodic, double t,
+                           const double* pot_dev, int dtype, void* val, int32_t* col,
+                           double* block_bounds /* [nblocks][2] */, int nblocks,
+                           double* bounds_out /* [2] */, hipStream_t s);
+int build_blocks(int64_t nrows);
+
+struct SweepArgs {
+    const void* val;
+    const int32_t* col;
+    int64_t nrows;
+    const void* V;
+    void* W;
+    double alpha, beta, gamma;
+    double* partials;   // this sweep's [grid][3][R] slot (FULL only)
+    int grid;           // workgroups
+};
+
+// Grid size (workgroups) the sweep kernel uses for this dtype / R.
+int sweep_grid(int dtype, int R);
+hipError_t launch_sweep(int dtype, int R, int variant, const SweepArgs& a, hipStream_t s);
+
+// eta[(sweep0 + s)*2 + q] for s < nslots from partials[s][grid][3][R].
+hipError_t launch_reduce_partials(const double* partials, int nslots, int grid, int R,
+                                  int sweep0, double* eta, hipStream_t s);
+hipError_t launch_eta_to_mu(const double* eta, int R, int M, double* mu, hipStream_t s);
+hipError_t launch_check_moments(const double* mu, int R, int M, int* flag, hipStream_t s);
+hipError_t launch_dos(const double* mu, int R, int M, int kernel, double kparam, double a,
+                      double b, const double* E, int K, double* rho, hipStream_t s);
+
+}  // namespace kpm

@@ -1,0 +1,400 @@
+// Host runtime behind the C ABI (include/kpm.h): argument validation, device
+// allocations, workspace caching and the launch sequence of the KPM
+// iteration.  No arithmetic of the method runs here beyond the two-number
+// scaling (a, b) from the Gershgorin bounds; everything else is enqueued as
+// device kernels on the caller's stream.
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "kpm_internal.h"
+
+namespace kpm {
+
+namespace {
+thread_local std::string g_error;
+
+// Scalar-product partials of this many consecutive sweeps are kept on the
+// device before one reduction launch folds them into eta.
+constexpr int kReduceEvery = 64;
+
+bool r_supported(int R) {
+    return R == 1 || R == 2 || R == 4 || R == 8 || R == 16 || R == 32 || R == 64;
+}
+
+size_t real_size(int dtype) { return dtype == KPM_C128 ? sizeof(double) : sizeof(float); }
+
+kpm_status fail(kpm_status st, const std::string& msg) {
+    set_error(msg);
+    return st;
+}
+
+kpm_status hip_fail(hipError_t e, const char* what) {
+    return fail(e == hipErrorOutOfMemory ? KPM_ENOMEM : KPM_EDEVICE,
+                std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define KPM_HIP(call, what)                           \
+    do {                                              \
+        hipError_t e_ = (call);                       \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+kpm_status check_device(const kpm_hamiltonian* H) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(KPM_EDEVICE, "hipGetDevice failed");
+    if (dev != H->device) return fail(KPM_EINVAL, "current device differs from the device H was built on");
+    return KPM_OK;
+}
+
+template <typename P>
+kpm_status grow(P** ptr, size_t* have, size_t need, const char* what) {
+    if (*have >= need && *ptr) return KPM_OK;
+    if (*ptr) {
+        KPM_HIP(hipFree(*ptr), "hipFree");
+        *ptr = nullptr;
+        *have = 0;
+    }
+    void* p = nullptr;
+    KPM_HIP(hipMalloc(&p, need), what);
+    *ptr = static_cast<P*>(p);
+    *have = need;
+    return KPM_OK;
+}
+
+kpm_status ensure_vectors(kpm_hamiltonian* H, int R) {
+    const size_t need = static_cast<size_t>(H->nrows) * 2 * R * real_size(H->dtype);
+    for (int i = 0; i < 2; ++i) {
+        size_t have = H->ws.vbytes;
+        kpm_status st = grow(&H->ws.vbuf[i], &have, need, "hipMalloc(vector block)");
+        if (st != KPM_OK) return st;
+    }
+    H->ws.vbytes = need;
+    return KPM_OK;
+}
+
+kpm_status ensure_partials(kpm_hamiltonian* H, int R, int slots) {
+    const int grid = sweep_grid(H->dtype, R);
+    const size_t need = static_cast<size_t>(slots) * grid * 3 * R * sizeof(double);
+    return grow(&H->ws.partials, &H->ws.pbytes, need, "hipMalloc(partials)");
+}
+
+kpm_status ensure_flag(kpm_hamiltonian* H) {
+    if (!H->ws.flag) KPM_HIP(hipMalloc(&H->ws.flag, sizeof(int)), "hipMalloc(flag)");
+    if (!H->ws.flag_host) KPM_HIP(hipHostMalloc(&H->ws.flag_host, sizeof(int)), "hipHostMalloc(flag)");
+    return KPM_OK;
+}
+
+// Event pairs around sweep launches (kpm_sweep_profile_*).
+struct SweepProfile {
+    bool on = false;
+    std::vector<hipEvent_t> start, stop;
+    size_t used = 0;
+};
+SweepProfile g_prof;
+
+hipError_t launch_sweep_profiled(int dtype, int R, int variant, const SweepArgs& a, hipStream_t s) {
+    if (!g_prof.on) return launch_sweep(dtype, R, variant, a, s);
+    if (g_prof.used == g_prof.start.size()) {
+        hipEvent_t e0, e1;
+        hipError_t e = hipEventCreate(&e0);
+        if (e != hipSuccess) return e;
+        if ((e = hipEventCreate(&e1)) != hipSuccess) return e;
+        g_prof.start.push_back(e0);
+        g_prof.stop.push_back(e1);
+    }
+    hipError_t e = hipEventRecord(g_prof.start[g_prof.used], s);
+    if (e != hipSuccess) return e;
+    if ((e = launch_sweep(dtype, R, variant, a, s)) != hipSuccess) return e;
+    if ((e = hipEventRecord(g_prof.stop[g_prof.used], s)) != hipSuccess) return e;
+    ++g_prof.used;
+    return hipSuccess;
+}
+
+}  // namespace
+
+void set_error(const std::string& msg) { g_error = msg; }
+
+}  // namespace kpm
+
+using namespace kpm;
+
+extern "C" {
+
+const char* kpm_last_error(void) { return g_error.c_str(); }
+
+const char* kpm_version(void) { return "kpm-mi355x 0.1 (gfx950)"; }
+
+kpm_status kpm_build_hamiltonian(const kpm_lattice_desc* d, void* stream, kpm_hamiltonian** out) {
+    g_error.clear();
+    if (!out) return fail(KPM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!d) return fail(KPM_EINVAL, "desc is NULL");
+    if (!d->potential) return fail(KPM_EINVAL, "potential is NULL");
+    for (int j = 0; j < 3; ++j) {
+        if (d->L[j] <= 0) return fail(KPM_EINVAL, "lattice side <= 0");
+        if (d->periodic[j] && d->L[j] < 3)
+            return fail(KPM_ENOTSUP, "periodic sides must be >= 3 (shorter ones alias the two neighbours)");
+    }
+    if (d->dtype != KPM_C128 && d->dtype != KPM_C64) return fail(KPM_EINVAL, "unknown dtype");
+    if (!std::isfinite(d->t)) return fail(KPM_EINVAL, "t is not finite");
+    if (d->fixed_scale) {
+        if (!(d->a > 0.0) || !std::isfinite(d->a) || !std::isfinite(d->b))
+            return fail(KPM_EINVAL, "fixed scale needs a finite a > 0 and a finite b");
+    } else if (!(d->margin >= 1.0) || !std::isfinite(d->margin)) {
+        return fail(KPM_EINVAL, "margin must be a finite number >= 1");
+    }
+    const int64_t nsite = static_cast<int64_t>(d->L[0]) * d->L[1] * d->L[2];
+    if (nsite > (INT32_MAX / 4)) return fail(KPM_ENOMEM, "lattice too large for int32 column indices");
+    for (int64_t i = 0; i < nsite; ++i)
+        if (!std::isfinite(d->potential[i])) return fail(KPM_EINVAL, "potential has a non-finite value");
+
+    auto* H = new kpm_hamiltonian();
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    H->dtype = d->dtype;
+    H->nrows = 4 * nsite;
+    H->width = kWidth;
+    if (hipGetDevice(&H->device) != hipSuccess) {
+        delete H;
+        return fail(KPM_EDEVICE, "hipGetDevice failed");
+    }
+    const size_t slots = static_cast<size_t>(H->nrows) * kWidth;
+    const int nblocks = build_blocks(H->nrows);
+    double* pot_dev = nullptr;
+    double* bb = nullptr;
+    double* bounds = nullptr;
+    double host_bounds[2] = {0.0, 0.0};
+    kpm_status st = KPM_OK;
+    hipError_t e;
+    if ((e = hipMalloc(&H->val, slots * 2 * real_size(H->dtype))) != hipSuccess) st = hip_fail(e, "hipMalloc(val)");
+    else if ((e = hipMalloc(&H->col, slots * sizeof(int32_t))) != hipSuccess) st = hip_fail(e, "hipMalloc(col)");
+    else if ((e = hipMalloc(&pot_dev, nsite * sizeof(double))) != hipSuccess) st = hip_fail(e, "hipMalloc(potential)");
+    else if ((e = hipMalloc(&bb, static_cast<size_t>(nblocks) * 2 * sizeof(double))) != hipSuccess) st = hip_fail(e, "hipMalloc(bounds)");
+    else if ((e = hipMalloc(&bounds, 2 * sizeof(double))) != hipSuccess) st = hip_fail(e, "hipMalloc(bounds)");
+    else if ((e = hipMemcpyAsync(pot_dev, d->potential, nsite * sizeof(double), hipMemcpyHostToDevice, s)) != hipSuccess)
+        st = hip_fail(e, "copy potential");
+    else if ((e = launch_build_ti(d->L[0], d->L[1], d->L[2], d->periodic, d->t, pot_dev, H->dtype, H->val,
+                                  H->col, bb, nblocks, bounds, s)) != hipSuccess)
+        st = hip_fail(e, "build kernel");
+    else if ((e = hipMemcpyAsync(host_bounds, bounds, 2 * sizeof(double), hipMemcpyDeviceToHost, s)) != hipSuccess)
+        st = hip_fail(e, "copy bounds");
+    else if ((e = hipStreamSynchronize(s)) != hipSuccess)
+        st = hip_fail(e, "synchronise");
+    if (pot_dev) (void)hipFree(pot_dev);
+    if (bb) (void)hipFree(bb);
+    if (bounds) (void)hipFree(bounds);
+    if (st != KPM_OK) {
+        kpm_destroy_hamiltonian(H);
+        return st;
+    }
+    H->emin = host_bounds[0];
+    H->emax = host_bounds[1];
+    if (d->fixed_scale) {
+        H->a = d->a;
+        H->b = d->b;
+    } else {
+        H->b = 0.5 * (H->emax + H->emin);
+        H->a = d->margin * 0.5 * (H->emax - H->emin);
+        if (!(H->a > 0.0)) {
+            kpm_destroy_hamiltonian(H);
+            return fail(KPM_EINVAL, "Gershgorin interval has zero width");
+        }
+    }
+    *out = H;
+    return KPM_OK;
+}
+
+kpm_status kpm_hamiltonian_info(const kpm_hamiltonian* H, int64_t* N, int64_t* nnz, int32_t* width,
+                                int32_t* dtype, double* a, double* b, double* emin, double* emax) {
+    g_error.clear();
+    if (!H) return fail(KPM_EINVAL, "H is NULL");
+    if (N) *N = H->nrows;
+    if (nnz) *nnz = H->nrows * H->width;
+    if (width) *width = H->width;
+    if (dtype) *dtype = H->dtype;
+    if (a) *a = H->a;
+    if (b) *b = H->b;
+    if (emin) *emin = H->emin;
+    if (emax) *emax = H->emax;
+    return KPM_OK;
+}
+
+kpm_status kpm_export_csr(const kpm_hamiltonian* H, int64_t* rowptr, int32_t* col, double* val) {
+    g_error.clear();
+    if (!H || !rowptr) return fail(KPM_EINVAL, "H or rowptr is NULL");
+    if ((col == nullptr) != (val == nullptr)) return fail(KPM_EINVAL, "col and val must both be set or both NULL");
+    kpm_status st = check_device(H);
+    if (st != KPM_OK) return st;
+    const size_t slots = static_cast<size_t>(H->nrows) * H->width;
+    std::vector<int32_t> c(slots);
+    std::vector<double> v(2 * slots);
+    KPM_HIP(hipMemcpy(c.data(), H->col, slots * sizeof(int32_t), hipMemcpyDeviceToHost), "copy col");
+    if (H->dtype == KPM_C128) {
+        KPM_HIP(hipMemcpy(v.data(), H->val, 2 * slots * sizeof(double), hipMemcpyDeviceToHost), "copy val");
+    } else {
+        std::vector<float> f(2 * slots);
+        KPM_HIP(hipMemcpy(f.data(), H->val, 2 * slots * sizeof(float), hipMemcpyDeviceToHost), "copy val");
+        for (size_t i = 0; i < 2 * slots; ++i) v[i] = f[i];
+    }
+    int64_t k = 0;
+    rowptr[0] = 0;
+    for (int64_t i = 0; i < H->nrows; ++i) {
+        for (int j = 0; j < H->width; ++j) {
+            const size_t s = static_cast<size_t>(i) * H->width + j;
+            if (j > 0 && c[s] == i) continue;   // padding slot
+            if (col) {
+                col[k] = c[s];
+                val[2 * k] = v[2 * s];
+                val[2 * k + 1] = v[2 * s + 1];
+            }
+            ++k;
+        }
+        rowptr[i + 1] = k;
+    }
+    return KPM_OK;
+}
+
+void kpm_destroy_hamiltonian(kpm_hamiltonian* H) {
+    if (!H) return;
+    (void)hipDeviceSynchronize();
+    if (H->val) (void)hipFree(H->val);
+    if (H->col) (void)hipFree(H->col);
+    for (int i = 0; i < 2; ++i)
+        if (H->ws.vbuf[i]) (void)hipFree(H->ws.vbuf[i]);
+    if (H->ws.partials) (void)hipFree(H->ws.partials);
+    if (H->ws.eta) (void)hipFree(H->ws.eta);
+    if (H->ws.flag) (void)hipFree(H->ws.flag);
+    if (H->ws.flag_host) (void)hipHostFree(H->ws.flag_host);
+    delete H;
+}
+
+kpm_status kpm_aug_spmmv(const kpm_hamiltonian* Hc, const void* V, void* W, int32_t R, double alpha,
+                         double beta, double gamma, int32_t variant, double* eta, void* stream) {
+    g_error.clear();
+    if (!Hc || !V || !W) return fail(KPM_EINVAL, "H, V or W is NULL");
+    if (!r_supported(R)) return fail(KPM_ENOTSUP, "R must be one of 1, 2, 4, 8, 16, 32, 64");
+    if (variant != KPM_FULL && variant != KPM_NODOT && variant != KPM_PLAIN)
+        return fail(KPM_EINVAL, "unknown variant");
+    if (!std::isfinite(alpha) || !std::isfinite(beta) || !std::isfinite(gamma))
+        return fail(KPM_EINVAL, "alpha, beta, gamma must be finite");
+    auto* H = const_cast<kpm_hamiltonian*>(Hc);
+    kpm_status st = check_device(H);
+    if (st != KPM_OK) return st;
+    const size_t bytes = static_cast<size_t>(H->nrows) * 2 * R * real_size(H->dtype);
+    const char* v0 = static_cast<const char*>(V);
+    const char* w0 = static_cast<const char*>(W);
+    if (v0 < w0 + bytes && w0 < v0 + bytes) return fail(KPM_EINVAL, "V and W overlap");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const bool dots = (variant == KPM_FULL && eta != nullptr);
+    if (dots) {
+        st = ensure_partials(H, R, 1);
+        if (st != KPM_OK) return st;
+    }
+    SweepArgs a{H->val, H->col, H->nrows, V, W, alpha, beta, gamma,
+                dots ? H->ws.partials : nullptr, sweep_grid(H->dtype, R)};
+    const int launch_variant = (variant == KPM_FULL && !dots) ? KPM_NODOT : variant;
+    KPM_HIP(launch_sweep_profiled(H->dtype, R, launch_variant, a, s), "sweep kernel");
+    if (dots) KPM_HIP(launch_reduce_partials(H->ws.partials, 1, a.grid, R, 0, eta, s), "reduce kernel");
+    return KPM_OK;
+}
+
+kpm_status kpm_moments(const kpm_hamiltonian* Hc, const void* V0, int32_t R, int32_t M, double* mu,
+                       double* eta_out, int32_t check, void* stream) {
+    g_error.clear();
+    if (!Hc || !V0 || !mu) return fail(KPM_EINVAL, "H, V0 or mu is NULL");
+    if (!r_supported(R)) return fail(KPM_ENOTSUP, "R must be one of 1, 2, 4, 8, 16, 32, 64");
+    if (M < 2 || (M % 2) != 0) return fail(KPM_EINVAL, "M must be even and >= 2");
+    auto* H = const_cast<kpm_hamiltonian*>(Hc);
+    kpm_status st = check_device(H);
+    if (st != KPM_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int sweeps = M / 2;
+    const int slots = sweeps < kReduceEvery ? sweeps : kReduceEvery;
+    if ((st = ensure_vectors(H, R)) != KPM_OK) return st;
+    if ((st = ensure_partials(H, R, slots)) != KPM_OK) return st;
+    double* eta = eta_out;
+    if (!eta) {
+        if ((st = grow(&H->ws.eta, &H->ws.etabytes, static_cast<size_t>(M) * R * 2 * sizeof(double),
+                       "hipMalloc(eta)")) != KPM_OK)
+            return st;
+        eta = H->ws.eta;
+    }
+    const int grid = sweep_grid(H->dtype, R);
+    const size_t slot_elems = static_cast<size_t>(grid) * 3 * R;
+    const size_t bytes = static_cast<size_t>(H->nrows) * 2 * R * real_size(H->dtype);
+    void* A = H->ws.vbuf[0];
+    void* B = H->ws.vbuf[1];
+    // nu_0 -> A (the caller's block stays untouched)
+    KPM_HIP(hipMemcpyAsync(A, V0, bytes, hipMemcpyDeviceToDevice, s), "copy V0");
+    const double inv_a = 1.0 / H->a;
+    for (int k = 0; k < sweeps; ++k) {
+        const int sl = k % kReduceEvery;
+        SweepArgs a{H->val, H->col, H->nrows, nullptr, nullptr, 0.0, 0.0, 0.0,
+                    H->ws.partials + sl * slot_elems, grid};
+        if (k == 0) {
+            // nu_1 = Htilde nu_0 = (1/a) H nu_0 - (b/a) nu_0
+            a.V = A; a.W = B; a.alpha = inv_a; a.beta = -H->b * inv_a; a.gamma = 0.0;
+        } else {
+            // swap roles: V = nu_k, W = nu_{k-1} -> nu_{k+1} = 2 Htilde nu_k - nu_{k-1}
+            if (k % 2 == 1) { a.V = B; a.W = A; } else { a.V = A; a.W = B; }
+            a.alpha = 2.0 * inv_a; a.beta = -2.0 * H->b * inv_a; a.gamma = -1.0;
+        }
+        KPM_HIP(launch_sweep_profiled(H->dtype, R, KPM_FULL, a, s), "sweep kernel");
+        if (sl == kReduceEvery - 1 || k == sweeps - 1)
+            KPM_HIP(launch_reduce_partials(H->ws.partials, sl + 1, grid, R, k - sl, eta, s), "reduce kernel");
+    }
+    KPM_HIP(launch_eta_to_mu(eta, R, M, mu, s), "eta_to_mu kernel");
+    if (check) {
+        if ((st = ensure_flag(H)) != KPM_OK) return st;
+        KPM_HIP(launch_check_moments(mu, R, M, H->ws.flag, s), "check kernel");
+        KPM_HIP(hipMemcpyAsync(H->ws.flag_host, H->ws.flag, sizeof(int), hipMemcpyDeviceToHost, s), "copy flag");
+        KPM_HIP(hipStreamSynchronize(s), "synchronise");
+        if (*H->ws.flag_host)
+            return fail(KPM_ESPECTRUM, "moments left [-mu_0, mu_0]: the scaled spectrum is not inside [-1, 1]");
+    }
+    return KPM_OK;
+}
+
+kpm_status kpm_dos(const double* mu, int32_t R, int32_t M, int32_t kernel, double kparam, double a, double b,
+                   const double* E, int32_t K, double* rho, void* stream) {
+    g_error.clear();
+    if (!mu || !E || !rho) return fail(KPM_EINVAL, "mu, E or rho is NULL");
+    if (R <= 0 || M <= 0 || K <= 0) return fail(KPM_EINVAL, "R, M and K must be positive");
+    if (!(a > 0.0) || !std::isfinite(a) || !std::isfinite(b)) return fail(KPM_EINVAL, "need finite a > 0 and finite b");
+    if (kernel != KPM_JACKSON && kernel != KPM_DIRICHLET && kernel != KPM_LORENTZ)
+        return fail(KPM_EINVAL, "unknown kernel");
+    if (kernel == KPM_LORENTZ && !(kparam > 0.0)) return fail(KPM_EINVAL, "Lorentz kernel needs kparam > 0");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    KPM_HIP(launch_dos(mu, R, M, kernel, kparam, a, b, E, K, rho, s), "dos kernel");
+    return KPM_OK;
+}
+
+kpm_status kpm_sweep_profile_enable(int32_t enable) {
+    g_error.clear();
+    g_prof.on = enable != 0;
+    return KPM_OK;
+}
+
+kpm_status kpm_sweep_profile_read(int64_t* count, double* total_ms, double* min_ms, double* max_ms) {
+    g_error.clear();
+    double tot = 0.0, lo = 0.0, hi = 0.0;
+    for (size_t i = 0; i < g_prof.used; ++i) {
+        KPM_HIP(hipEventSynchronize(g_prof.stop[i]), "hipEventSynchronize");
+        float ms = 0.0f;
+        KPM_HIP(hipEventElapsedTime(&ms, g_prof.start[i], g_prof.stop[i]), "hipEventElapsedTime");
+        tot += ms;
+        lo = (i == 0 || ms < lo) ? ms : lo;
+        hi = (i == 0 || ms > hi) ? ms : hi;
+    }
+    if (count) *count = static_cast<int64_t>(g_prof.used);
+    if (total_ms) *total_ms = tot;
+    if (min_ms) *min_ms = lo;
+    if (max_ms) *max_ms = hi;
+    g_prof.used = 0;
+    return KPM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,222 @@
+"""Thin ctypes binding of libkpm.so (include/kpm.h).
+
+Argument marshalling only: every step of the KPM path runs in the library's
+HIP kernels.  PyTorch supplies device memory (tensors) and the HIP stream.
+The binding refuses to run when the compiled library is missing; there is
+no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libkpm.so")
+
+KPM_OK, KPM_EINVAL, KPM_ENOMEM, KPM_EDEVICE, KPM_ENOTSUP, KPM_ESPECTRUM, KPM_EINTERNAL = 0, -1, -2, -3, -4, -5, -6
+C128, C64 = 0, 1
+JACKSON, DIRICHLET, LORENTZ = 0, 1, 2
+FULL, NODOT, PLAIN = 0, 1, 2
+SUPPORTED_R = (1, 2, 4, 8, 16, 32, 64)
+
+_KERNELS = {"jackson": JACKSON, "dirichlet": DIRICHLET, "lorentz": LORENTZ}
+_VARIANTS = {"full": FULL, "nodot": NODOT, "plain": PLAIN}
+_DTYPES = {"c128": C128, "c64": C64}
+_TORCH_DTYPE = {C128: torch.complex128, C64: torch.complex64}
+
+
+class KPMError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"kpm status {status}: {msg}")
+        self.status = status
+
+
+class LatticeDesc(ctypes.Structure):
+    _fields_ = [
+        ("L", ctypes.c_int32 * 3),
+        ("periodic", ctypes.c_int32 * 3),
+        ("t", ctypes.c_double),
+        ("potential", ctypes.c_void_p),
+        ("dtype", ctypes.c_int32),
+        ("margin", ctypes.c_double),
+        ("fixed_scale", ctypes.c_int32),
+        ("a", ctypes.c_double),
+        ("b", ctypes.c_double),
+    ]
+
+
+_LIB = None
+EXPORTS = ("kpm_build_hamiltonian", "kpm_hamiltonian_info", "kpm_export_csr",
+           "kpm_destroy_hamiltonian", "kpm_aug_spmmv", "kpm_moments", "kpm_dos",
+           "kpm_sweep_profile_enable", "kpm_sweep_profile_read", "kpm_last_error", "kpm_version")
+
+
+def lib():
+    """Load libkpm.so (built by __graft_entry__.build() / paper_1410_5242_amd.build)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_1410_5242_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    L.kpm_build_hamiltonian.restype = ctypes.c_int
+    L.kpm_build_hamiltonian.argtypes = [ctypes.POINTER(LatticeDesc), vp, ctypes.POINTER(vp)]
+    L.kpm_hamiltonian_info.restype = ctypes.c_int
+    L.kpm_hamiltonian_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i32),
+                                       ctypes.POINTER(i32), ctypes.POINTER(dbl), ctypes.POINTER(dbl),
+                                       ctypes.POINTER(dbl), ctypes.POINTER(dbl)]
+    L.kpm_export_csr.restype = ctypes.c_int
+    L.kpm_export_csr.argtypes = [vp, vp, vp, vp]
+    L.kpm_destroy_hamiltonian.restype = None
+    L.kpm_destroy_hamiltonian.argtypes = [vp]
+    L.kpm_aug_spmmv.restype = ctypes.c_int
+    L.kpm_aug_spmmv.argtypes = [vp, vp, vp, i32, dbl, dbl, dbl, i32, vp, vp]
+    L.kpm_moments.restype = ctypes.c_int
+    L.kpm_moments.argtypes = [vp, vp, i32, i32, vp, vp, i32, vp]
+    L.kpm_dos.restype = ctypes.c_int
+    L.kpm_dos.argtypes = [vp, i32, i32, i32, dbl, dbl, dbl, vp, i32, vp, vp]
+    L.kpm_sweep_profile_enable.restype = ctypes.c_int
+    L.kpm_sweep_profile_enable.argtypes = [i32]
+    L.kpm_sweep_profile_read.restype = ctypes.c_int
+    L.kpm_sweep_profile_read.argtypes = [ctypes.POINTER(i64), ctypes.POINTER(dbl), ctypes.POINTER(dbl),
+                                         ctypes.POINTER(dbl)]
+    L.kpm_last_error.restype = ctypes.c_char_p
+    L.kpm_last_error.argtypes = []
+    L.kpm_version.restype = ctypes.c_char_p
+    L.kpm_version.argtypes = []
+    _LIB = L
+    return L
+
+
+def _check(status: int):
+    if status != KPM_OK:
+        raise KPMError(status, lib().kpm_last_error().decode())
+
+
+def _stream(stream) -> ctypes.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dptr(t: torch.Tensor) -> ctypes.c_void_p:
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Hamiltonian:
+    """Owning wrapper of a kpm_hamiltonian handle."""
+
+    def __init__(self, handle: ctypes.c_void_p):
+        self.handle = handle
+        N, nnz = ctypes.c_int64(), ctypes.c_int64()
+        width, dtype = ctypes.c_int32(), ctypes.c_int32()
+        a, b, lo, hi = ctypes.c_double(), ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        _check(lib().kpm_hamiltonian_info(handle, N, nnz, width, dtype, a, b, lo, hi))
+        self.N, self.nnz_stored, self.width = N.value, nnz.value, width.value
+        self.dtype = dtype.value
+        self.a, self.b, self.emin, self.emax = a.value, b.value, lo.value, hi.value
+
+    @property
+    def torch_dtype(self):
+        return _TORCH_DTYPE[self.dtype]
+
+    def close(self):
+        if self.handle:
+            lib().kpm_destroy_hamiltonian(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def build_hamiltonian(L, potential, t: float = 1.0, periodic=(1, 1, 1), dtype: str = "c128",
+                      margin: float = 1.01, fixed_scale=None, stream=None) -> Hamiltonian:
+    """kpm_build_hamiltonian: H of eq. "Ham" on the device plus its Gershgorin scaling."""
+    pot = np.ascontiguousarray(potential, dtype=np.float64).reshape(-1)
+    d = LatticeDesc()
+    for j in range(3):
+        d.L[j] = int(L[j])
+        d.periodic[j] = 1 if periodic[j] else 0
+    d.t = float(t)
+    d.potential = pot.ctypes.data
+    d.dtype = _DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
+    d.margin = float(margin)
+    if fixed_scale is not None:
+        d.fixed_scale = 1
+        d.a, d.b = float(fixed_scale[0]), float(fixed_scale[1])
+    h = ctypes.c_void_p()
+    _check(lib().kpm_build_hamiltonian(ctypes.byref(d), _stream(stream), ctypes.byref(h)))
+    return Hamiltonian(h)
+
+
+def export_csr(H: Hamiltonian):
+    """kpm_export_csr: (rowptr int64, col int32, val complex128) on the host."""
+    rowptr = np.zeros(H.N + 1, dtype=np.int64)
+    _check(lib().kpm_export_csr(H.handle, rowptr.ctypes.data, None, None))
+    nnz = int(rowptr[-1])
+    col = np.zeros(nnz, dtype=np.int32)
+    val = np.zeros(2 * nnz, dtype=np.float64)
+    _check(lib().kpm_export_csr(H.handle, rowptr.ctypes.data, col.ctypes.data, val.ctypes.data))
+    return rowptr, col, val.view(np.complex128)
+
+
+def aug_spmmv(H: Hamiltonian, V: torch.Tensor, W: torch.Tensor, alpha: float, beta: float, gamma: float,
+              variant: str = "full", eta: torch.Tensor | None = None, stream=None):
+    """kpm_aug_spmmv: one fused sweep W <- alpha H V + beta V + gamma W (+ eta for "full")."""
+    R = V.shape[1]
+    _check(lib().kpm_aug_spmmv(H.handle, _dptr(V), _dptr(W), R, float(alpha), float(beta), float(gamma),
+                               _VARIANTS[variant], _dptr(eta) if eta is not None else None, _stream(stream)))
+
+
+def moments(H: Hamiltonian, V0: torch.Tensor, M: int, mu: torch.Tensor | None = None,
+            eta: torch.Tensor | None = None, check: bool = True, stream=None) -> torch.Tensor:
+    """kpm_moments: mu[R][M] (float64, device) for the [N][R] start block V0."""
+    if V0.dim() != 2 or V0.shape[0] != H.N:
+        raise ValueError("V0 must be [N][R]")
+    if V0.dtype != H.torch_dtype:
+        raise ValueError(f"V0 must be {H.torch_dtype}")
+    R = V0.shape[1]
+    if mu is None:
+        mu = torch.empty((R, M), dtype=torch.float64, device=V0.device)
+    _check(lib().kpm_moments(H.handle, _dptr(V0), R, int(M), _dptr(mu),
+                             _dptr(eta) if eta is not None else None, 1 if check else 0, _stream(stream)))
+    return mu
+
+
+def dos(mu: torch.Tensor, a: float, b: float, E: torch.Tensor, kernel: str = "jackson", kparam: float = 0.0,
+        rho: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """kpm_dos: density of states per unit energy on the device energy grid E."""
+    R, M = mu.shape
+    K = E.numel()
+    if rho is None:
+        rho = torch.empty(K, dtype=torch.float64, device=E.device)
+    _check(lib().kpm_dos(_dptr(mu), R, M, _KERNELS[kernel], float(kparam), float(a), float(b),
+                         _dptr(E), K, _dptr(rho), _stream(stream)))
+    return rho
+
+
+def sweep_profile_enable(on: bool = True):
+    """kpm_sweep_profile_enable: bracket every sweep kernel with HIP events."""
+    _check(lib().kpm_sweep_profile_enable(1 if on else 0))
+
+
+def sweep_profile_read():
+    """kpm_sweep_profile_read: (count, total_ms, min_ms, max_ms) of the recorded sweeps; clears them."""
+    n, tot, lo, hi = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    _check(lib().kpm_sweep_profile_read(n, tot, lo, hi))
+    return n.value, tot.value, lo.value, hi.value
+
+
+def version() -> str:
+    return lib().kpm_version().decode()

@@ -1,0 +1,74 @@
+"""Host-only checks of the C ABI: the library loads, exports every symbol the
+header declares, and rejects invalid arguments before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "kpm.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(kpm_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1410_5242_amd import kpm
+    if not os.path.exists(kpm.LIB_PATH):
+        pytest.skip("libkpm.so not built (run __graft_entry__.build())")
+    return kpm.lib()
+
+
+def test_header_declares_the_boundary():
+    syms = declared_symbols()
+    for s in ("kpm_build_hamiltonian", "kpm_moments", "kpm_dos", "kpm_aug_spmmv",
+              "kpm_export_csr", "kpm_hamiltonian_info", "kpm_destroy_hamiltonian",
+              "kpm_last_error", "kpm_version"):
+        assert s in syms
+
+
+def test_library_exports_every_declared_symbol(L):
+    raw = ctypes.CDLL(os.path.join(ROOT, "paper_1410_5242_amd", "libkpm.so"))
+    for s in declared_symbols():
+        assert hasattr(raw, s), s
+
+
+def test_version_and_error_strings(L):
+    assert b"gfx950" in L.kpm_version()
+    assert isinstance(L.kpm_last_error(), bytes)
+
+
+def test_argument_validation_without_device(L):
+    from paper_1410_5242_amd import kpm
+    out = ctypes.c_void_p(1)
+    assert L.kpm_build_hamiltonian(None, None, ctypes.byref(out)) == kpm.KPM_EINVAL
+    assert out.value is None
+    assert b"desc" in L.kpm_last_error()
+    d = kpm.LatticeDesc()
+    d.L[0] = d.L[1] = d.L[2] = 4
+    d.periodic[0] = d.periodic[1] = d.periodic[2] = 1
+    d.t, d.margin = 1.0, 1.01
+    assert L.kpm_build_hamiltonian(ctypes.byref(d), None, ctypes.byref(out)) == kpm.KPM_EINVAL  # no potential
+    fake = ctypes.c_void_p(0x1000)
+    assert L.kpm_moments(None, fake, 1, 8, fake, None, 0, None) == kpm.KPM_EINVAL
+    assert L.kpm_aug_spmmv(None, fake, fake, 1, 1.0, 0.0, 0.0, 0, None, None) == kpm.KPM_EINVAL
+    assert L.kpm_dos(None, 1, 8, 0, 0.0, 1.0, 0.0, fake, 4, fake, None) == kpm.KPM_EINVAL
+    assert L.kpm_dos(fake, 1, 8, 0, 0.0, 1.0, 0.0, fake, 0, fake, None) == kpm.KPM_EINVAL   # K = 0
+    assert L.kpm_dos(fake, 1, 8, 0, 0.0, -1.0, 0.0, fake, 4, fake, None) == kpm.KPM_EINVAL  # a <= 0
+    assert L.kpm_dos(fake, 1, 8, 7, 0.0, 1.0, 0.0, fake, 4, fake, None) == kpm.KPM_EINVAL   # kernel
+    assert L.kpm_dos(fake, 1, 8, 2, 0.0, 1.0, 0.0, fake, 4, fake, None) == kpm.KPM_EINVAL   # Lorentz lambda
+    assert L.kpm_hamiltonian_info(None, None, None, None, None, None, None, None, None) == kpm.KPM_EINVAL
+    L.kpm_destroy_hamiltonian(None)   # no-op
+
+
+def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
+    from paper_1410_5242_amd import kpm
+    monkeypatch.setattr(kpm, "_LIB", None)
+    monkeypatch.setattr(kpm, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(RuntimeError, match="not built"):
+        kpm.lib()

@@ -1,0 +1,323 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Tolerances: complex128 moments agree with the oracle to 1e-12 absolute
+(relative to mu_0 = 1, since |mu_n| <= mu_0); complex64 storage with FP64
+scalar products agrees with the complex128 oracle to 1e-5.  The matrix is
+compared bit for bit (its entries are V_n +- 2, +-t/2, +-i t/2).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1410_5242_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL_C128 = 1e-12
+TOL_C64 = 1e-5
+
+
+def kpm():
+    from paper_1410_5242_amd import kpm as K
+    return K
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def device():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    return torch.device("cuda:0")
+
+
+def oracle_problem(L, gamma, seed, t=1.0, periodic=(1, 1, 1)):
+    pot = inputs.potential(L, gamma, seed)
+    H = O.ti_hamiltonian(L, pot, t=t, periodic=periodic)
+    a, b = O.scaling(*O.gershgorin(H))
+    return pot, H, a, b
+
+
+def sorted_rows(rowptr, col, val):
+    out = []
+    for i in range(len(rowptr) - 1):
+        s, e = rowptr[i], rowptr[i + 1]
+        o = np.argsort(col[s:e], kind="stable")
+        out.append((col[s:e][o], val[s:e][o]))
+    return out
+
+
+# --------------------------------------------------------------------------
+# a1-a2: Hamiltonian and Gershgorin scaling
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("L,periodic,t", [
+    ((3, 3, 3), (1, 1, 1), 1.0),
+    ((5, 4, 7), (1, 1, 1), 0.75),
+    ((4, 3, 5), (1, 1, 0), 1.0),
+    ((2, 3, 1), (0, 1, 0), 1.25),
+])
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_hamiltonian_matches_oracle_exactly(L, periodic, t, dtype):
+    say("hamiltonian", L, periodic, t, dtype)
+    K = kpm()
+    pot, Ho, a, b = oracle_problem(L, 2.0, 3, t=t, periodic=periodic)
+    H = K.build_hamiltonian(L, pot, t=t, periodic=periodic, dtype=dtype)
+    assert H.N == Ho.n and H.width == 13
+    assert H.emin == pytest.approx(O.gershgorin(Ho)[0], abs=1e-14)
+    assert H.emax == pytest.approx(O.gershgorin(Ho)[1], abs=1e-14)
+    assert H.a == pytest.approx(a, rel=1e-15) and H.b == pytest.approx(b, abs=1e-15)
+    rp, col, val = K.export_csr(H)
+    assert np.array_equal(rp, Ho.rowptr)
+    ref_val = Ho.val
+    if dtype == "c64":
+        ref_val = ref_val.astype(np.complex64).astype(np.complex128)
+    for (c1, v1), (c2, v2) in zip(sorted_rows(rp, col, val), sorted_rows(Ho.rowptr, Ho.col, ref_val)):
+        assert np.array_equal(c1, c2)
+        assert np.array_equal(v1, v2)
+    H.close()
+
+
+# --------------------------------------------------------------------------
+# a3-a7: moments through kpm_moments
+# --------------------------------------------------------------------------
+def gpu_moments(L, pot, v0, M, dtype="c128", t=1.0, periodic=(1, 1, 1), eta=False):
+    K = kpm()
+    H = K.build_hamiltonian(L, pot, t=t, periodic=periodic, dtype=dtype)
+    V0 = torch.from_numpy(v0.astype(np.complex128 if dtype == "c128" else np.complex64)).cuda()
+    et = torch.zeros((M, v0.shape[1], 2), dtype=torch.float64, device="cuda") if eta else None
+    mu = K.moments(H, V0, M, eta=et)
+    torch.cuda.synchronize()
+    out = mu.cpu().numpy()
+    e = et.cpu().numpy() if eta else None
+    H.close()
+    return out, e
+
+
+def test_config1_matches_oracle_and_dense_eigendecomposition():
+    # 8x8x8 periodic lattice, gamma = 1, seed 0, R = 1, M = 128, complex128
+    L, M = (8, 8, 8), 128
+    say("config1")
+    pot, Ho, a, b = oracle_problem(L, 1.0, 0)
+    v0 = inputs.phase_block(Ho.n, 1, 0)
+    mu, _ = gpu_moments(L, pot, v0, M)
+    ref = O.kpm_moments(Ho, a, b, v0, M)
+    assert np.abs(mu - ref).max() <= TOL_C128
+    dense = O.dense_moments(Ho.dense(), a, b, v0, M)
+    assert np.abs(mu - dense).max() <= 1e-11
+    assert abs(mu[0, 0] - 1.0) <= 1e-14
+
+
+@pytest.mark.parametrize("R", [1, 2, 4, 8, 16, 32, 64])
+def test_moments_every_block_width(R):
+    # 7 x 5 x 6 sites: 840 rows, so every tile height leaves a ragged tail
+    L, M = (7, 5, 6), 48
+    say("moments R", R)
+    pot, Ho, a, b = oracle_problem(L, 1.5, R)
+    v0 = inputs.phase_block(Ho.n, R, 100 + R)
+    mu, eta = gpu_moments(L, pot, v0, M, eta=True)
+    ref_eta = O.kpm_eta(Ho, a, b, v0, M)
+    ref = O.mu_from_eta(ref_eta)
+    assert np.abs(mu - ref).max() <= TOL_C128
+    got_eta = eta[..., 0] + 1j * eta[..., 1]
+    assert np.abs(got_eta - ref_eta).max() <= TOL_C128
+    assert np.all(eta[0::2, :, 1] == 0.0)
+
+
+def test_moments_open_boundaries_and_many_tiles():
+    # open z side (padding slots), 9 x 8 x 10 sites = 2880 rows, R = 32, M = 200
+    L, M, R = (9, 8, 10), 200, 32
+    say("open boundaries")
+    pot, Ho, a, b = oracle_problem(L, 1.0, 4, periodic=(1, 1, 0))
+    v0 = inputs.phase_block(Ho.n, R, 5)
+    mu, _ = gpu_moments(L, pot, v0, M, periodic=(1, 1, 0))
+    ref = O.kpm_moments(Ho, a, b, v0, M)
+    assert np.abs(mu - ref).max() <= TOL_C128
+
+
+def test_moments_minimal_sizes():
+    # one site (N = 4, all sides open), M = 2 (only the initialisation sweep)
+    K = kpm()
+    L = (1, 1, 1)
+    say("minimal sizes")
+    pot, Ho, a, b = oracle_problem(L, 1.0, 9, periodic=(0, 0, 0))
+    for R, M in ((1, 2), (4, 2), (32, 6)):
+        v0 = inputs.phase_block(Ho.n, R, 1)
+        mu, _ = gpu_moments(L, pot, v0, M, periodic=(0, 0, 0))
+        ref = O.kpm_moments(Ho, a, b, v0, M)
+        assert np.abs(mu - ref).max() <= TOL_C128
+
+
+def test_complex64_storage_with_fp64_products():
+    L, M, R = (10, 10, 8), 400, 8
+    say("c64")
+    pot, Ho, a, b = oracle_problem(L, 2.0, 2)
+    v0 = inputs.phase_block(Ho.n, R, 2)
+    mu, _ = gpu_moments(L, pot, v0, M, dtype="c64")
+    ref = O.kpm_moments(Ho, a, b, v0, M)
+    err = np.abs(mu - ref).max()
+    say("c64 max |dmu|", err)
+    assert err <= TOL_C64
+    assert err > 0.0                      # it really ran in single precision
+    assert np.abs(mu[:, 0] - 1.0).max() <= 1e-6
+
+
+def test_moments_are_bitwise_deterministic():
+    K = kpm()
+    L, M, R = (12, 12, 12), 64, 32
+    say("determinism")
+    pot = inputs.potential(L, 1.0, 0)
+    H = K.build_hamiltonian(L, pot)
+    V0 = torch.from_numpy(inputs.phase_block(H.N, R, 0)).cuda()
+    m1 = K.moments(H, V0, M).cpu()
+    m2 = K.moments(H, V0, M).cpu()
+    assert torch.equal(m1, m2)
+    H.close()
+
+
+# --------------------------------------------------------------------------
+# a4-a6, a14: single sweeps and the diagnostic variants
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("R", [1, 8, 32, 64])
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_single_sweep_variants(R, dtype):
+    K = kpm()
+    L = (5, 6, 7)
+    say("sweep variants", R, dtype)
+    pot, Ho, a, b = oracle_problem(L, 1.0, 8)
+    Hd = Ho.dense()
+    cdt = np.complex128 if dtype == "c128" else np.complex64
+    H = K.build_hamiltonian(L, pot, dtype=dtype)
+    rng = np.random.default_rng(R)
+    X = (rng.standard_normal((Ho.n, R)) + 1j * rng.standard_normal((Ho.n, R))).astype(cdt)
+    Y = (rng.standard_normal((Ho.n, R)) + 1j * rng.standard_normal((Ho.n, R))).astype(cdt)
+    Hx = Hd.astype(cdt).astype(np.complex128) @ X.astype(np.complex128)
+    tol = 1e-12 if dtype == "c128" else 5e-5
+    alpha, beta, gamma = 0.3, -0.7, -1.0
+
+    Vt = torch.from_numpy(X).cuda()
+    Wt = torch.from_numpy(Y.copy()).cuda()
+    K.aug_spmmv(H, Vt, Wt, 1.0, 0.0, 0.0, variant="plain")
+    assert np.abs(Wt.cpu().numpy() - Hx).max() <= tol * max(1.0, np.abs(Hx).max())
+
+    Wt = torch.from_numpy(Y.copy()).cuda()
+    K.aug_spmmv(H, Vt, Wt, alpha, beta, gamma, variant="nodot")
+    ref = alpha * Hx + beta * X + gamma * Y
+    assert np.abs(Wt.cpu().numpy() - ref).max() <= tol * max(1.0, np.abs(ref).max())
+
+    Wt = torch.from_numpy(Y.copy()).cuda()
+    eta = torch.zeros((2, R, 2), dtype=torch.float64, device="cuda")
+    K.aug_spmmv(H, Vt, Wt, alpha, beta, gamma, variant="full", eta=eta)
+    Wn = Wt.cpu().numpy()
+    assert np.abs(Wn - ref).max() <= tol * max(1.0, np.abs(ref).max())
+    e = eta.cpu().numpy()
+    x64, w64 = X.astype(np.complex128), Wn.astype(np.complex128)
+    vv = np.sum(np.abs(x64) ** 2, axis=0)
+    wv = np.sum(w64.conj() * x64, axis=0)
+    assert np.abs(e[0, :, 0] - vv).max() <= 1e-12 * vv.max()
+    assert np.abs(e[1, :, 0] + 1j * e[1, :, 1] - wv).max() <= 1e-12 * np.abs(wv).max() * 10
+    H.close()
+
+
+# --------------------------------------------------------------------------
+# a8: density of states
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("kernel,kparam", [("jackson", 0.0), ("dirichlet", 0.0), ("lorentz", 4.0)])
+def test_dos_matches_oracle(kernel, kparam):
+    K = kpm()
+    say("dos", kernel)
+    L, M, R = (6, 6, 6), 300, 4
+    pot, Ho, a, b = oracle_problem(L, 1.0, 1)
+    v0 = inputs.phase_block(Ho.n, R, 3)
+    mu = O.kpm_moments(Ho, a, b, v0, M)
+    E = np.concatenate([O.midpoint_grid(777, a, b), [b - a, b + a, b + 2 * a, b - 3 * a]])
+    g = {"jackson": O.jackson(M), "dirichlet": O.dirichlet(M), "lorentz": O.lorentz(M, kparam)}[kernel]
+    ref = O.dos(mu, g, a, b, E)
+    rho = K.dos(torch.from_numpy(mu).cuda(), a, b, torch.from_numpy(E).cuda(), kernel=kernel, kparam=kparam)
+    got = rho.cpu().numpy()
+    assert np.abs(got - ref).max() <= 1e-10 * np.abs(ref).max()
+    assert np.all(got[-4:] == 0.0)       # |x| >= 1
+
+
+def test_dos_long_expansion():
+    # M = 5000 spans three LDS chunks of the reconstruction kernel
+    K = kpm()
+    M = 5000
+    x0 = 0.31
+    mu = np.cos(np.arange(M) * np.arccos(x0))[None, :]
+    E = O.midpoint_grid(4096, 1.0, 0.0)
+    ref = O.dos(mu, O.jackson(M), 1.0, 0.0, E)
+    got = K.dos(torch.from_numpy(mu).cuda(), 1.0, 0.0, torch.from_numpy(E).cuda()).cpu().numpy()
+    assert np.abs(got - ref).max() <= 1e-9 * np.abs(ref).max()
+
+
+# --------------------------------------------------------------------------
+# error paths reached from the host
+# --------------------------------------------------------------------------
+def test_error_paths():
+    K = kpm()
+    L = (4, 4, 4)
+    pot = inputs.potential(L, 1.0, 0)
+    H = K.build_hamiltonian(L, pot)
+    V0 = torch.from_numpy(inputs.phase_block(H.N, 4, 0)).cuda()
+    with pytest.raises(K.KPMError) as e:
+        K.moments(H, V0, 7)
+    assert e.value.status == K.KPM_EINVAL
+    V3 = torch.from_numpy(inputs.phase_block(H.N, 3, 0)).cuda()
+    with pytest.raises(K.KPMError) as e:
+        K.moments(H, V3, 8)
+    assert e.value.status == K.KPM_ENOTSUP
+    with pytest.raises(K.KPMError) as e:
+        K.build_hamiltonian((2, 4, 4), np.zeros(32))
+    assert e.value.status == K.KPM_ENOTSUP
+    with pytest.raises(K.KPMError) as e:
+        K.build_hamiltonian(L, np.full(64, np.nan))
+    assert e.value.status == K.KPM_EINVAL
+    # a caller-fixed scale far too small: the spectrum leaves [-1, 1]
+    Hs = K.build_hamiltonian(L, pot, fixed_scale=(2.0, 0.0))
+    with pytest.raises(K.KPMError) as e:
+        K.moments(Hs, V0, 64)
+    assert e.value.status == K.KPM_ESPECTRUM
+    Hs.close()
+    H.close()
+
+
+# --------------------------------------------------------------------------
+# the benchmark workload at full size: 64^3 lattice, R = 32, M = 2000
+# --------------------------------------------------------------------------
+@pytest.mark.slow
+def test_full_size_benchmark_workload():
+    K = kpm()
+    L, R, M = (64, 64, 64), 32, 2000
+    say("full size: build")
+    pot = inputs.potential(L, 1.0, 0)
+    H = K.build_hamiltonian(L, pot)
+    assert H.N == 1048576
+    Ho = O.ti_hamiltonian(L, pot)
+    a, b = O.scaling(*O.gershgorin(Ho))
+    assert H.a == pytest.approx(a, rel=1e-15) and H.b == pytest.approx(b, abs=1e-15)
+    v0 = inputs.phase_block(H.N, R, 0)
+    V0 = torch.from_numpy(v0).cuda()
+    say("full size: moments")
+    mu = K.moments(H, V0, M).cpu().numpy()
+    # prefix: the oracle runs the first 8 moments (4 sweeps) at full size
+    say("full size: oracle prefix")
+    ref = O.kpm_moments(Ho, a, b, v0, 8)
+    assert np.abs(mu[:, :8] - ref).max() <= TOL_C128
+    # properties at any size: mu_0 = 1, |mu_n| <= 1, and the Jackson DOS integrates to 1
+    assert np.abs(mu[:, 0] - 1.0).max() <= 1e-13
+    assert np.abs(mu).max() <= 1.0 + 1e-12
+    E = O.midpoint_grid(4096, H.a, H.b)
+    rho = K.dos(torch.from_numpy(mu).cuda(), H.a, H.b, torch.from_numpy(E).cuda()).cpu().numpy()
+    assert abs(rho.sum() * (2 * H.a / 4096) - 1.0) < 1e-4
+    # same GPU run, truncated: moments are prefix-identical
+    mu_short = K.moments(H, V0, 64).cpu().numpy()
+    assert np.array_equal(mu_short, mu[:, :64])
+    H.close()
