@@ -91,6 +91,37 @@ def cpu_baseline(L, gamma, R, dtype, target_s=15.0):
                       f"{dt:.2f} s; Gflop/s {sweep_flops(Ho.n, R) * sweeps / dt / 1e9:.2f}"}
 
 
+COPY_BYTES = 1 << 30
+
+
+def probe(args, H, V0, M, R, Sd):
+    """Copy calibration plus a few sweeps, for rocprofv3 --pmc runs."""
+    import torch
+    from paper_1410_5242_amd import kpm
+    x = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=V0.device)
+    y = torch.empty_like(x)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for _ in range(3):
+        y.copy_(x)
+    ev[1].record()
+    torch.cuda.synchronize()
+    copy_ms = ev[0].elapsed_time(ev[1]) / 3
+    del x, y
+    kpm.sweep_profile_read()
+    kpm.sweep_profile_enable(True)
+    mu = kpm.moments(H, V0, 2 * args.probe_sweeps)
+    torch.cuda.synchronize()
+    kpm.sweep_profile_enable(False)
+    n, tot, lo, hi = kpm.sweep_profile_read()
+    bps = sweep_bytes(H.N, 13 * H.N, R, Sd)
+    print(json.dumps({"probe": True, "copy_bytes_read": COPY_BYTES, "copy_bytes_written": COPY_BYTES,
+                      "copy_ms": round(copy_ms, 4), "copy_GBps": round(2 * COPY_BYTES / copy_ms / 1e6, 1),
+                      "sweeps": n, "sweep_avg_ms": round(tot / max(n, 1), 5),
+                      "sweep_algorithmic_bytes": bps, "mu0": float(mu[0, 0].item())}), flush=True)
+    H.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -99,6 +130,10 @@ def main():
     ap.add_argument("--workload", default="ti64_r32_m2000_c128", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-target-s", type=float, default=15.0)
+    ap.add_argument("--probe", action="store_true",
+                    help="short run for hardware counters: a 1 GiB device copy (the calibration kernel "
+                         "of known traffic) and --probe-sweeps fused sweeps of the workload")
+    ap.add_argument("--probe-sweeps", type=int, default=8)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU sharding is a design, "
@@ -125,6 +160,10 @@ def main():
     mu = torch.empty((R, M), dtype=torch.float64, device=dev)
     rho = torch.empty(K, dtype=torch.float64, device=dev)
     log(f"[bench] built H: N={N} a={H.a:.6f} b={H.b:.6f} ({build_s:.3f} s)")
+
+    if args.probe:
+        probe(args, H, V0, M, R, Sd)
+        return
 
     def step():
         kpm.moments(H, V0, M, mu=mu, check=True)

@@ -144,6 +144,44 @@ kpm_status kpm_moments(const kpm_hamiltonian* H, const void* V0, int32_t R, int3
 kpm_status kpm_dos(const double* mu, int32_t R, int32_t M, int32_t kernel, double kparam,
                    double a, double b, const double* E, int32_t K, double* rho, void* stream);
 
+/* Launch shape of the fused sweep kernel (process-wide, not thread-safe;
+ * results do not depend on it beyond the order of floating-point sums):
+ *   wg_per_cu    workgroups (of 4 waves) per compute unit in the persistent
+ *                grid; 0 selects 8 (32 resident waves per CU)
+ *   xcd_ways     row tiles are split into this many contiguous ranges, one
+ *                per accelerator die, matching the round-robin dispatch of
+ *                workgroups to the 8 XCDs; 1 disables it; default 8
+ *   chunk_tiles  consecutive row tiles a workgroup takes per grab (dynamic)
+ *                or before striding (static); default 8
+ *   dynamic      nonzero: each workgroup reads the id of the die it runs on
+ *                and takes tiles from that die's range through an atomic
+ *                counter, then helps the other ranges; the rows a workgroup
+ *                sums then vary between runs, so the scalar products agree
+ *                between runs only to rounding.  Zero: static mapping
+ *                (workgroup g takes range g % xcd_ways), bitwise
+ *                reproducible; default 0
+ *   prefetch     nonzero: before a wave streams its tiles it touches every
+ *                line of their matrix rows and old W rows, so that the
+ *                per-row loads hit L2; default 1
+ *   pencil       processing order of the lattice sites: pencils of
+ *                pencil x pencil sites spanning the whole z extent, each
+ *                walked plane by plane (x fastest), so that the rows a sweep
+ *                gathers for the z neighbours were fetched one plane
+ *                earlier; 0 keeps the natural row order; default 16.  The
+ *                storage order of H and of the vector blocks never changes.
+ * kpm_set_sweep_tuning(NULL) restores the defaults.  Errors: KPM_EINVAL
+ * (negative field). */
+typedef struct {
+    int32_t wg_per_cu;
+    int32_t xcd_ways;
+    int32_t chunk_tiles;
+    int32_t pencil;
+    int32_t dynamic;
+    int32_t prefetch;
+} kpm_sweep_tuning;
+kpm_status kpm_set_sweep_tuning(const kpm_sweep_tuning* tuning);
+kpm_status kpm_get_sweep_tuning(kpm_sweep_tuning* tuning);
+
 /* Sweep-kernel timing for measurement tools.  While enabled (process-wide,
  * not thread-safe), every fused sweep launched by kpm_moments and
  * kpm_aug_spmmv is bracketed by a pair of HIP events on its own stream.

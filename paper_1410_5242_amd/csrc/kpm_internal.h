@@ -23,6 +23,8 @@ struct Workspace {
     void* vbuf[2] = {nullptr, nullptr};   // two [N][R] blocks
     size_t vbytes = 0;
     double* partials = nullptr;            // [slots][grid][3][R]
+    int* queue = nullptr;                  // [slots][kXcds] tile counters
+    size_t qbytes = 0;
     size_t pbytes = 0;
     double* eta = nullptr;                 // [M][R][2]
     size_t etabytes = 0;
@@ -38,6 +40,9 @@ struct kpm_hamiltonian {
     int width = kpm::kWidth;        // slots per row (row-major, diagonal first)
     void* val = nullptr;            // [N][width] complex (re, im) in dtype
     int32_t* col = nullptr;         // [N][width]
+    int L[3] = {0, 0, 0};           // lattice sides
+    int32_t* sched = nullptr;       // device [N/4]: sites in processing order (nullptr = natural)
+    int sched_pencil = -1;          // pencil side the schedule was made for
     double a = 1.0, b = 0.0;        // Htilde = (H - b)/a
     double emin = 0.0, emax = 0.0;  // Gershgorin interval
     int device = 0;
@@ -63,10 +68,18 @@ struct SweepArgs {
     int64_t nrows;
     const void* V;
     void* W;
+    const int32_t* sched;   // sites in processing order, or nullptr
     double alpha, beta, gamma;
     double* partials;   // this sweep's [grid][3][R] slot (FULL only)
     int grid;           // workgroups
+    int* queue = nullptr;   // this sweep's [kXcds] tile counters (zero), or nullptr
+    int xcd_ways = 1;   // filled by launch_sweep from the tuning
+    int chunk = 1;
+    int prefetch = 1;
 };
+
+kpm_sweep_tuning get_tuning();
+void set_tuning(const kpm_sweep_tuning& t);
 
 // Grid size (workgroups) the sweep kernel uses for this dtype / R.
 int sweep_grid(int dtype, int R);
@@ -76,6 +89,7 @@ hipError_t launch_sweep(int dtype, int R, int variant, const SweepArgs& a, hipSt
 hipError_t launch_reduce_partials(const double* partials, int nslots, int grid, int R,
                                   int sweep0, double* eta, hipStream_t s);
 hipError_t launch_eta_to_mu(const double* eta, int R, int M, double* mu, hipStream_t s);
+hipError_t launch_zero_ints(int* p, int n, hipStream_t s);
 hipError_t launch_check_moments(const double* mu, int R, int M, int* flag, hipStream_t s);
 hipError_t launch_dos(const double* mu, int R, int M, int kernel, double kparam, double a,
                       double b, const double* E, int K, double* rho, hipStream_t s);

@@ -82,6 +82,43 @@ kpm_status ensure_partials(kpm_hamiltonian* H, int R, int slots) {
     return grow(&H->ws.partials, &H->ws.pbytes, need, "hipMalloc(partials)");
 }
 
+// Sites in processing order: pencils of P x P sites over the full z extent,
+// pencils ordered x-block fastest, each pencil walked plane by plane with x
+// fastest.  Every site appears exactly once.
+std::vector<int32_t> pencil_schedule(const int L[3], int P) {
+    std::vector<int32_t> s;
+    s.reserve(static_cast<size_t>(L[0]) * L[1] * L[2]);
+    for (int by = 0; by < L[1]; by += P)
+        for (int bx = 0; bx < L[0]; bx += P)
+            for (int z = 0; z < L[2]; ++z)
+                for (int y = by; y < by + P && y < L[1]; ++y)
+                    for (int x = bx; x < bx + P && x < L[0]; ++x)
+                        s.push_back(static_cast<int32_t>(x + static_cast<int64_t>(L[0]) * (y + static_cast<int64_t>(L[1]) * z)));
+    return s;
+}
+
+// Make H's processing schedule match the current tuning.
+kpm_status ensure_schedule(kpm_hamiltonian* H) {
+    const int P = get_tuning().pencil;
+    if (P == H->sched_pencil) return KPM_OK;
+    if (H->sched) {
+        KPM_HIP(hipFree(H->sched), "hipFree");
+        H->sched = nullptr;
+    }
+    H->sched_pencil = P;
+    if (P <= 0) return KPM_OK;
+    std::vector<int32_t> s = pencil_schedule(H->L, P);
+    if (static_cast<int64_t>(s.size()) * 4 != H->nrows) return fail(KPM_EINTERNAL, "schedule size mismatch");
+    KPM_HIP(hipMalloc(&H->sched, s.size() * sizeof(int32_t)), "hipMalloc(schedule)");
+    KPM_HIP(hipMemcpy(H->sched, s.data(), s.size() * sizeof(int32_t), hipMemcpyHostToDevice), "copy schedule");
+    return KPM_OK;
+}
+
+kpm_status ensure_queue(kpm_hamiltonian* H) {
+    return grow(&H->ws.queue, &H->ws.qbytes, static_cast<size_t>(kReduceEvery) * kXcds * sizeof(int),
+                "hipMalloc(queue)");
+}
+
 kpm_status ensure_flag(kpm_hamiltonian* H) {
     if (!H->ws.flag) KPM_HIP(hipMalloc(&H->ws.flag, sizeof(int)), "hipMalloc(flag)");
     if (!H->ws.flag_host) KPM_HIP(hipHostMalloc(&H->ws.flag_host, sizeof(int)), "hipHostMalloc(flag)");
@@ -156,6 +193,7 @@ kpm_status kpm_build_hamiltonian(const kpm_lattice_desc* d, void* stream, kpm_ha
     hipStream_t s = static_cast<hipStream_t>(stream);
     H->dtype = d->dtype;
     H->nrows = 4 * nsite;
+    for (int j = 0; j < 3; ++j) H->L[j] = d->L[j];
     H->width = kWidth;
     if (hipGetDevice(&H->device) != hipSuccess) {
         delete H;
@@ -265,6 +303,8 @@ void kpm_destroy_hamiltonian(kpm_hamiltonian* H) {
     for (int i = 0; i < 2; ++i)
         if (H->ws.vbuf[i]) (void)hipFree(H->ws.vbuf[i]);
     if (H->ws.partials) (void)hipFree(H->ws.partials);
+    if (H->ws.queue) (void)hipFree(H->ws.queue);
+    if (H->sched) (void)hipFree(H->sched);
     if (H->ws.eta) (void)hipFree(H->ws.eta);
     if (H->ws.flag) (void)hipFree(H->ws.flag);
     if (H->ws.flag_host) (void)hipHostFree(H->ws.flag_host);
@@ -288,13 +328,17 @@ kpm_status kpm_aug_spmmv(const kpm_hamiltonian* Hc, const void* V, void* W, int3
     const char* w0 = static_cast<const char*>(W);
     if (v0 < w0 + bytes && w0 < v0 + bytes) return fail(KPM_EINVAL, "V and W overlap");
     hipStream_t s = static_cast<hipStream_t>(stream);
+    if ((st = ensure_schedule(H)) != KPM_OK) return st;
     const bool dots = (variant == KPM_FULL && eta != nullptr);
     if (dots) {
         st = ensure_partials(H, R, 1);
         if (st != KPM_OK) return st;
     }
-    SweepArgs a{H->val, H->col, H->nrows, V, W, alpha, beta, gamma,
+    if ((st = ensure_queue(H)) != KPM_OK) return st;
+    KPM_HIP(launch_zero_ints(H->ws.queue, kXcds, s), "zero kernel");
+    SweepArgs a{H->val, H->col, H->nrows, V, W, H->sched, alpha, beta, gamma,
                 dots ? H->ws.partials : nullptr, sweep_grid(H->dtype, R)};
+    a.queue = H->ws.queue;
     const int launch_variant = (variant == KPM_FULL && !dots) ? KPM_NODOT : variant;
     KPM_HIP(launch_sweep_profiled(H->dtype, R, launch_variant, a, s), "sweep kernel");
     if (dots) KPM_HIP(launch_reduce_partials(H->ws.partials, 1, a.grid, R, 0, eta, s), "reduce kernel");
@@ -314,7 +358,9 @@ kpm_status kpm_moments(const kpm_hamiltonian* Hc, const void* V0, int32_t R, int
     const int sweeps = M / 2;
     const int slots = sweeps < kReduceEvery ? sweeps : kReduceEvery;
     if ((st = ensure_vectors(H, R)) != KPM_OK) return st;
+    if ((st = ensure_schedule(H)) != KPM_OK) return st;
     if ((st = ensure_partials(H, R, slots)) != KPM_OK) return st;
+    if ((st = ensure_queue(H)) != KPM_OK) return st;
     double* eta = eta_out;
     if (!eta) {
         if ((st = grow(&H->ws.eta, &H->ws.etabytes, static_cast<size_t>(M) * R * 2 * sizeof(double),
@@ -332,8 +378,11 @@ kpm_status kpm_moments(const kpm_hamiltonian* Hc, const void* V0, int32_t R, int
     const double inv_a = 1.0 / H->a;
     for (int k = 0; k < sweeps; ++k) {
         const int sl = k % kReduceEvery;
-        SweepArgs a{H->val, H->col, H->nrows, nullptr, nullptr, 0.0, 0.0, 0.0,
+        if (sl == 0)   // tile counters of the next kReduceEvery sweeps
+            KPM_HIP(launch_zero_ints(H->ws.queue, kReduceEvery * kXcds, s), "zero kernel");
+        SweepArgs a{H->val, H->col, H->nrows, nullptr, nullptr, H->sched, 0.0, 0.0, 0.0,
                     H->ws.partials + sl * slot_elems, grid};
+        a.queue = H->ws.queue + sl * kXcds;
         if (k == 0) {
             // nu_1 = Htilde nu_0 = (1/a) H nu_0 - (b/a) nu_0
             a.V = A; a.W = B; a.alpha = inv_a; a.beta = -H->b * inv_a; a.gamma = 0.0;
@@ -369,6 +418,28 @@ kpm_status kpm_dos(const double* mu, int32_t R, int32_t M, int32_t kernel, doubl
     if (kernel == KPM_LORENTZ && !(kparam > 0.0)) return fail(KPM_EINVAL, "Lorentz kernel needs kparam > 0");
     hipStream_t s = static_cast<hipStream_t>(stream);
     KPM_HIP(launch_dos(mu, R, M, kernel, kparam, a, b, E, K, rho, s), "dos kernel");
+    return KPM_OK;
+}
+
+kpm_status kpm_set_sweep_tuning(const kpm_sweep_tuning* t) {
+    g_error.clear();
+    if (!t) {
+        set_tuning(kpm_sweep_tuning{0, kXcds, 8, 16, 0, 1});
+        return KPM_OK;
+    }
+    if (t->wg_per_cu < 0 || t->xcd_ways < 0 || t->chunk_tiles < 0 || t->pencil < 0 || t->dynamic < 0 ||
+        t->prefetch < 0)
+        return fail(KPM_EINVAL, "tuning fields must be >= 0");
+    if (t->wg_per_cu > 64 || t->xcd_ways > 64 || t->chunk_tiles > (1 << 20))
+        return fail(KPM_EINVAL, "tuning field out of range");
+    set_tuning(*t);
+    return KPM_OK;
+}
+
+kpm_status kpm_get_sweep_tuning(kpm_sweep_tuning* t) {
+    g_error.clear();
+    if (!t) return fail(KPM_EINVAL, "tuning is NULL");
+    *t = get_tuning();
     return KPM_OK;
 }
 

@@ -34,6 +34,11 @@ class KPMError(RuntimeError):
         self.status = status
 
 
+class SweepTuning(ctypes.Structure):
+    _fields_ = [("wg_per_cu", ctypes.c_int32), ("xcd_ways", ctypes.c_int32), ("chunk_tiles", ctypes.c_int32),
+                ("pencil", ctypes.c_int32), ("dynamic", ctypes.c_int32), ("prefetch", ctypes.c_int32)]
+
+
 class LatticeDesc(ctypes.Structure):
     _fields_ = [
         ("L", ctypes.c_int32 * 3),
@@ -51,7 +56,7 @@ class LatticeDesc(ctypes.Structure):
 _LIB = None
 EXPORTS = ("kpm_build_hamiltonian", "kpm_hamiltonian_info", "kpm_export_csr",
            "kpm_destroy_hamiltonian", "kpm_aug_spmmv", "kpm_moments", "kpm_dos",
-           "kpm_sweep_profile_enable", "kpm_sweep_profile_read", "kpm_last_error", "kpm_version")
+           "kpm_set_sweep_tuning", "kpm_get_sweep_tuning", "kpm_sweep_profile_enable", "kpm_sweep_profile_read", "kpm_last_error", "kpm_version")
 
 
 def lib():
@@ -79,6 +84,10 @@ def lib():
     L.kpm_moments.argtypes = [vp, vp, i32, i32, vp, vp, i32, vp]
     L.kpm_dos.restype = ctypes.c_int
     L.kpm_dos.argtypes = [vp, i32, i32, i32, dbl, dbl, dbl, vp, i32, vp, vp]
+    L.kpm_set_sweep_tuning.restype = ctypes.c_int
+    L.kpm_set_sweep_tuning.argtypes = [ctypes.POINTER(SweepTuning)]
+    L.kpm_get_sweep_tuning.restype = ctypes.c_int
+    L.kpm_get_sweep_tuning.argtypes = [ctypes.POINTER(SweepTuning)]
     L.kpm_sweep_profile_enable.restype = ctypes.c_int
     L.kpm_sweep_profile_enable.argtypes = [i32]
     L.kpm_sweep_profile_read.restype = ctypes.c_int
@@ -204,6 +213,24 @@ def dos(mu: torch.Tensor, a: float, b: float, E: torch.Tensor, kernel: str = "ja
     _check(lib().kpm_dos(_dptr(mu), R, M, _KERNELS[kernel], float(kparam), float(a), float(b),
                          _dptr(E), K, _dptr(rho), _stream(stream)))
     return rho
+
+
+def set_sweep_tuning(wg_per_cu: int = 0, xcd_ways: int = 8, chunk_tiles: int = 8, pencil: int = 16,
+                     dynamic: int = 0, prefetch: int = 1):
+    """kpm_set_sweep_tuning: launch shape and site order of the sweep kernel (process-wide)."""
+    _check(lib().kpm_set_sweep_tuning(ctypes.byref(SweepTuning(wg_per_cu, xcd_ways, chunk_tiles, pencil,
+                                                               dynamic, prefetch))))
+
+
+def reset_sweep_tuning():
+    _check(lib().kpm_set_sweep_tuning(None))
+
+
+def get_sweep_tuning():
+    t = SweepTuning()
+    _check(lib().kpm_get_sweep_tuning(ctypes.byref(t)))
+    return {"wg_per_cu": t.wg_per_cu, "xcd_ways": t.xcd_ways, "chunk_tiles": t.chunk_tiles, "pencil": t.pencil,
+            "dynamic": t.dynamic, "prefetch": t.prefetch}
 
 
 def sweep_profile_enable(on: bool = True):

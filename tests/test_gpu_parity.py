@@ -169,17 +169,41 @@ def test_complex64_storage_with_fp64_products():
     assert np.abs(mu[:, 0] - 1.0).max() <= 1e-6
 
 
-def test_moments_are_bitwise_deterministic():
+def test_moments_are_bitwise_deterministic_static_mapping():
     K = kpm()
     L, M, R = (12, 12, 12), 64, 32
     say("determinism")
     pot = inputs.potential(L, 1.0, 0)
     H = K.build_hamiltonian(L, pot)
     V0 = torch.from_numpy(inputs.phase_block(H.N, R, 0)).cuda()
-    m1 = K.moments(H, V0, M).cpu()
-    m2 = K.moments(H, V0, M).cpu()
+    try:
+        K.set_sweep_tuning(dynamic=0)
+        m1 = K.moments(H, V0, M).cpu()
+        m2 = K.moments(H, V0, M).cpu()
+    finally:
+        K.reset_sweep_tuning()
     assert torch.equal(m1, m2)
     H.close()
+
+
+@pytest.mark.parametrize("tuning", [
+    dict(dynamic=1), dict(dynamic=1, chunk_tiles=1), dict(dynamic=0, prefetch=0),
+    dict(dynamic=0, pencil=0, xcd_ways=1, chunk_tiles=3), dict(wg_per_cu=2, dynamic=1, pencil=5),
+])
+def test_launch_shapes_agree(tuning):
+    # the launch shape and site order change only the order of the FP64 sums
+    K = kpm()
+    L, M, R = (11, 9, 10), 200, 32
+    say("launch shape", tuning)
+    pot, Ho, a, b = oracle_problem(L, 1.0, 6)
+    v0 = inputs.phase_block(Ho.n, R, 6)
+    ref = O.kpm_moments(Ho, a, b, v0, M)
+    try:
+        K.set_sweep_tuning(**tuning)
+        mu, _ = gpu_moments(L, pot, v0, M)
+    finally:
+        K.reset_sweep_tuning()
+    assert np.abs(mu - ref).max() <= TOL_C128
 
 
 # --------------------------------------------------------------------------
