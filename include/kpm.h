@@ -163,6 +163,9 @@ kpm_status kpm_dos(const double* mu, int32_t R, int32_t M, int32_t kernel, doubl
  *   prefetch     nonzero: before a wave streams its tiles it touches every
  *                line of their matrix rows and old W rows, so that the
  *                per-row loads hit L2; default 1
+ *   stream       bit 0: old-W loads, bit 1: new-W stores carry the
+ *                non-temporal hint (W is touched once per sweep, unlike the
+ *                V rows, which are gathered 13 times); default 0
  *   pencil       processing order of the lattice sites: pencils of
  *                pencil x pencil sites spanning the whole z extent, each
  *                walked plane by plane (x fastest), so that the rows a sweep
@@ -178,6 +181,7 @@ typedef struct {
     int32_t pencil;
     int32_t dynamic;
     int32_t prefetch;
+    int32_t stream;
 } kpm_sweep_tuning;
 kpm_status kpm_set_sweep_tuning(const kpm_sweep_tuning* tuning);
 kpm_status kpm_get_sweep_tuning(kpm_sweep_tuning* tuning);

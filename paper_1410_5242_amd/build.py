@@ -15,7 +15,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libkpm.so")
-SOURCES = ["kpm_runtime.cpp", "kpm_build.hip", "kpm_spmmv.hip", "kpm_dos.hip"]
+SOURCES = ["kpm_runtime.cpp", "kpm_build.hip", "kpm_spmmv.hip", "kpm_dos.hip",
+           "kpm_sweep_c128_large.hip", "kpm_sweep_c128_small.hip",
+           "kpm_sweep_c64_large.hip", "kpm_sweep_c64_small.hip"]
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -35,7 +37,7 @@ def _compile(src: str, verbose: bool) -> str:
     return obj
 
 
-def build(verbose: bool = False, jobs: int = 4) -> str:
+def build(verbose: bool = False, jobs: int = 8) -> str:
     os.makedirs(OBJ, exist_ok=True)
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
@@ -48,7 +50,7 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
     return LIB
 
 
-def asm(src: str = "kpm_spmmv.hip", out: str | None = None) -> str:
+def asm(src: str = "kpm_sweep_c128_large.hip", out: str | None = None) -> str:
     """Write the gfx950 assembly of one source (for inspection)."""
     out = out or os.path.join(OBJ, os.path.splitext(src)[0] + ".s")
     os.makedirs(OBJ, exist_ok=True)

@@ -76,6 +76,7 @@ struct SweepArgs {
     int xcd_ways = 1;   // filled by launch_sweep from the tuning
     int chunk = 1;
     int prefetch = 1;
+    int stream = 0;
 };
 
 kpm_sweep_tuning get_tuning();
@@ -84,6 +85,11 @@ void set_tuning(const kpm_sweep_tuning& t);
 // Grid size (workgroups) the sweep kernel uses for this dtype / R.
 int sweep_grid(int dtype, int R);
 hipError_t launch_sweep(int dtype, int R, int variant, const SweepArgs& a, hipStream_t s);
+// per-precision instantiations of the sweep kernel (R <= 16 and R >= 32)
+hipError_t launch_sweep_c128_small(int R, int variant, const SweepArgs& a, hipStream_t s);
+hipError_t launch_sweep_c128_large(int R, int variant, const SweepArgs& a, hipStream_t s);
+hipError_t launch_sweep_c64_small(int R, int variant, const SweepArgs& a, hipStream_t s);
+hipError_t launch_sweep_c64_large(int R, int variant, const SweepArgs& a, hipStream_t s);
 
 // eta[(sweep0 + s)*2 + q] for s < nslots from partials[s][grid][3][R].
 hipError_t launch_reduce_partials(const double* partials, int nslots, int grid, int R,

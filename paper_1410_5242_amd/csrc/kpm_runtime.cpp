@@ -424,11 +424,11 @@ kpm_status kpm_dos(const double* mu, int32_t R, int32_t M, int32_t kernel, doubl
 kpm_status kpm_set_sweep_tuning(const kpm_sweep_tuning* t) {
     g_error.clear();
     if (!t) {
-        set_tuning(kpm_sweep_tuning{0, kXcds, 8, 16, 0, 1});
+        set_tuning(kpm_sweep_tuning{0, kXcds, 8, 16, 0, 1, 0});
         return KPM_OK;
     }
     if (t->wg_per_cu < 0 || t->xcd_ways < 0 || t->chunk_tiles < 0 || t->pencil < 0 || t->dynamic < 0 ||
-        t->prefetch < 0)
+        t->prefetch < 0 || t->stream < 0 || t->stream > 3)
         return fail(KPM_EINVAL, "tuning fields must be >= 0");
     if (t->wg_per_cu > 64 || t->xcd_ways > 64 || t->chunk_tiles > (1 << 20))
         return fail(KPM_EINVAL, "tuning field out of range");

@@ -36,7 +36,8 @@ class KPMError(RuntimeError):
 
 class SweepTuning(ctypes.Structure):
     _fields_ = [("wg_per_cu", ctypes.c_int32), ("xcd_ways", ctypes.c_int32), ("chunk_tiles", ctypes.c_int32),
-                ("pencil", ctypes.c_int32), ("dynamic", ctypes.c_int32), ("prefetch", ctypes.c_int32)]
+                ("pencil", ctypes.c_int32), ("dynamic", ctypes.c_int32), ("prefetch", ctypes.c_int32),
+                ("stream", ctypes.c_int32)]
 
 
 class LatticeDesc(ctypes.Structure):
@@ -216,10 +217,10 @@ def dos(mu: torch.Tensor, a: float, b: float, E: torch.Tensor, kernel: str = "ja
 
 
 def set_sweep_tuning(wg_per_cu: int = 0, xcd_ways: int = 8, chunk_tiles: int = 8, pencil: int = 16,
-                     dynamic: int = 0, prefetch: int = 1):
+                     dynamic: int = 0, prefetch: int = 1, stream: int = 0):
     """kpm_set_sweep_tuning: launch shape and site order of the sweep kernel (process-wide)."""
     _check(lib().kpm_set_sweep_tuning(ctypes.byref(SweepTuning(wg_per_cu, xcd_ways, chunk_tiles, pencil,
-                                                               dynamic, prefetch))))
+                                                               dynamic, prefetch, stream))))
 
 
 def reset_sweep_tuning():
@@ -230,7 +231,7 @@ def get_sweep_tuning():
     t = SweepTuning()
     _check(lib().kpm_get_sweep_tuning(ctypes.byref(t)))
     return {"wg_per_cu": t.wg_per_cu, "xcd_ways": t.xcd_ways, "chunk_tiles": t.chunk_tiles, "pencil": t.pencil,
-            "dynamic": t.dynamic, "prefetch": t.prefetch}
+            "dynamic": t.dynamic, "prefetch": t.prefetch, "stream": t.stream}
 
 
 def sweep_profile_enable(on: bool = True):
