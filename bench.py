@@ -36,9 +36,20 @@ WORKLOADS = {
     "ti64_r32_m2000_c128": ((64, 64, 64), 1.0, 32, 2000, "c128", 4096),
     "ti128x128x64_r32_m2000_c64": ((128, 128, 64), 2.0, 32, 2000, "c64", 4096),
 }
-SWEEP_KERNEL = "aug_spmmv_kernel"
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "aug_spmmv_traffic.json")
-SWEEP_SOURCE = os.path.join(ROOT, "paper_1410_5242_amd", "csrc", "kpm_spmmv.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_traffic.json")
+CSRC = os.path.join(ROOT, "paper_1410_5242_amd", "csrc")
+# sources that define each sweep kernel (hashed to tie counters to the code they were taken on)
+KERNEL_SOURCES = {
+    "lattice_kernel": ["kpm_lattice.hip", "kpm_sweep.h"],
+    "aug_spmmv_kernel": ["kpm_sweep.h", "kpm_sweep_c128_large.hip", "kpm_sweep_c64_large.hip"],
+}
+
+
+def kernel_source_sha(kernel: str) -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[kernel]:
+        h.update(open(os.path.join(CSRC, f), "rb").read())
+    return h.hexdigest()
 
 
 def log(msg: str):
@@ -55,13 +66,13 @@ def sweep_flops(N, R, nnzr=13, Fa=2, Fm=6):
     return R * N * (nnzr * (Fa + Fm) + math.ceil(7 * Fa / 2) + math.ceil(9 * Fm / 2))
 
 
-def traffic_record(bytes_per_sweep):
-    """HBM bytes per sweep from the committed rocprofv3 counters, if they match this kernel source."""
+def traffic_record(kernel: str, workload: str):
+    """Calibrated HBM bytes per launch from the committed rocprofv3 counters, or None when the
+    counters were taken on another kernel source or workload."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
-    rec = json.load(open(TRAFFIC_FILE))
-    sha = hashlib.sha256(open(SWEEP_SOURCE, "rb").read()).hexdigest()
-    if rec.get("source_sha256") != sha:
+    rec = json.load(open(TRAFFIC_FILE)).get(f"{kernel}:{workload}")
+    if not rec or rec.get("source_sha256") != kernel_source_sha(kernel):
         return None
     return rec.get("hbm_bytes_per_launch")
 
@@ -159,7 +170,8 @@ def main():
     E = torch.from_numpy((H.b + H.a * (-1.0 + (2.0 * np.arange(K) + 1.0) / K))).to(dev)
     mu = torch.empty((R, M), dtype=torch.float64, device=dev)
     rho = torch.empty(K, dtype=torch.float64, device=dev)
-    log(f"[bench] built H: N={N} a={H.a:.6f} b={H.b:.6f} ({build_s:.3f} s)")
+    sweep_kernel = kpm.sweep_kernel(H, R)
+    log(f"[bench] built H: N={N} a={H.a:.6f} b={H.b:.6f} ({build_s:.3f} s); sweep kernel {sweep_kernel}")
 
     if args.probe:
         probe(args, H, V0, M, R, Sd)
@@ -194,7 +206,10 @@ def main():
 
     sweeps_per_step = M // 2
     nnz = 13 * N
-    bps = sweep_bytes(N, nnz, R, Sd)
+    # the lattice kernel stores the matrix structure implicitly: no index bytes
+    Si = 0 if sweep_kernel == "lattice_kernel" else 4
+    bps = sweep_bytes(N, nnz, R, Sd, Si)
+    bps_crs = sweep_bytes(N, nnz, R, Sd, 4)
     fps = sweep_flops(N, R)
     value = bps * sweeps_per_step / (ms_per_step * 1e-3) / 1e9
     gflops = fps * sweeps_per_step / (ms_per_step * 1e-3) / 1e9
@@ -221,6 +236,7 @@ def main():
                         f"gamma={gamma}, R={R}, M={M}, {dtype}, Jackson DOS on {K} energies",
             "sweeps_per_step": sweeps_per_step,
             "bytes_per_sweep": bps,
+            "bytes_per_sweep_crs_model": bps_crs,
             "flops_per_sweep": fps,
         },
         "pct_hbm_peak": round(100.0 * value / HBM_PEAK_GBS, 2),
@@ -231,12 +247,12 @@ def main():
         "build_ms": round(build_s * 1e3, 1),
         "roofline": {
             "bound": "hbm",
-            "kernel": SWEEP_KERNEL,
+            "kernel": sweep_kernel,
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": traffic_record(bps),
+            "traffic": traffic_record(sweep_kernel, args.workload),
             "launches": n_sweeps,
             "avg_launch_ms": round(sweep_avg_ms, 5),
             "min_launch_ms": round(sweep_ms_min, 5),

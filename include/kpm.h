@@ -160,12 +160,19 @@ kpm_status kpm_dos(const double* mu, int32_t R, int32_t M, int32_t kernel, doubl
  *                between runs only to rounding.  Zero: static mapping
  *                (workgroup g takes range g % xcd_ways), bitwise
  *                reproducible; default 0
- *   prefetch     nonzero: before a wave streams its tiles it touches every
- *                line of their matrix rows and old W rows, so that the
- *                per-row loads hit L2; default 1
+ *   prefetch     generic sweep: before a wave streams its tiles it touches
+ *                every line of their matrix rows and old W rows; lattice
+ *                sweep: the matrix rows of a site arrive through one vector
+ *                load issued a step ahead instead of scalar loads; default 0
+ *   lattice      1 (default): at R = 32, on lattices with at least 128
+ *                4 x 4-site pencils, use the cache-blocked sweep that keeps a
+ *                ring of z-planes of V in LDS (of the other fields only
+ *                `prefetch` applies to it); 2: use it whenever R = 32; 0: the
+ *                generic gather sweep
  *   stream       bit 0: old-W loads, bit 1: new-W stores carry the
  *                non-temporal hint (W is touched once per sweep, unlike the
- *                V rows, which are gathered 13 times); default 0
+ *                V rows, which are gathered 13 times), so that L2 keeps the
+ *                planes of V that neighbouring tiles gather; default 3
  *   pencil       processing order of the lattice sites: pencils of
  *                pencil x pencil sites spanning the whole z extent, each
  *                walked plane by plane (x fastest), so that the rows a sweep
@@ -182,9 +189,15 @@ typedef struct {
     int32_t dynamic;
     int32_t prefetch;
     int32_t stream;
+    int32_t lattice;
 } kpm_sweep_tuning;
 kpm_status kpm_set_sweep_tuning(const kpm_sweep_tuning* tuning);
 kpm_status kpm_get_sweep_tuning(kpm_sweep_tuning* tuning);
+
+/* Which sweep kernel kpm_moments / kpm_aug_spmmv launch for H at block
+ * width R under the current tuning: *kernel = 0 generic gather sweep,
+ * 1 cache-blocked lattice sweep.  Errors: KPM_EINVAL. */
+kpm_status kpm_sweep_kernel(const kpm_hamiltonian* H, int32_t R, int32_t* kernel);
 
 /* Sweep-kernel timing for measurement tools.  While enabled (process-wide,
  * not thread-safe), every fused sweep launched by kpm_moments and

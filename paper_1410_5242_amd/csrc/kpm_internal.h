@@ -41,6 +41,7 @@ struct kpm_hamiltonian {
     void* val = nullptr;            // [N][width] complex (re, im) in dtype
     int32_t* col = nullptr;         // [N][width]
     int L[3] = {0, 0, 0};           // lattice sides
+    int periodic[3] = {0, 0, 0};
     int32_t* sched = nullptr;       // device [N/4]: sites in processing order (nullptr = natural)
     int sched_pencil = -1;          // pencil side the schedule was made for
     double a = 1.0, b = 0.0;        // Htilde = (H - b)/a
@@ -78,6 +79,24 @@ struct SweepArgs {
     int prefetch = 1;
     int stream = 0;
 };
+
+// Cache-blocked sweep for the library's lattice Hamiltonians at R = 32.
+struct LatticeArgs {
+    const void* val;
+    const void* V;
+    void* W;
+    double alpha, beta, gamma;
+    double* partials;   // this sweep's [grid][3][R] slot (FULL only)
+    int L[3];
+    int periodic[3];
+    int grid;
+    int prefetch;       // matrix rows through one vector load per site (a step ahead)
+    int stream;         // non-temporal hint: bit 0 old-W loads, bit 1 new-W stores
+};
+bool lattice_supported(const kpm_hamiltonian* H, int R);
+int lattice_tiles(const kpm_hamiltonian* H);
+int lattice_grid(const kpm_hamiltonian* H);
+hipError_t launch_lattice(int dtype, int variant, const LatticeArgs& a, hipStream_t s);
 
 kpm_sweep_tuning get_tuning();
 void set_tuning(const kpm_sweep_tuning& t);

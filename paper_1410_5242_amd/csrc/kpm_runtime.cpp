@@ -76,8 +76,21 @@ kpm_status ensure_vectors(kpm_hamiltonian* H, int R) {
     return KPM_OK;
 }
 
+// Grid of the sweep kernel that kpm_moments / kpm_aug_spmmv will launch.
+// The lattice kernel runs one workgroup per 4 x 4-site pencil; below about
+// half a workgroup per CU the generic sweep fills the machine better.
+bool use_lattice(const kpm_hamiltonian* H, int R) {
+    const int t = get_tuning().lattice;
+    if (t == 0 || !lattice_supported(H, R)) return false;
+    return t == 2 || lattice_tiles(H) >= 128;
+}
+
+int launch_grid(const kpm_hamiltonian* H, int R) {
+    return use_lattice(H, R) ? lattice_grid(H) : sweep_grid(H->dtype, R);
+}
+
 kpm_status ensure_partials(kpm_hamiltonian* H, int R, int slots) {
-    const int grid = sweep_grid(H->dtype, R);
+    const int grid = launch_grid(H, R);
     const size_t need = static_cast<size_t>(slots) * grid * 3 * R * sizeof(double);
     return grow(&H->ws.partials, &H->ws.pbytes, need, "hipMalloc(partials)");
 }
@@ -151,6 +164,32 @@ hipError_t launch_sweep_profiled(int dtype, int R, int variant, const SweepArgs&
     return hipSuccess;
 }
 
+// One fused sweep: the cache-blocked lattice kernel where it applies, the
+// generic gather kernel otherwise.
+hipError_t launch_any_sweep(kpm_hamiltonian* H, int R, int variant, const SweepArgs& a, hipStream_t s) {
+    if (use_lattice(H, R)) {
+        LatticeArgs la{H->val, a.V, a.W, a.alpha, a.beta, a.gamma, a.partials,
+                       {H->L[0], H->L[1], H->L[2]}, {H->periodic[0], H->periodic[1], H->periodic[2]}, a.grid,
+                       get_tuning().prefetch, get_tuning().stream};
+        if (!g_prof.on) return launch_lattice(H->dtype, variant, la, s);
+        if (g_prof.used == g_prof.start.size()) {
+            hipEvent_t e0, e1;
+            hipError_t e = hipEventCreate(&e0);
+            if (e != hipSuccess) return e;
+            if ((e = hipEventCreate(&e1)) != hipSuccess) return e;
+            g_prof.start.push_back(e0);
+            g_prof.stop.push_back(e1);
+        }
+        hipError_t e = hipEventRecord(g_prof.start[g_prof.used], s);
+        if (e != hipSuccess) return e;
+        if ((e = launch_lattice(H->dtype, variant, la, s)) != hipSuccess) return e;
+        if ((e = hipEventRecord(g_prof.stop[g_prof.used], s)) != hipSuccess) return e;
+        ++g_prof.used;
+        return hipSuccess;
+    }
+    return launch_sweep_profiled(H->dtype, R, variant, a, s);
+}
+
 }  // namespace
 
 void set_error(const std::string& msg) { g_error = msg; }
@@ -193,7 +232,10 @@ kpm_status kpm_build_hamiltonian(const kpm_lattice_desc* d, void* stream, kpm_ha
     hipStream_t s = static_cast<hipStream_t>(stream);
     H->dtype = d->dtype;
     H->nrows = 4 * nsite;
-    for (int j = 0; j < 3; ++j) H->L[j] = d->L[j];
+    for (int j = 0; j < 3; ++j) {
+        H->L[j] = d->L[j];
+        H->periodic[j] = d->periodic[j] ? 1 : 0;
+    }
     H->width = kWidth;
     if (hipGetDevice(&H->device) != hipSuccess) {
         delete H;
@@ -337,10 +379,10 @@ kpm_status kpm_aug_spmmv(const kpm_hamiltonian* Hc, const void* V, void* W, int3
     if ((st = ensure_queue(H)) != KPM_OK) return st;
     KPM_HIP(launch_zero_ints(H->ws.queue, kXcds, s), "zero kernel");
     SweepArgs a{H->val, H->col, H->nrows, V, W, H->sched, alpha, beta, gamma,
-                dots ? H->ws.partials : nullptr, sweep_grid(H->dtype, R)};
+                dots ? H->ws.partials : nullptr, launch_grid(H, R)};
     a.queue = H->ws.queue;
     const int launch_variant = (variant == KPM_FULL && !dots) ? KPM_NODOT : variant;
-    KPM_HIP(launch_sweep_profiled(H->dtype, R, launch_variant, a, s), "sweep kernel");
+    KPM_HIP(launch_any_sweep(H, R, launch_variant, a, s), "sweep kernel");
     if (dots) KPM_HIP(launch_reduce_partials(H->ws.partials, 1, a.grid, R, 0, eta, s), "reduce kernel");
     return KPM_OK;
 }
@@ -368,7 +410,7 @@ kpm_status kpm_moments(const kpm_hamiltonian* Hc, const void* V0, int32_t R, int
             return st;
         eta = H->ws.eta;
     }
-    const int grid = sweep_grid(H->dtype, R);
+    const int grid = launch_grid(H, R);
     const size_t slot_elems = static_cast<size_t>(grid) * 3 * R;
     const size_t bytes = static_cast<size_t>(H->nrows) * 2 * R * real_size(H->dtype);
     void* A = H->ws.vbuf[0];
@@ -391,7 +433,7 @@ kpm_status kpm_moments(const kpm_hamiltonian* Hc, const void* V0, int32_t R, int
             if (k % 2 == 1) { a.V = B; a.W = A; } else { a.V = A; a.W = B; }
             a.alpha = 2.0 * inv_a; a.beta = -2.0 * H->b * inv_a; a.gamma = -1.0;
         }
-        KPM_HIP(launch_sweep_profiled(H->dtype, R, KPM_FULL, a, s), "sweep kernel");
+        KPM_HIP(launch_any_sweep(H, R, KPM_FULL, a, s), "sweep kernel");
         if (sl == kReduceEvery - 1 || k == sweeps - 1)
             KPM_HIP(launch_reduce_partials(H->ws.partials, sl + 1, grid, R, k - sl, eta, s), "reduce kernel");
     }
@@ -424,11 +466,11 @@ kpm_status kpm_dos(const double* mu, int32_t R, int32_t M, int32_t kernel, doubl
 kpm_status kpm_set_sweep_tuning(const kpm_sweep_tuning* t) {
     g_error.clear();
     if (!t) {
-        set_tuning(kpm_sweep_tuning{0, kXcds, 8, 16, 0, 1, 0});
+        set_tuning(kpm_sweep_tuning{0, kXcds, 8, 16, 0, 0, 3, 1});
         return KPM_OK;
     }
     if (t->wg_per_cu < 0 || t->xcd_ways < 0 || t->chunk_tiles < 0 || t->pencil < 0 || t->dynamic < 0 ||
-        t->prefetch < 0 || t->stream < 0 || t->stream > 3)
+        t->prefetch < 0 || t->stream < 0 || t->stream > 3 || t->lattice < 0 || t->lattice > 2)
         return fail(KPM_EINVAL, "tuning fields must be >= 0");
     if (t->wg_per_cu > 64 || t->xcd_ways > 64 || t->chunk_tiles > (1 << 20))
         return fail(KPM_EINVAL, "tuning field out of range");
@@ -440,6 +482,13 @@ kpm_status kpm_get_sweep_tuning(kpm_sweep_tuning* t) {
     g_error.clear();
     if (!t) return fail(KPM_EINVAL, "tuning is NULL");
     *t = get_tuning();
+    return KPM_OK;
+}
+
+kpm_status kpm_sweep_kernel(const kpm_hamiltonian* Hc, int32_t R, int32_t* kernel) {
+    g_error.clear();
+    if (!Hc || !kernel) return fail(KPM_EINVAL, "H or kernel is NULL");
+    *kernel = use_lattice(Hc, R) ? 1 : 0;
     return KPM_OK;
 }
 

@@ -7,7 +7,6 @@
 namespace kpm {
 namespace {
 
-constexpr int kWaves = 4;
 
 // eta[sweep] from the partial sums of nslots consecutive sweeps, one
 // workgroup per sweep, each output summed over the workgroups in index order.
@@ -62,7 +61,7 @@ check_moments_kernel(const double* __restrict__ mu, int R, int M, int* __restric
 }  // namespace
 
 namespace {
-kpm_sweep_tuning g_tuning = {0, kXcds, 8, 16, 0, 1, 0};
+kpm_sweep_tuning g_tuning = {0, kXcds, 8, 16, 0, 0, 3, 1};
 }
 
 kpm_sweep_tuning get_tuning() { return g_tuning; }

@@ -37,7 +37,7 @@ class KPMError(RuntimeError):
 class SweepTuning(ctypes.Structure):
     _fields_ = [("wg_per_cu", ctypes.c_int32), ("xcd_ways", ctypes.c_int32), ("chunk_tiles", ctypes.c_int32),
                 ("pencil", ctypes.c_int32), ("dynamic", ctypes.c_int32), ("prefetch", ctypes.c_int32),
-                ("stream", ctypes.c_int32)]
+                ("stream", ctypes.c_int32), ("lattice", ctypes.c_int32)]
 
 
 class LatticeDesc(ctypes.Structure):
@@ -57,7 +57,7 @@ class LatticeDesc(ctypes.Structure):
 _LIB = None
 EXPORTS = ("kpm_build_hamiltonian", "kpm_hamiltonian_info", "kpm_export_csr",
            "kpm_destroy_hamiltonian", "kpm_aug_spmmv", "kpm_moments", "kpm_dos",
-           "kpm_set_sweep_tuning", "kpm_get_sweep_tuning", "kpm_sweep_profile_enable", "kpm_sweep_profile_read", "kpm_last_error", "kpm_version")
+           "kpm_set_sweep_tuning", "kpm_get_sweep_tuning", "kpm_sweep_kernel", "kpm_sweep_profile_enable", "kpm_sweep_profile_read", "kpm_last_error", "kpm_version")
 
 
 def lib():
@@ -89,6 +89,8 @@ def lib():
     L.kpm_set_sweep_tuning.argtypes = [ctypes.POINTER(SweepTuning)]
     L.kpm_get_sweep_tuning.restype = ctypes.c_int
     L.kpm_get_sweep_tuning.argtypes = [ctypes.POINTER(SweepTuning)]
+    L.kpm_sweep_kernel.restype = ctypes.c_int
+    L.kpm_sweep_kernel.argtypes = [vp, i32, ctypes.POINTER(i32)]
     L.kpm_sweep_profile_enable.restype = ctypes.c_int
     L.kpm_sweep_profile_enable.argtypes = [i32]
     L.kpm_sweep_profile_read.restype = ctypes.c_int
@@ -217,10 +219,10 @@ def dos(mu: torch.Tensor, a: float, b: float, E: torch.Tensor, kernel: str = "ja
 
 
 def set_sweep_tuning(wg_per_cu: int = 0, xcd_ways: int = 8, chunk_tiles: int = 8, pencil: int = 16,
-                     dynamic: int = 0, prefetch: int = 1, stream: int = 0):
+                     dynamic: int = 0, prefetch: int = 0, stream: int = 3, lattice: int = 1):
     """kpm_set_sweep_tuning: launch shape and site order of the sweep kernel (process-wide)."""
     _check(lib().kpm_set_sweep_tuning(ctypes.byref(SweepTuning(wg_per_cu, xcd_ways, chunk_tiles, pencil,
-                                                               dynamic, prefetch, stream))))
+                                                               dynamic, prefetch, stream, lattice))))
 
 
 def reset_sweep_tuning():
@@ -231,7 +233,15 @@ def get_sweep_tuning():
     t = SweepTuning()
     _check(lib().kpm_get_sweep_tuning(ctypes.byref(t)))
     return {"wg_per_cu": t.wg_per_cu, "xcd_ways": t.xcd_ways, "chunk_tiles": t.chunk_tiles, "pencil": t.pencil,
-            "dynamic": t.dynamic, "prefetch": t.prefetch, "stream": t.stream}
+            "dynamic": t.dynamic, "prefetch": t.prefetch, "stream": t.stream,
+            "lattice": t.lattice}
+
+
+def sweep_kernel(H: Hamiltonian, R: int) -> str:
+    """kpm_sweep_kernel: name of the sweep kernel used for H at block width R."""
+    k = ctypes.c_int32()
+    _check(lib().kpm_sweep_kernel(H.handle, int(R), ctypes.byref(k)))
+    return "lattice_kernel" if k.value == 1 else "aug_spmmv_kernel"
 
 
 def sweep_profile_enable(on: bool = True):

@@ -187,8 +187,10 @@ def test_moments_are_bitwise_deterministic_static_mapping():
 
 
 @pytest.mark.parametrize("tuning", [
-    dict(dynamic=1), dict(dynamic=1, chunk_tiles=1), dict(dynamic=0, prefetch=0),
-    dict(dynamic=0, pencil=0, xcd_ways=1, chunk_tiles=3), dict(wg_per_cu=2, dynamic=1, pencil=5),
+    dict(lattice=0, dynamic=1), dict(lattice=0, dynamic=1, chunk_tiles=1),
+    dict(lattice=0, dynamic=0, prefetch=0), dict(lattice=0, stream=3),
+    dict(lattice=0, dynamic=0, pencil=0, xcd_ways=1, chunk_tiles=3),
+    dict(lattice=0, wg_per_cu=2, dynamic=1, pencil=5), dict(lattice=2), dict(lattice=2, prefetch=0),
 ])
 def test_launch_shapes_agree(tuning):
     # the launch shape and site order change only the order of the FP64 sums
@@ -204,6 +206,67 @@ def test_launch_shapes_agree(tuning):
     finally:
         K.reset_sweep_tuning()
     assert np.abs(mu - ref).max() <= TOL_C128
+
+
+# --------------------------------------------------------------------------
+# the cache-blocked lattice sweep (R = 32): tile edges, ragged tiles, open sides
+# --------------------------------------------------------------------------
+LATTICE_GEOMETRIES = [
+    ((4, 4, 4), (1, 1, 1)), ((5, 7, 3), (1, 1, 1)), ((3, 3, 3), (1, 1, 1)),
+    ((6, 5, 4), (0, 1, 1)), ((4, 9, 5), (1, 0, 1)), ((8, 8, 6), (1, 1, 0)),
+    ((2, 3, 5), (0, 1, 1)), ((1, 1, 7), (0, 0, 1)), ((9, 4, 1), (1, 1, 0)), ((13, 6, 4), (0, 0, 0)),
+]
+
+
+@pytest.mark.parametrize("L,periodic", LATTICE_GEOMETRIES)
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_lattice_sweep_matches_oracle(L, periodic, dtype):
+    K = kpm()
+    M, R = 40, 32
+    say("lattice", L, periodic, dtype)
+    pot, Ho, a, b = oracle_problem(L, 1.5, 11, periodic=periodic)
+    v0 = inputs.phase_block(Ho.n, R, 12)
+    ref_eta = O.kpm_eta(Ho, a, b, v0, M)
+    ref = O.mu_from_eta(ref_eta)
+    try:
+        K.set_sweep_tuning(lattice=2)
+        mu, eta = gpu_moments(L, pot, v0, M, dtype=dtype, periodic=periodic, eta=True)
+        K.set_sweep_tuning(lattice=0)
+        mu_g, _ = gpu_moments(L, pot, v0, M, dtype=dtype, periodic=periodic)
+    finally:
+        K.reset_sweep_tuning()
+    tol = TOL_C128 if dtype == "c128" else TOL_C64
+    assert np.abs(mu - ref).max() <= tol
+    assert np.abs(mu - mu_g).max() <= (1e-13 if dtype == "c128" else 1e-6)
+    if dtype == "c128":
+        got_eta = eta[..., 0] + 1j * eta[..., 1]
+        assert np.abs(got_eta - ref_eta).max() <= TOL_C128
+
+
+def test_lattice_single_sweep_variants():
+    K = kpm()
+    L, R = (6, 5, 7), 32
+    pot, Ho, a, b = oracle_problem(L, 1.0, 13, periodic=(1, 0, 1))
+    Hd = Ho.dense()
+    H = K.build_hamiltonian(L, pot, periodic=(1, 0, 1))
+    rng = np.random.default_rng(5)
+    X = rng.standard_normal((Ho.n, R)) + 1j * rng.standard_normal((Ho.n, R))
+    Y = rng.standard_normal((Ho.n, R)) + 1j * rng.standard_normal((Ho.n, R))
+    Hx = Hd @ X
+    Vt = torch.from_numpy(X).cuda()
+    try:
+        K.set_sweep_tuning(lattice=2)
+        assert K.sweep_kernel(H, R) == "lattice_kernel"
+        Wt = torch.from_numpy(Y.copy()).cuda()
+        K.aug_spmmv(H, Vt, Wt, 1.0, 0.0, 0.0, variant="plain")
+        assert np.abs(Wt.cpu().numpy() - Hx).max() <= 1e-12 * np.abs(Hx).max()
+        Wt = torch.from_numpy(Y.copy()).cuda()
+        K.aug_spmmv(H, Vt, Wt, 0.3, -0.7, -1.0, variant="nodot")
+        ref = 0.3 * Hx - 0.7 * X - Y
+        assert np.abs(Wt.cpu().numpy() - ref).max() <= 1e-12 * np.abs(ref).max()
+    finally:
+        K.reset_sweep_tuning()
+    H.close()
 
 
 # --------------------------------------------------------------------------
