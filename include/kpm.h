@@ -208,6 +208,57 @@ kpm_status kpm_sweep_kernel(const kpm_hamiltonian* H, int32_t R, int32_t* kernel
 kpm_status kpm_sweep_profile_enable(int32_t enable);
 kpm_status kpm_sweep_profile_read(int64_t* count, double* total_ms, double* min_ms, double* max_ms);
 
+/* Batched moments: n_inst independent problems in one persistent launch.
+ * Instance i is exactly kpm_moments(H[i], V0[i], R, M) (section
+ * "Algorithm" / Alg. "kpm_improved_blocked" per instance; the paper's
+ * outlook combines loosely coupled outer iterations into one launch, here
+ * the independent disorder realisations and lattice sizes of a study):
+ * M/2 fused sweeps, the scalar products eta_0 .. eta_{M-1} and the doubling
+ * identity to mu_0 .. mu_{M-1}.  One workgroup owns one instance from the
+ * first sweep to its moments; instances are taken longest-first, so the
+ * result of an instance is bitwise independent of the batch it is in and
+ * of the tuning's mapping (it depends on `waves`, which fixes the order
+ * of the sums).
+ *   H:   host array [n_inst] of handles, all of one dtype, built on the
+ *        current device; the same handle may appear more than once.
+ *   V0:  host array [n_inst] of device start blocks [N_i][R] in that dtype
+ *        (read-only).
+ *   mu:  device [n_inst][R][M] doubles.
+ * R in {1, 2, 4, 8, 16, 32, 64}; M even and >= 2; per instance the block
+ * and the matrix arrays must each be smaller than 4 GiB.
+ * flags: KPM_BATCH_CHECK synchronises `stream` and returns KPM_ESPECTRUM if
+ * any instance has a moment that is non-finite or |mu_n| > mu_0 (1 + 1e-6);
+ * KPM_BATCH_GRAPH captures the launch sequence (counter reset and the
+ * persistent kernel) in a HIP graph and, while the next call repeats the
+ * same handles, start blocks, mu, R, M and tuning, replays it instead of
+ * re-uploading the instance table.
+ * Workspaces (two blocks per instance, the per-sweep products, the instance
+ * table) are library-owned, one set per device, shared by all calls: the
+ * call is not thread-safe, and calls on different streams must not overlap.
+ * Errors: KPM_EINVAL, KPM_ENOTSUP, KPM_ENOMEM, KPM_ESPECTRUM, KPM_EDEVICE. */
+enum { KPM_BATCH_CHECK = 1, KPM_BATCH_GRAPH = 2 };
+kpm_status kpm_moments_batched(const kpm_hamiltonian* const* H, const void* const* V0, int32_t n_inst,
+                               int32_t R, int32_t M, double* mu, int32_t flags, void* stream);
+
+/* Launch shape of the batched solver (process-wide, not thread-safe):
+ *   waves      waves per workgroup (4, 8 or 16, capped by what the
+ *              workgroup's LDS and registers allow: 16 in complex64, 8 in
+ *              complex128, fewer for R <= 2); 0 = 8 (or the cap if lower).
+ *              The order of the floating-point sums of a sweep depends on it.
+ *   wg_per_cu  workgroups per compute unit in the persistent grid; 0 = 1
+ *   dynamic    nonzero (default): workgroups take instances from the
+ *              longest-first list through an atomic counter (greedy
+ *              longest-processing-time); zero: workgroup g takes entries
+ *              g, g + grid, ... of that list.
+ * kpm_set_batch_tuning(NULL) restores the defaults.  Errors: KPM_EINVAL. */
+typedef struct {
+    int32_t waves;
+    int32_t wg_per_cu;
+    int32_t dynamic;
+} kpm_batch_tuning;
+kpm_status kpm_set_batch_tuning(const kpm_batch_tuning* tuning);
+kpm_status kpm_get_batch_tuning(kpm_batch_tuning* tuning);
+
 /* Thread-local message for the last failing call on this thread ("" if none). */
 const char* kpm_last_error(void);
 

@@ -1,0 +1,401 @@
+#pragma once
+// Batched persistent KPM solver: many independent Hamiltonians (disorder
+// realisations, lattices of different size) solved in one launch.
+//
+// Every instance is the whole iteration of Alg. "kpm_improved_blocked"
+// (M/2 fused sweeps, eta reduction, eta -> mu) for its own H and start
+// block.  Instances share nothing, so one workgroup owns one instance from
+// its first sweep to its moments and synchronises only with itself: the
+// only barrier between sweep k and sweep k + 1 is a workgroup barrier, and
+// the scalar products of a sweep are summed inside the workgroup in a fixed
+// order, so the result of an instance does not depend on which workgroup
+// ran it or on what else ran beside it.
+//
+// Work distribution: the host lists the instances longest-first; the
+// persistent grid takes them from that list through an atomic counter
+// (greedy longest-processing-time scheduling), or, without the counter,
+// workgroup g takes entries g, g + grid, ...
+//
+// Thread mapping (wave64): a lane owns CPL consecutive complex elements of
+// a block row (16 bytes where the block is wide enough), so a wave covers
+// 64 CPL / R block rows per pass.  The matrix rows of a pass (values and
+// column indices, contiguous in memory) are copied by the wave into its own
+// LDS slot with coalesced loads one pass ahead, and every lane then reads
+// the entries of its own row from LDS; the 13 neighbour rows of V are
+// gathered straight from memory.
+//
+// The pass body has no divergent branches, so that the compiler's count of
+// outstanding memory operations stays exact and a pass never waits for the
+// stores of the previous one: every access goes through a buffer resource
+// clipped to its array (reads past the end return zero, writes past it are
+// dropped), which makes the ragged last pass and the read-ahead past the
+// last pass safe without per-lane conditions, and a resource of size zero
+// switches off the old-W read of the first sweep.
+#include "kpm_internal.h"
+
+namespace kpm {
+namespace batch {
+
+constexpr int kLdsMax = 160 * 1024;
+
+// Waves per SIMD the register allocation must leave room for: complex128
+// keeps 13 gathered (re, im) pairs of doubles per row in flight per lane and
+// gets up to 256 registers (at most 8 waves per workgroup).
+template <typename T> constexpr int kMinWaves = sizeof(T) == 8 ? 2 : 4;
+template <typename T> constexpr int kMaxWaves = sizeof(T) == 8 ? 8 : 16;
+
+// A lane owns CPL consecutive complex elements of a block row, 16 bytes
+// where the block is wide enough: every vector memory instruction of the
+// sweep then moves 16 bytes per lane (the texture-address path, not HBM,
+// limits a gather-heavy sweep, and its cost is per lane and instruction).
+template <typename T, int R>
+constexpr int cpl() {
+    return (16 / (2 * static_cast<int>(sizeof(T)))) < R ? 16 / (2 * static_cast<int>(sizeof(T))) : R;
+}
+
+template <typename T, int R>
+struct Shape {
+    static constexpr int CPL = cpl<T, R>();                                 // complex per lane
+    static constexpr int LPR = R / CPL;                                      // lanes per row
+    static constexpr int RPW = 64 / LPR;                                     // rows per pass
+    static constexpr int kValWords = kWidth * 2 * static_cast<int>(sizeof(T)) / 4;   // per row
+    static constexpr int kV = RPW * kValWords;                              // value words per pass
+    static constexpr int kC = RPW * kWidth;                                 // column words per pass
+    // widest load (in words) that divides a part, so that every load of a
+    // pass is aligned (passes start at multiples of RPW rows)
+    static constexpr int kVecV = kV % 4 == 0 ? 4 : kV % 2 == 0 ? 2 : 1;
+    static constexpr int kVecC = kC % 4 == 0 ? 4 : kC % 2 == 0 ? 2 : 1;
+    static constexpr int kLoadsV = (kV / kVecV + 63) / 64;                   // loads per lane
+    static constexpr int kLoadsC = (kC / kVecC + 63) / 64;
+    // every lane loads and stores whole vectors: the parts are padded to
+    // multiples of 64 loads
+    static constexpr int kColOff = kLoadsV * 64 * kVecV;
+    static constexpr int kStageWords = kColOff + kLoadsC * 64 * kVecC;
+    // staging one pass ahead keeps the staged words live across the pass
+    static constexpr bool kAhead = kLoadsV * kVecV + kLoadsC * kVecC <= 16;
+};
+
+template <typename T, int R, int WAVES>
+constexpr int lds_bytes() {
+    using S = Shape<T, R>;
+    return WAVES * (S::kAhead ? 2 : 1) * S::kStageWords * 4 + 2 * WAVES * 3 * R * 8 + 16;
+}
+
+template <typename T, int R, int WAVES>
+constexpr bool instantiable() {
+    return lds_bytes<T, R, WAVES>() <= kLdsMax && WAVES <= kMaxWaves<T>;
+}
+
+template <int VW> struct Words;
+template <> struct Words<1> {
+    using type = int;
+    static __device__ type load(__amdgpu_buffer_rsrc_t rs, unsigned off) {
+        return static_cast<int>(__builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0));
+    }
+    static __device__ void store(type x, __amdgpu_buffer_rsrc_t rs, unsigned off) {
+        __builtin_amdgcn_raw_buffer_store_b32(static_cast<unsigned>(x), rs, off, 0, 0);
+    }
+};
+template <> struct Words<2> {
+    using type = int __attribute__((ext_vector_type(2)));
+    static __device__ type load(__amdgpu_buffer_rsrc_t rs, unsigned off) {
+        return __builtin_bit_cast(type, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0));
+    }
+    static __device__ void store(type x, __amdgpu_buffer_rsrc_t rs, unsigned off) {
+        __builtin_amdgcn_raw_buffer_store_b64(x, rs, off, 0, 0);
+    }
+};
+template <> struct Words<4> {
+    using type = int __attribute__((ext_vector_type(4)));
+    static __device__ type load(__amdgpu_buffer_rsrc_t rs, unsigned off) {
+        return __builtin_bit_cast(type, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
+    }
+    static __device__ void store(type x, __amdgpu_buffer_rsrc_t rs, unsigned off) {
+        __builtin_amdgcn_raw_buffer_store_b128(x, rs, off, 0, 0);
+    }
+};
+
+// Raw buffer resource over `bytes` bytes at p (at most 4 GiB - 1).
+__device__ inline __amdgpu_buffer_rsrc_t rsrc(const void* p, uint64_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, static_cast<int>(bytes), 0x00020000);
+}
+
+// CPL complex numbers of storage type T as (re, im, re, im, ...).
+template <typename T, int CPL>
+struct Lanes {
+    static constexpr int kWords = 2 * CPL * static_cast<int>(sizeof(T)) / 4;
+    using W = Words<kWords>;
+    using type = T __attribute__((ext_vector_type(2 * CPL)));
+    static __device__ type load(__amdgpu_buffer_rsrc_t rs, unsigned off) {
+        return __builtin_bit_cast(type, W::load(rs, off));
+    }
+    static __device__ void store(const type& x, __amdgpu_buffer_rsrc_t rs, unsigned off) {
+        W::store(__builtin_bit_cast(typename W::type, x), rs, off);
+    }
+};
+
+// Orders LDS writes of a wave before later LDS reads of other lanes of the
+// same wave (the LDS executes one wave's accesses in order; this only stops
+// the compiler from moving them).
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename T> struct Pair;
+template <> struct Pair<float> { using type = float __attribute__((ext_vector_type(2))); };
+template <> struct Pair<double> { using type = double __attribute__((ext_vector_type(2))); };
+
+template <typename T, int R, int WAVES>
+__global__ void __launch_bounds__(64 * WAVES, kMinWaves<T>)
+batched_kernel(const BatchInst* __restrict__ insts, const int32_t* __restrict__ order, int n_inst,
+               int* __restrict__ counter, int* __restrict__ flag, int M) {
+    using S = Shape<T, R>;
+    constexpr int CPL = S::CPL;
+    using LV = Lanes<T, CPL>;
+    using Cv = typename LV::type;
+    using P2 = typename Pair<T>::type;
+    using WV = Words<S::kVecV>;
+    using WC = Words<S::kVecC>;
+    constexpr int LPR = S::LPR;
+    constexpr int RPW = S::RPW;
+    constexpr int kVW = S::kValWords;
+    constexpr int kBufs = S::kAhead ? 2 : 1;
+    constexpr int kWpv = static_cast<int>(sizeof(T)) / 4;   // words per real
+    constexpr unsigned kCB = 2 * sizeof(T);                 // bytes per complex
+    __shared__ __attribute__((aligned(16))) int stage[WAVES][kBufs][S::kStageWords];
+    __shared__ double red[2][WAVES][3][R];
+    __shared__ int s_next;
+
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int sub = lane / LPR;          // block row within a pass
+    const int cc = lane % LPR;           // the lane's columns: cc * CPL + t, t < CPL
+    const int sweeps = M / 2;
+
+    for (int it = 0;; ++it) {
+        int idx;
+        if (counter) {
+            if (threadIdx.x == 0) s_next = atomicAdd(counter, 1);
+            __syncthreads();
+            idx = s_next;
+        } else {
+            idx = blockIdx.x + it * static_cast<int>(gridDim.x);
+        }
+        idx = __builtin_amdgcn_readfirstlane(idx);
+        if (idx >= n_inst) break;
+        const BatchInst d = insts[order[idx]];
+        const int64_t N = d.nrows;
+        const int64_t npass = (N + RPW - 1) / RPW;
+        const uint64_t vbytes = static_cast<uint64_t>(N) * R * kCB;
+        const __amdgpu_buffer_rsrc_t val_rs = rsrc(d.val, static_cast<uint64_t>(N) * kVW * 4);
+        const __amdgpu_buffer_rsrc_t col_rs = rsrc(d.col, static_cast<uint64_t>(N) * kWidth * 4);
+
+        // nu_0 -> a: the recurrence overwrites the block holding nu_{k-1}
+        {
+            const __amdgpu_buffer_rsrc_t src = rsrc(d.v0, vbytes);
+            const __amdgpu_buffer_rsrc_t dst = rsrc(d.a, vbytes);
+            const unsigned n16 = static_cast<unsigned>((vbytes + 15) / 16);
+            for (unsigned i = threadIdx.x; i < n16; i += 64 * WAVES)
+                Words<4>::store(Words<4>::load(src, 16 * i), dst, 16 * i);
+        }
+
+        // words of pass q's matrix rows (values, then column indices); lanes
+        // past the end of a part fetch words that are never read
+        auto fetch = [&](int64_t q, typename WV::type* wv, typename WC::type* wc) {
+            const unsigned pv = static_cast<unsigned>(q) * (S::kV * 4);
+            const unsigned pc = static_cast<unsigned>(q) * (S::kC * 4);
+#pragma unroll
+            for (int i = 0; i < S::kLoadsV; ++i)
+                wv[i] = WV::load(val_rs, pv + (lane + 64 * i) * (4 * S::kVecV));
+#pragma unroll
+            for (int i = 0; i < S::kLoadsC; ++i)
+                wc[i] = WC::load(col_rs, pc + (lane + 64 * i) * (4 * S::kVecC));
+        };
+        auto put = [&](int* dst, const typename WV::type* wv, const typename WC::type* wc) {
+#pragma unroll
+            for (int i = 0; i < S::kLoadsV; ++i)
+                *reinterpret_cast<typename WV::type*>(dst + (lane + 64 * i) * S::kVecV) = wv[i];
+#pragma unroll
+            for (int i = 0; i < S::kLoadsC; ++i)
+                *reinterpret_cast<typename WC::type*>(dst + S::kColOff + (lane + 64 * i) * S::kVecC) = wc[i];
+        };
+
+        for (int k = 0; k < sweeps; ++k) {
+            // k = 0: nu_1 = Htilde nu_0 into b; k >= 1: the block holding
+            // nu_{k-1} is overwritten by nu_{k+1} = 2 Htilde nu_k - nu_{k-1}
+            const void* V = (k & 1) ? d.b : d.a;
+            void* W = (k & 1) ? d.a : d.b;
+            const T alpha = static_cast<T>(k == 0 ? d.inv_a : 2.0 * d.inv_a);
+            const T beta = static_cast<T>(k == 0 ? -d.shift : -2.0 * d.shift);
+            const __amdgpu_buffer_rsrc_t vrs = rsrc(V, vbytes);
+            const __amdgpu_buffer_rsrc_t wrs = rsrc(W, vbytes);
+            const __amdgpu_buffer_rsrc_t wold_rs = rsrc(W, k == 0 ? 0 : vbytes);   // zeros in sweep 0
+            double ae[CPL], aor[CPL], aoi[CPL];
+#pragma unroll
+            for (int t = 0; t < CPL; ++t) ae[t] = aor[t] = aoi[t] = 0.0;
+            typename WV::type wv[S::kLoadsV];
+            typename WC::type wc[S::kLoadsC];
+            int buf = 0;
+            if constexpr (S::kAhead) {
+                fetch(wave, wv, wc);
+                put(stage[wave][0], wv, wc);
+            }
+            for (int64_t q = wave; q < npass; q += WAVES) {
+                if constexpr (!S::kAhead) {
+                    wave_sync();   // every lane has read the slot before it is refilled
+                    fetch(q, wv, wc);
+                    put(stage[wave][0], wv, wc);
+                }
+                wave_sync();
+                const int* st = stage[wave][buf];
+                // gathers of the 13 neighbour rows
+                Cv v[kWidth];
+#pragma unroll
+                for (int j = 0; j < kWidth; ++j) {
+                    const unsigned c = static_cast<unsigned>(st[S::kColOff + sub * kWidth + j]);
+                    v[j] = LV::load(vrs, (c * R + cc * CPL) * kCB);
+                }
+                const int64_t row = q * RPW + sub;
+                const unsigned off = static_cast<unsigned>(row * R + cc * CPL) * kCB;
+                const Cv wo = LV::load(wold_rs, off);
+                // matrix rows of this wave's next pass (zeros past the end)
+                if constexpr (S::kAhead) fetch(q + WAVES, wv, wc);
+                const int* sv = st + sub * kVW;
+                Cv acc;
+#pragma unroll
+                for (int e = 0; e < 2 * CPL; ++e) acc[e] = T(0);
+#pragma unroll
+                for (int j = 0; j < kWidth; ++j) {
+                    // (re, im) of entry j: one 8- or 16-byte LDS read
+                    const P2 h = *reinterpret_cast<const P2*>(sv + 2 * j * kWpv);
+#pragma unroll
+                    for (int t = 0; t < CPL; ++t) {
+                        acc[2 * t] = fma(h.x, v[j][2 * t], acc[2 * t]);
+                        acc[2 * t] = fma(-h.y, v[j][2 * t + 1], acc[2 * t]);
+                        acc[2 * t + 1] = fma(h.x, v[j][2 * t + 1], acc[2 * t + 1]);
+                        acc[2 * t + 1] = fma(h.y, v[j][2 * t], acc[2 * t + 1]);
+                    }
+                }
+                // slot 0 is the diagonal: v[0] is V of this row
+                Cv wn;
+#pragma unroll
+                for (int e = 0; e < 2 * CPL; ++e) wn[e] = fma(alpha, acc[e], beta * v[0][e]) - wo[e];
+                // rows past N: the store is dropped, the products masked
+                LV::store(wn, wrs, off);
+                const bool act = row < N;
+#pragma unroll
+                for (int t = 0; t < CPL; ++t) {
+                    const double vr = act ? static_cast<double>(v[0][2 * t]) : 0.0;
+                    const double vi = act ? static_cast<double>(v[0][2 * t + 1]) : 0.0;
+                    const double wr = wn[2 * t], wi = wn[2 * t + 1];
+                    ae[t] = fma(vr, vr, fma(vi, vi, ae[t]));
+                    aor[t] = fma(wr, vr, fma(wi, vi, aor[t]));
+                    aoi[t] = fma(wr, vi, fma(-wi, vr, aoi[t]));
+                }
+                if constexpr (S::kAhead) {
+                    put(stage[wave][buf ^ 1], wv, wc);
+                    buf ^= 1;
+                }
+            }
+            // lanes cc, cc + LPR, ... of a wave hold the same columns
+#pragma unroll
+            for (int t = 0; t < CPL; ++t) {
+#pragma unroll
+                for (int o = LPR; o < 64; o <<= 1) {
+                    ae[t] += __shfl_xor(ae[t], o);
+                    aor[t] += __shfl_xor(aor[t], o);
+                    aoi[t] += __shfl_xor(aoi[t], o);
+                }
+                if (sub == 0) {
+                    red[k & 1][wave][0][cc * CPL + t] = ae[t];
+                    red[k & 1][wave][1][cc * CPL + t] = aor[t];
+                    red[k & 1][wave][2][cc * CPL + t] = aoi[t];
+                }
+            }
+            // all of W is written (it is the next sweep's V) and red is full
+            __syncthreads();
+            if (threadIdx.x < 3 * R) {
+                const int qq = threadIdx.x / R, r = threadIdx.x % R;
+                double sum = 0.0;
+#pragma unroll
+                for (int wvi = 0; wvi < WAVES; ++wvi) sum += red[k & 1][wvi][qq][r];
+                d.eta[(static_cast<int64_t>(k) * 3 + qq) * R + r] = sum;
+            }
+        }
+        __syncthreads();   // eta of every sweep is visible to the workgroup
+        // mu_0 = eta_0, mu_1 = Re eta_1, mu_{2m} = 2 eta_{2m} - mu_0,
+        // mu_{2m+1} = 2 Re eta_{2m+1} - mu_1
+        int bad = 0;
+        for (int i = threadIdx.x; i < R * M; i += 64 * WAVES) {
+            const int r = i / M, n = i % M;
+            const double mu0 = d.eta[r];
+            const double ref = d.eta[(n & 1) * R + r];
+            const double x = 2.0 * d.eta[(static_cast<int64_t>(n >> 1) * 3 + (n & 1)) * R + r] - ref;
+            d.mu[i] = x;
+            if (!isfinite(x) || fabs(x) > mu0 * (1.0 + 1e-6) + 1e-300) bad = 1;
+        }
+        if (bad) flag[0] = 1;
+        __syncthreads();   // the grab slot and LDS are free for the next instance
+    }
+}
+
+template <typename T, int R, int WAVES>
+hipError_t launch_waves(const BatchArgs& a, hipStream_t s) {
+    if constexpr (instantiable<T, R, WAVES>()) {
+        batched_kernel<T, R, WAVES><<<a.grid, 64 * WAVES, 0, s>>>(a.inst, a.order, a.n_inst,
+                                                                  a.dynamic ? a.counter : nullptr, a.flag, a.M);
+        return hipGetLastError();
+    } else {
+        return hipErrorInvalidValue;
+    }
+}
+
+template <typename T, int R>
+hipError_t launch_r(const BatchArgs& a, hipStream_t s) {
+    switch (a.waves) {
+    case 4: return launch_waves<T, R, 4>(a, s);
+    case 8: return launch_waves<T, R, 8>(a, s);
+    case 16: return launch_waves<T, R, 16>(a, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t launch_dtype(int R, const BatchArgs& a, hipStream_t s) {
+    switch (R) {
+    case 1: return launch_r<T, 1>(a, s);
+    case 2: return launch_r<T, 2>(a, s);
+    case 4: return launch_r<T, 4>(a, s);
+    case 8: return launch_r<T, 8>(a, s);
+    case 16: return launch_r<T, 16>(a, s);
+    case 32: return launch_r<T, 32>(a, s);
+    case 64: return launch_r<T, 64>(a, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+// Largest workgroup (4, 8 or 16 waves) that can be launched for this R, or
+// 0 if none.
+template <typename T, int R>
+int max_waves_r() {
+    return instantiable<T, R, 16>() ? 16 : instantiable<T, R, 8>() ? 8 : instantiable<T, R, 4>() ? 4 : 0;
+}
+
+template <typename T>
+int max_waves(int R) {
+    switch (R) {
+    case 1: return max_waves_r<T, 1>();
+    case 2: return max_waves_r<T, 2>();
+    case 4: return max_waves_r<T, 4>();
+    case 8: return max_waves_r<T, 8>();
+    case 16: return max_waves_r<T, 16>();
+    case 32: return max_waves_r<T, 32>();
+    case 64: return max_waves_r<T, 64>();
+    }
+    return 0;
+}
+
+}  // namespace batch
+}  // namespace kpm

@@ -98,6 +98,36 @@ int lattice_tiles(const kpm_hamiltonian* H);
 int lattice_grid(const kpm_hamiltonian* H);
 hipError_t launch_lattice(int dtype, int variant, const LatticeArgs& a, hipStream_t s);
 
+// One instance of the batched solver (device-side descriptor).
+struct BatchInst {
+    const void* val;        // H: [N][kWidth] complex, diagonal in slot 0
+    const int32_t* col;     // H: [N][kWidth]
+    const void* v0;         // start block [N][R] (read-only)
+    void* a;                // work blocks [N][R]
+    void* b;
+    double* eta;            // [M/2][3][R]: <v|v>, Re <w|v>, Im <w|v> per sweep
+    double* mu;             // [R][M] output
+    int64_t nrows;          // N
+    double inv_a;           // 1/a
+    double shift;           // b/a
+};
+
+struct BatchArgs {
+    const BatchInst* inst;  // [n_inst]
+    const int32_t* order;   // [n_inst] processing order (longest first)
+    int n_inst;
+    int* counter;           // zero before the launch (dynamic mapping)
+    int* flag;              // set to 1 when a moment leaves [-mu_0, mu_0]
+    int M;
+    int grid;
+    int waves;              // waves per workgroup: 4, 8 or 16
+    int dynamic;
+};
+hipError_t launch_batched(int dtype, int R, const BatchArgs& a, hipStream_t s);
+// Largest workgroup (in waves, <= 16) that can run this dtype and R.
+int batched_max_waves(int dtype, int R);
+int device_cus();
+
 kpm_sweep_tuning get_tuning();
 void set_tuning(const kpm_sweep_tuning& t);
 

@@ -6,7 +6,9 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <algorithm>
 #include <cstring>
+#include <numeric>
 #include <string>
 #include <vector>
 
@@ -188,6 +190,44 @@ hipError_t launch_any_sweep(kpm_hamiltonian* H, int R, int variant, const SweepA
         return hipSuccess;
     }
     return launch_sweep_profiled(H->dtype, R, variant, a, s);
+}
+
+// ---- batched solver: process-wide state, one set per device ----
+kpm_batch_tuning g_batch_tuning = {0, 0, 1};
+
+struct BatchState {
+    BatchInst* inst = nullptr;          // device instance table
+    size_t inst_bytes = 0;
+    int32_t* order = nullptr;           // device processing order
+    size_t order_bytes = 0;
+    int* ints = nullptr;                // device [0] instance counter, [1] spectrum flag
+    int* flag_host = nullptr;           // pinned mirror of ints[1]
+    void* vec = nullptr;                // two work blocks per instance
+    size_t vec_bytes = 0;
+    double* eta = nullptr;              // per instance [M/2][3][R]
+    size_t eta_bytes = 0;
+    hipStream_t capture = nullptr;      // private stream the graph is captured on
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    // what the captured graph was made for
+    std::vector<BatchInst> key_inst;
+    std::vector<int32_t> key_order;
+    int key_dtype = -1, key_R = 0, key_M = 0, key_grid = 0, key_waves = 0, key_dynamic = -1;
+};
+std::vector<BatchState> g_batch;
+
+void drop_graph(BatchState& b) {
+    if (b.exec) (void)hipGraphExecDestroy(b.exec);
+    if (b.graph) (void)hipGraphDestroy(b.graph);
+    b.exec = nullptr;
+    b.graph = nullptr;
+    b.key_inst.clear();
+    b.key_order.clear();
+}
+
+bool same_inst(const BatchInst& x, const BatchInst& y) {
+    return x.val == y.val && x.col == y.col && x.v0 == y.v0 && x.a == y.a && x.b == y.b && x.eta == y.eta &&
+           x.mu == y.mu && x.nrows == y.nrows && x.inv_a == y.inv_a && x.shift == y.shift;
 }
 
 }  // namespace
@@ -514,6 +554,156 @@ kpm_status kpm_sweep_profile_read(int64_t* count, double* total_ms, double* min_
     if (min_ms) *min_ms = lo;
     if (max_ms) *max_ms = hi;
     g_prof.used = 0;
+    return KPM_OK;
+}
+
+kpm_status kpm_set_batch_tuning(const kpm_batch_tuning* t) {
+    g_error.clear();
+    if (!t) {
+        g_batch_tuning = kpm_batch_tuning{0, 0, 1};
+        return KPM_OK;
+    }
+    if (t->waves != 0 && t->waves != 4 && t->waves != 8 && t->waves != 16)
+        return fail(KPM_EINVAL, "waves must be 0, 4, 8 or 16");
+    if (t->wg_per_cu < 0 || t->wg_per_cu > 16) return fail(KPM_EINVAL, "wg_per_cu must be in [0, 16]");
+    if (t->dynamic < 0) return fail(KPM_EINVAL, "dynamic must be >= 0");
+    g_batch_tuning = *t;
+    return KPM_OK;
+}
+
+kpm_status kpm_get_batch_tuning(kpm_batch_tuning* t) {
+    g_error.clear();
+    if (!t) return fail(KPM_EINVAL, "tuning is NULL");
+    *t = g_batch_tuning;
+    return KPM_OK;
+}
+
+kpm_status kpm_moments_batched(const kpm_hamiltonian* const* H, const void* const* V0, int32_t n_inst, int32_t R,
+                               int32_t M, double* mu, int32_t flags, void* stream) {
+    g_error.clear();
+    if (!H || !V0 || !mu) return fail(KPM_EINVAL, "H, V0 or mu is NULL");
+    if (n_inst <= 0) return fail(KPM_EINVAL, "n_inst must be positive");
+    if (!r_supported(R)) return fail(KPM_ENOTSUP, "R must be one of 1, 2, 4, 8, 16, 32, 64");
+    if (M < 2 || (M % 2) != 0) return fail(KPM_EINVAL, "M must be even and >= 2");
+    if ((flags & ~(KPM_BATCH_CHECK | KPM_BATCH_GRAPH)) != 0) return fail(KPM_EINVAL, "unknown flag");
+    if (static_cast<int64_t>(R) * M > (INT32_MAX / 2)) return fail(KPM_EINVAL, "R * M too large");
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(KPM_EDEVICE, "hipGetDevice failed");
+    int dtype = -1;
+    for (int i = 0; i < n_inst; ++i) {
+        if (!H[i] || !V0[i]) return fail(KPM_EINVAL, "H[i] or V0[i] is NULL (i = " + std::to_string(i) + ")");
+        if (H[i]->device != dev) return fail(KPM_EINVAL, "H[i] was built on another device");
+        if (i == 0) dtype = H[i]->dtype;
+        if (H[i]->dtype != dtype) return fail(KPM_EINVAL, "all instances must have one dtype");
+        const uint64_t pair = 2 * real_size(dtype);
+        const uint64_t n = static_cast<uint64_t>(H[i]->nrows);
+        // 32-bit buffer offsets, with room for the read-ahead past the last pass
+        const uint64_t lim = (1ull << 32) - (1ull << 24);
+        if (n * R * pair >= lim || n * kWidth * pair >= lim)
+            return fail(KPM_ENOTSUP, "an instance's vector block or matrix reaches 4 GiB");
+    }
+    if (static_cast<int>(g_batch.size()) <= dev) g_batch.resize(dev + 1);
+    BatchState& b = g_batch[dev];
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t rs = real_size(dtype);
+
+    // instance table: two work blocks and the sweep products per instance
+    std::vector<size_t> voff(n_inst);
+    size_t vtotal = 0;
+    for (int i = 0; i < n_inst; ++i) {
+        voff[i] = vtotal;
+        const size_t blk = (static_cast<size_t>(H[i]->nrows) * 2 * R * rs + 255) / 256 * 256;
+        vtotal += 2 * blk;
+    }
+    const size_t eta_per = static_cast<size_t>(M / 2) * 3 * R;
+    const size_t eta_total = eta_per * n_inst * sizeof(double);
+    const bool grows = vtotal > b.vec_bytes || eta_total > b.eta_bytes ||
+                       n_inst * sizeof(BatchInst) > b.inst_bytes || n_inst * sizeof(int32_t) > b.order_bytes;
+    if (grows) drop_graph(b);   // the captured graph points into the buffers being replaced
+    kpm_status st;
+    if ((st = grow(&b.vec, &b.vec_bytes, vtotal, "hipMalloc(batch blocks)")) != KPM_OK) return st;
+    if ((st = grow(&b.eta, &b.eta_bytes, eta_total, "hipMalloc(batch eta)")) != KPM_OK) return st;
+    if ((st = grow(&b.inst, &b.inst_bytes, n_inst * sizeof(BatchInst), "hipMalloc(batch table)")) != KPM_OK)
+        return st;
+    if ((st = grow(&b.order, &b.order_bytes, n_inst * sizeof(int32_t), "hipMalloc(batch order)")) != KPM_OK)
+        return st;
+    if (!b.ints) KPM_HIP(hipMalloc(&b.ints, 2 * sizeof(int)), "hipMalloc(batch flags)");
+    if (!b.flag_host) KPM_HIP(hipHostMalloc(&b.flag_host, sizeof(int)), "hipHostMalloc(batch flag)");
+
+    std::vector<BatchInst> inst(n_inst);
+    for (int i = 0; i < n_inst; ++i) {
+        const size_t blk = (static_cast<size_t>(H[i]->nrows) * 2 * R * rs + 255) / 256 * 256;
+        char* base = static_cast<char*>(b.vec) + voff[i];
+        inst[i] = BatchInst{H[i]->val, H[i]->col, V0[i], base, base + blk, b.eta + eta_per * i,
+                            mu + static_cast<size_t>(i) * R * M, H[i]->nrows, 1.0 / H[i]->a, H[i]->b / H[i]->a};
+    }
+    // longest first (greedy longest-processing-time order), ties by index
+    std::vector<int32_t> order(n_inst);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t x, int32_t y) { return H[x]->nrows > H[y]->nrows; });
+
+    const int max_w = batched_max_waves(dtype, R);
+    if (max_w == 0) return fail(KPM_EINTERNAL, "no batched kernel for this dtype and R");
+    // 8 waves (one workgroup per CU) by default: measured faster than 16 on
+    // the 512-instance family, whose sweep is bound by the texture-address path
+    int waves = g_batch_tuning.waves > 0 ? g_batch_tuning.waves : (max_w < 8 ? max_w : 8);
+    if (waves > max_w) waves = max_w;
+    const int per_cu = g_batch_tuning.wg_per_cu > 0 ? g_batch_tuning.wg_per_cu : 1;
+    int grid = device_cus() * per_cu;
+    if (grid > n_inst) grid = n_inst;
+    const int dynamic = g_batch_tuning.dynamic ? 1 : 0;
+    BatchArgs args{b.inst, b.order, n_inst, b.ints, b.ints + 1, M, grid, waves, dynamic};
+
+    const bool use_graph = (flags & KPM_BATCH_GRAPH) != 0;
+    bool hit = use_graph && b.exec && b.key_dtype == dtype && b.key_R == R && b.key_M == M &&
+               b.key_grid == grid && b.key_waves == waves && b.key_dynamic == dynamic &&
+               b.key_inst.size() == inst.size() && b.key_order == order;
+    for (size_t i = 0; hit && i < inst.size(); ++i) hit = same_inst(b.key_inst[i], inst[i]);
+
+    if (hit) {
+        KPM_HIP(hipGraphLaunch(b.exec, s), "hipGraphLaunch");
+    } else {
+        drop_graph(b);
+        KPM_HIP(hipMemcpyAsync(b.inst, inst.data(), n_inst * sizeof(BatchInst), hipMemcpyHostToDevice, s),
+                "copy instance table");
+        KPM_HIP(hipMemcpyAsync(b.order, order.data(), n_inst * sizeof(int32_t), hipMemcpyHostToDevice, s),
+                "copy instance order");
+        KPM_HIP(hipStreamSynchronize(s), "synchronise");   // the host tables are about to go away
+        if (use_graph) {
+            if (!b.capture) KPM_HIP(hipStreamCreateWithFlags(&b.capture, hipStreamNonBlocking), "hipStreamCreate");
+            KPM_HIP(hipStreamBeginCapture(b.capture, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+            hipError_t e1 = launch_zero_ints(b.ints, 2, b.capture);
+            hipError_t e2 = e1 == hipSuccess ? launch_batched(dtype, R, args, b.capture) : e1;
+            hipGraph_t g = nullptr;
+            hipError_t e3 = hipStreamEndCapture(b.capture, &g);
+            if (e2 != hipSuccess) {
+                if (g) (void)hipGraphDestroy(g);
+                return hip_fail(e2, "batched kernel (capture)");
+            }
+            if (e3 != hipSuccess) return hip_fail(e3, "hipStreamEndCapture");
+            b.graph = g;
+            KPM_HIP(hipGraphInstantiate(&b.exec, b.graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+            b.key_inst = inst;
+            b.key_order = order;
+            b.key_dtype = dtype;
+            b.key_R = R;
+            b.key_M = M;
+            b.key_grid = grid;
+            b.key_waves = waves;
+            b.key_dynamic = dynamic;
+            KPM_HIP(hipGraphLaunch(b.exec, s), "hipGraphLaunch");
+        } else {
+            KPM_HIP(launch_zero_ints(b.ints, 2, s), "zero kernel");
+            KPM_HIP(launch_batched(dtype, R, args, s), "batched kernel");
+        }
+    }
+    if (flags & KPM_BATCH_CHECK) {
+        KPM_HIP(hipMemcpyAsync(b.flag_host, b.ints + 1, sizeof(int), hipMemcpyDeviceToHost, s), "copy flag");
+        KPM_HIP(hipStreamSynchronize(s), "synchronise");
+        if (*b.flag_host)
+            return fail(KPM_ESPECTRUM, "moments left [-mu_0, mu_0] in at least one instance");
+    }
     return KPM_OK;
 }
 

@@ -67,20 +67,23 @@ kpm_sweep_tuning g_tuning = {0, kXcds, 8, 16, 0, 0, 3, 1};
 kpm_sweep_tuning get_tuning() { return g_tuning; }
 void set_tuning(const kpm_sweep_tuning& t) { g_tuning = t; }
 
+int device_cus() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    static int cached[64] = {0};
+    if (dev < 0 || dev >= 64) return 256;
+    if (!cached[dev]) {
+        hipDeviceProp_t p;
+        cached[dev] = hipGetDeviceProperties(&p, dev) == hipSuccess ? p.multiProcessorCount : 256;
+    }
+    return cached[dev];
+}
+
 int sweep_grid(int dtype, int R) {
     (void)dtype;
     (void)R;
-    static int cus = 0;
-    if (!cus) {
-        int dev = 0;
-        cus = 256;
-        if (hipGetDevice(&dev) == hipSuccess) {
-            hipDeviceProp_t p;
-            if (hipGetDeviceProperties(&p, dev) == hipSuccess) cus = p.multiProcessorCount;
-        }
-    }
     const int per_cu = g_tuning.wg_per_cu > 0 ? g_tuning.wg_per_cu : 8;   // 32 waves per CU
-    int g = cus * per_cu;
+    const int g = device_cus() * per_cu;
     return (g + kXcds - 1) / kXcds * kXcds;
 }
 

@@ -47,3 +47,21 @@ def phase_block(N: int, R: int, seed: int, dtype=np.complex128) -> np.ndarray:
 def lattice_sites(L) -> int:
     Lx, Ly, Lz = (int(v) for v in L)
     return Lx * Ly * Lz
+
+
+_BATCH_STREAM = 0x5EED_0003
+
+
+def instance_family(n: int, sides, gamma_max: float, seed: int):
+    """Recipe of a batch of independent disorder realisations.
+
+    Instance i gets a cubic side L_i drawn uniformly from `sides`, a disorder
+    strength gamma_i ~ U[0, gamma_max], and its own potential and start-block
+    seeds.  Returns a list of dicts (L, gamma, pot_seed, vec_seed).
+    """
+    rng = np.random.default_rng([int(seed), _BATCH_STREAM])
+    sides = np.asarray(list(sides), dtype=np.int64)
+    Ls = rng.choice(sides, size=n)
+    gammas = rng.uniform(0.0, gamma_max, size=n)
+    return [dict(L=(int(L), int(L), int(L)), gamma=float(g), pot_seed=int(seed) * 1_000_003 + i,
+                 vec_seed=int(seed) * 1_000_003 + n + i) for i, (L, g) in enumerate(zip(Ls, gammas))]

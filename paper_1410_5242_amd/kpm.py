@@ -40,6 +40,13 @@ class SweepTuning(ctypes.Structure):
                 ("stream", ctypes.c_int32), ("lattice", ctypes.c_int32)]
 
 
+class BatchTuning(ctypes.Structure):
+    _fields_ = [("waves", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32), ("dynamic", ctypes.c_int32)]
+
+
+BATCH_CHECK, BATCH_GRAPH = 1, 2
+
+
 class LatticeDesc(ctypes.Structure):
     _fields_ = [
         ("L", ctypes.c_int32 * 3),
@@ -57,7 +64,8 @@ class LatticeDesc(ctypes.Structure):
 _LIB = None
 EXPORTS = ("kpm_build_hamiltonian", "kpm_hamiltonian_info", "kpm_export_csr",
            "kpm_destroy_hamiltonian", "kpm_aug_spmmv", "kpm_moments", "kpm_dos",
-           "kpm_set_sweep_tuning", "kpm_get_sweep_tuning", "kpm_sweep_kernel", "kpm_sweep_profile_enable", "kpm_sweep_profile_read", "kpm_last_error", "kpm_version")
+           "kpm_set_sweep_tuning", "kpm_get_sweep_tuning", "kpm_sweep_kernel", "kpm_sweep_profile_enable", "kpm_sweep_profile_read", "kpm_moments_batched",
+           "kpm_set_batch_tuning", "kpm_get_batch_tuning", "kpm_last_error", "kpm_version")
 
 
 def lib():
@@ -96,6 +104,12 @@ def lib():
     L.kpm_sweep_profile_read.restype = ctypes.c_int
     L.kpm_sweep_profile_read.argtypes = [ctypes.POINTER(i64), ctypes.POINTER(dbl), ctypes.POINTER(dbl),
                                          ctypes.POINTER(dbl)]
+    L.kpm_moments_batched.restype = ctypes.c_int
+    L.kpm_moments_batched.argtypes = [vp, vp, i32, i32, i32, vp, i32, vp]
+    L.kpm_set_batch_tuning.restype = ctypes.c_int
+    L.kpm_set_batch_tuning.argtypes = [ctypes.POINTER(BatchTuning)]
+    L.kpm_get_batch_tuning.restype = ctypes.c_int
+    L.kpm_get_batch_tuning.argtypes = [ctypes.POINTER(BatchTuning)]
     L.kpm_last_error.restype = ctypes.c_char_p
     L.kpm_last_error.argtypes = []
     L.kpm_version.restype = ctypes.c_char_p
@@ -204,6 +218,42 @@ def moments(H: Hamiltonian, V0: torch.Tensor, M: int, mu: torch.Tensor | None = 
     _check(lib().kpm_moments(H.handle, _dptr(V0), R, int(M), _dptr(mu),
                              _dptr(eta) if eta is not None else None, 1 if check else 0, _stream(stream)))
     return mu
+
+
+def moments_batched(Hs, V0s, M: int, mu: torch.Tensor | None = None, check: bool = True,
+                    graph: bool = False, stream=None) -> torch.Tensor:
+    """kpm_moments_batched: mu[n_inst][R][M] (float64, device) for instances (Hs[i], V0s[i])."""
+    n = len(Hs)
+    if n == 0 or len(V0s) != n:
+        raise ValueError("need one start block per Hamiltonian")
+    R = V0s[0].shape[1]
+    for H, V0 in zip(Hs, V0s):
+        if V0.dim() != 2 or V0.shape[0] != H.N or V0.shape[1] != R:
+            raise ValueError("V0s[i] must be [N_i][R] with one R for all instances")
+        if V0.dtype != H.torch_dtype:
+            raise ValueError(f"V0s[i] must be {H.torch_dtype}")
+    if mu is None:
+        mu = torch.empty((n, R, M), dtype=torch.float64, device=V0s[0].device)
+    hs = (ctypes.c_void_p * n)(*[H.handle for H in Hs])
+    vs = (ctypes.c_void_p * n)(*[_dptr(V0).value for V0 in V0s])
+    flags = (BATCH_CHECK if check else 0) | (BATCH_GRAPH if graph else 0)
+    _check(lib().kpm_moments_batched(hs, vs, n, R, int(M), _dptr(mu), flags, _stream(stream)))
+    return mu
+
+
+def set_batch_tuning(waves: int = 0, wg_per_cu: int = 0, dynamic: int = 1):
+    """kpm_set_batch_tuning: launch shape of the batched solver (process-wide)."""
+    _check(lib().kpm_set_batch_tuning(ctypes.byref(BatchTuning(waves, wg_per_cu, dynamic))))
+
+
+def reset_batch_tuning():
+    _check(lib().kpm_set_batch_tuning(None))
+
+
+def get_batch_tuning():
+    t = BatchTuning()
+    _check(lib().kpm_get_batch_tuning(ctypes.byref(t)))
+    return {"waves": t.waves, "wg_per_cu": t.wg_per_cu, "dynamic": t.dynamic}
 
 
 def dos(mu: torch.Tensor, a: float, b: float, E: torch.Tensor, kernel: str = "jackson", kparam: float = 0.0,

@@ -1,0 +1,203 @@
+"""GPU parity of the batched persistent solver (kpm_moments_batched).
+
+Every instance of a batch must reproduce the CPU oracle's moments for its
+own Hamiltonian and start block (1e-12 in complex128, 1e-5 with complex64
+storage), whatever else is in the batch; with a fixed workgroup size the
+moments of an instance are bitwise independent of the batch composition,
+of the instance-to-workgroup mapping and of graph replay.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1410_5242_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL_C128 = 1e-12
+TOL_C64 = 1e-5
+
+
+def kpm():
+    from paper_1410_5242_amd import kpm as K
+    return K
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def device():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    yield torch.device("cuda:0")
+    kpm().reset_batch_tuning()
+
+
+# Uneven sizes: 108 .. 1008 rows, one open lattice, none a multiple of
+# every pass height.
+SHAPES = [((3, 3, 3), (1, 1, 1)), ((4, 4, 4), (1, 1, 1)), ((5, 4, 3), (1, 1, 1)),
+          ((6, 6, 7), (1, 1, 1)), ((3, 5, 4), (1, 0, 1)), ((4, 3, 6), (1, 1, 1))]
+
+
+def make_batch(shapes, R, dtype, seed0=10):
+    """Per instance: oracle CSR, scaling, start block (host) and the device problem."""
+    K = kpm()
+    out = []
+    for i, (L, per) in enumerate(shapes):
+        gamma = 0.5 + 0.7 * i
+        pot = inputs.potential(L, gamma, seed0 + i)
+        Ho = O.ti_hamiltonian(L, pot, periodic=per)
+        a, b = O.scaling(*O.gershgorin(Ho))
+        v0 = inputs.phase_block(Ho.n, R, seed0 + 100 + i)
+        H = K.build_hamiltonian(L, pot, periodic=per, dtype=dtype)
+        tdt = torch.complex128 if dtype == "c128" else torch.complex64
+        V0 = torch.from_numpy(v0.astype(np.complex128 if dtype == "c128" else np.complex64)).cuda().to(tdt)
+        out.append(dict(Ho=Ho, a=a, b=b, v0=v0, H=H, V0=V0))
+    return out
+
+
+def run(batch, M, **kw):
+    K = kpm()
+    mu = K.moments_batched([x["H"] for x in batch], [x["V0"] for x in batch], M, **kw)
+    torch.cuda.synchronize()
+    return mu.cpu().numpy()
+
+
+@pytest.mark.parametrize("R", [1, 2, 4, 8, 16, 32, 64])
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_batched_matches_oracle(R, dtype):
+    M = 48
+    say("batched vs oracle", dtype, "R", R)
+    batch = make_batch(SHAPES, R, dtype)
+    mu = run(batch, M)
+    tol = TOL_C128 if dtype == "c128" else TOL_C64
+    for i, x in enumerate(batch):
+        ref = O.kpm_moments(x["Ho"], x["a"], x["b"], x["v0"], M)
+        err = np.abs(mu[i] - ref).max()
+        assert err <= tol, (i, err)
+        assert np.abs(mu[i][:, 0] - np.sum(np.abs(x["v0"]) ** 2, axis=0)).max() <= (1e-14 if dtype == "c128" else 1e-6)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_batched_equals_single_instance_calls(dtype):
+    # the batched solver and kpm_moments compute the same moments; the
+    # order of the sums differs, so they agree to rounding
+    K = kpm()
+    R, M = 8, 64
+    say("batched vs kpm_moments", dtype)
+    batch = make_batch(SHAPES[:4], R, dtype)
+    mu = run(batch, M)
+    for i, x in enumerate(batch):
+        ref = K.moments(x["H"], x["V0"], M)
+        torch.cuda.synchronize()
+        assert np.abs(mu[i] - ref.cpu().numpy()).max() <= (1e-13 if dtype == "c128" else 1e-6)
+
+
+@pytest.mark.parametrize("waves", [4, 8, 16])
+def test_batched_result_independent_of_batch_and_mapping(waves):
+    K = kpm()
+    R, M = 8, 40
+    say("batched determinism, waves", waves)
+    batch = make_batch(SHAPES, R, "c64")
+    K.set_batch_tuning(waves=waves, wg_per_cu=1, dynamic=1)
+    full = run(batch, M)
+    # each instance alone
+    for i in range(len(batch)):
+        alone = run([batch[i]], M)
+        assert np.array_equal(alone[0], full[i]), i
+    # other mappings: static, several workgroups per CU, reversed batch order
+    K.set_batch_tuning(waves=waves, wg_per_cu=2, dynamic=0)
+    assert np.array_equal(run(batch, M), full)
+    rev = run(batch[::-1], M)
+    assert np.array_equal(rev[::-1], full)
+    K.reset_batch_tuning()
+
+
+def test_batched_same_handle_repeated_and_many_instances():
+    # 300 instances (more than one per CU) that share four Hamiltonians
+    K = kpm()
+    R, M = 4, 32
+    say("batched many instances")
+    base = make_batch(SHAPES[:4], R, "c128")
+    gen = np.random.default_rng(5)
+    picks = gen.integers(0, 4, size=300)
+    Hs = [base[p]["H"] for p in picks]
+    V0s = [base[p]["V0"] for p in picks]
+    mu = K.moments_batched(Hs, V0s, M)
+    torch.cuda.synchronize()
+    mu = mu.cpu().numpy()
+    refs = [O.kpm_moments(x["Ho"], x["a"], x["b"], x["v0"], M) for x in base]
+    for i, p in enumerate(picks):
+        assert np.abs(mu[i] - refs[p]).max() <= TOL_C128
+
+
+def test_batched_graph_replay():
+    # replays interleaved with eager work; each replay must equal the eager
+    # result, and a replay must see new contents of the same start blocks
+    K = kpm()
+    R, M = 8, 64
+    say("batched graph replay")
+    batch = make_batch(SHAPES, R, "c64")
+    eager = run(batch, M)
+    Hs = [x["H"] for x in batch]
+    V0s = [x["V0"] for x in batch]
+    mu = torch.empty((len(batch), R, M), dtype=torch.float64, device="cuda")
+    for rep in range(4):
+        K.moments_batched(Hs, V0s, M, mu=mu, graph=True)
+        torch.cuda.synchronize()
+        assert np.array_equal(mu.cpu().numpy(), eager), rep
+        # unrelated eager work between replays
+        scratch = torch.randn(1 << 20, device="cuda")
+        (scratch * 2.0).sum().item()
+        run(batch[:2], M)
+    # same pointers, new start-block contents: the replay picks them up
+    for x in batch:
+        x["V0"].mul_(-1j)
+    K.moments_batched(Hs, V0s, M, mu=mu, graph=True)
+    torch.cuda.synchronize()
+    # multiplying every start vector by a phase leaves the moments unchanged
+    assert np.abs(mu.cpu().numpy() - eager).max() <= 1e-6
+    for x in batch:
+        x["V0"].mul_(0.5)
+    K.moments_batched(Hs, V0s, M, mu=mu, graph=True)
+    torch.cuda.synchronize()
+    assert np.abs(mu.cpu().numpy() - 0.25 * eager).max() <= 1e-6
+
+
+def test_batched_spectrum_check_and_errors():
+    K = kpm()
+    R, M = 4, 64
+    say("batched errors")
+    batch = make_batch(SHAPES[:2], R, "c128")
+    # a fixed scale far below the spectral radius: the recurrence grows
+    L, per = SHAPES[0]
+    pot = inputs.potential(L, 1.0, 1)
+    bad = K.build_hamiltonian(L, pot, periodic=per, dtype="c128", fixed_scale=(1.0, 0.0))
+    V0 = torch.from_numpy(inputs.phase_block(bad.N, R, 3)).cuda()
+    with pytest.raises(K.KPMError) as e:
+        K.moments_batched([batch[0]["H"], bad], [batch[0]["V0"], V0], M)
+    assert e.value.status == K.KPM_ESPECTRUM
+    # mixed storage precisions
+    other = make_batch(SHAPES[:1], R, "c64")
+    with pytest.raises(K.KPMError) as e:
+        K.moments_batched([batch[0]["H"], other[0]["H"]], [batch[0]["V0"], other[0]["V0"]], M)
+    assert e.value.status == K.KPM_EINVAL
+    # odd M, unsupported R
+    with pytest.raises(K.KPMError) as e:
+        K.moments_batched([batch[0]["H"]], [batch[0]["V0"]], 7)
+    assert e.value.status == K.KPM_EINVAL
+    v3 = torch.zeros((batch[0]["H"].N, 3), dtype=torch.complex128, device="cuda")
+    with pytest.raises(K.KPMError) as e:
+        K.moments_batched([batch[0]["H"]], [v3], M)
+    assert e.value.status == K.KPM_ENOTSUP
+    # the library stays usable
+    mu = run(batch, M)
+    ref = O.kpm_moments(batch[1]["Ho"], batch[1]["a"], batch[1]["b"], batch[1]["v0"], M)
+    assert np.abs(mu[1] - ref).max() <= TOL_C128
