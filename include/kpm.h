@@ -259,6 +259,56 @@ typedef struct {
 kpm_status kpm_set_batch_tuning(const kpm_batch_tuning* tuning);
 kpm_status kpm_get_batch_tuning(kpm_batch_tuning* tuning);
 
+/* ---- Learned DOS reconstruction (a small MLP; not part of the paper) ----
+ * Network, for one sample x of n_in features (the first n_in - 1 Chebyshev
+ * moments of the stochastic average plus the disorder strength):
+ *   h1 = gelu(x W1 + b1), h2 = gelu(h1 W2 + b2), h3 = gelu(h2 W3 + b3)
+ *   q = softmax(h3 W4 + b4)           n_out DOS masses on a fixed energy grid
+ *   e = softplus(h3 w5 + b5)          predicted L1 error of q
+ * with gelu(x) = x Phi(x) (exact, erf form).  Training loss for a batch of B
+ * samples with target masses p (rows sum to 1) and error targets t:
+ *   L = (1/B) sum_b [ -sum_k p_bk log q_bk + lam (e_b - t_b)^2 ].
+ * All matrix products run on the matrix cores in BF16 with FP32
+ * accumulation (weights are BF16 copies of FP32 masters; activations are
+ * rounded to BF16 when stored); biases, softmax, loss and Adam are FP32.
+ * Parameter vectors on the host are FP32 in the order W1 [n_in][hidden],
+ * b1, W2 [hidden][hidden], b2, W3, b3, W4 [hidden][n_out], b4, w5 [hidden],
+ * b5 (row-major).  The network, its weights, Adam state and activations
+ * are library-owned device memory for batches up to max_batch.  Calls on
+ * one network must not overlap.  Errors: KPM_EINVAL (NULL, sizes out of
+ * range, non-finite parameters), KPM_ENOMEM, KPM_EDEVICE. */
+typedef struct kpm_mlp kpm_mlp;
+kpm_status kpm_mlp_create(int32_t n_in, int32_t hidden, int32_t n_out, int32_t max_batch, kpm_mlp** out);
+void       kpm_mlp_destroy(kpm_mlp* net);
+/* Number of parameters (floats) in the host parameter vector. */
+kpm_status kpm_mlp_param_count(const kpm_mlp* net, int64_t* count);
+/* Load parameters (host, FP32) and reset the Adam state.  Synchronous. */
+kpm_status kpm_mlp_set_params(kpm_mlp* net, const float* params);
+/* Copy the FP32 master parameters / the last computed gradients to the
+ * host (same order).  Synchronous. */
+kpm_status kpm_mlp_get_params(const kpm_mlp* net, float* params);
+kpm_status kpm_mlp_get_grads(const kpm_mlp* net, float* grads);
+/* Inference: x device [B][n_in] FP32 -> q device [B][n_out], e device [B]
+ * (either may be NULL).  1 <= B <= max_batch. */
+kpm_status kpm_mlp_forward(kpm_mlp* net, const float* x, int32_t B, float* q, float* e, void* stream);
+/* Forward and backward pass: gradients of L (kept on the device, see
+ * kpm_mlp_get_grads) for x [B][n_in], p [B][n_out], t [B] (device FP32;
+ * t NULL: each sample's error target is its own current L1 error
+ * sum_k |q_k - p_k|, treated as a constant); loss (device [1], may be NULL)
+ * receives L.  lam >= 0. */
+kpm_status kpm_mlp_backward(kpm_mlp* net, const float* x, const float* p, const float* t, int32_t B, float lam,
+                            float* loss, void* stream);
+/* One Adam step (bias-corrected) on the masters from the last gradients. */
+kpm_status kpm_mlp_adam_step(kpm_mlp* net, float lr, float beta1, float beta2, float eps, void* stream);
+/* kpm_mlp_backward followed by kpm_mlp_adam_step(lr, 0.9, 0.999, 1e-8). */
+kpm_status kpm_mlp_train_step(kpm_mlp* net, const float* x, const float* p, const float* t, int32_t B, float lam,
+                              float lr, float* loss, void* stream);
+/* The network's GEMM on its own: C [M][N] FP32 = op(A) op(B), BF16 bits in
+ * A (row-major [M][K], or [K][M] if trans_a) and B ([K][N], or [N][K] if
+ * trans_b), all device; not both transposed. */
+kpm_status kpm_mlp_gemm_bf16(const uint16_t* A, const uint16_t* B, int32_t M, int32_t N, int32_t K, int32_t trans_a,
+                             int32_t trans_b, float* C, void* stream);
+
 /* Thread-local message for the last failing call on this thread ("" if none). */
 const char* kpm_last_error(void);
 

@@ -1,0 +1,288 @@
+"""Autotuner for the launch shapes of the KPM kernels, with a JSON cache.
+
+The paper generates fully unrolled kernels per (C, R) and picks the best
+configuration for the hardware at hand (section "Performance Engineering",
+SELL-C-sigma and the block-vector width).  Here the kernels are compiled
+once for every supported block width, and what is left to choose at run
+time is their launch shape and the block width itself:
+
+* the fused sweep (``kpm_set_sweep_tuning``): grid size, die-aware tile
+  ranges, chunking, site order, non-temporal streams, and whether the
+  cache-blocked lattice kernel or the generic gather kernel runs;
+* the batched persistent solver (``kpm_set_batch_tuning``): workgroup size,
+  workgroups per CU, dynamic or static instance mapping;
+* the block width R for a given number of random vectors S (S/R passes of
+  kpm_moments at width R; the matrix is read once per pass and sweep).
+
+Candidates are timed on the caller's problem with HIP events around the
+library calls; every candidate produces the same moments up to the order of
+floating-point sums, so the choice never changes results beyond rounding.
+Winners are cached per (kernel, dtype, R, size bucket) in a JSON file and
+re-applied without timing on later runs.  Only host logic lives here.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+import time
+from dataclasses import dataclass, field
+
+DEFAULT_CACHE = os.environ.get(
+    "KPM_TUNING_CACHE", os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning", "mi355x.json"))
+
+DTYPE_NAMES = {0: "c128", 1: "c64"}
+
+SWEEP_FIELDS = ("wg_per_cu", "xcd_ways", "chunk_tiles", "pencil", "dynamic", "prefetch", "stream", "lattice")
+BATCH_FIELDS = ("waves", "wg_per_cu", "dynamic")
+
+
+def size_bucket(n: int) -> int:
+    """Rows rounded down to a power of two: problems within a factor of two share a tuning."""
+    return 1 << max(0, int(n).bit_length() - 1)
+
+
+def sweep_key(dtype: int, R: int, N: int, L=None) -> str:
+    lat = "x".join(str(int(v)) for v in L) if L is not None else "-"
+    return f"sweep:{DTYPE_NAMES[dtype]}:R{R}:N{size_bucket(N)}:L{lat}"
+
+
+def batch_key(dtype: int, R: int, n_inst: int, total_rows: int) -> str:
+    return f"batched:{DTYPE_NAMES[dtype]}:R{R}:n{size_bucket(n_inst)}:N{size_bucket(total_rows)}"
+
+
+def width_key(dtype: int, S: int, N: int) -> str:
+    return f"width:{DTYPE_NAMES[dtype]}:S{S}:N{size_bucket(N)}"
+
+
+def sweep_candidates(R: int, lattice_ok: bool) -> list[dict]:
+    """Launch shapes of the fused sweep worth timing at block width R."""
+    base = dict(wg_per_cu=0, xcd_ways=8, chunk_tiles=8, pencil=16, dynamic=0, prefetch=0, stream=3, lattice=0)
+    out = []
+    for wg in (4, 8):
+        for chunk in (4, 8, 16):
+            for pencil in (0, 16):
+                for stream in (0, 3):
+                    c = dict(base, wg_per_cu=wg, chunk_tiles=chunk, pencil=pencil, stream=stream)
+                    out.append(c)
+    if lattice_ok:
+        for prefetch in (0, 1):
+            for stream in (0, 1, 2, 3):
+                out.append(dict(base, lattice=2, prefetch=prefetch, stream=stream))
+    return out
+
+
+def batch_candidates(max_waves: int = 16) -> list[dict]:
+    out = []
+    for waves in (4, 8, 16):
+        if waves > max_waves:
+            continue
+        for per_cu in (1, 2, 4):
+            if waves * per_cu > 32:
+                continue
+            for dyn in (1, 0):
+                out.append(dict(waves=waves, wg_per_cu=per_cu, dynamic=dyn))
+    return out
+
+
+def block_widths(S: int, supported=(1, 2, 4, 8, 16, 32, 64)) -> list[int]:
+    """Block widths R that split S random vectors into whole passes."""
+    return [R for R in supported if R <= S and S % R == 0]
+
+
+@dataclass
+class Trial:
+    params: dict
+    seconds: float
+
+
+@dataclass
+class TuneResult:
+    key: str
+    best: dict
+    seconds: float
+    trials: list = field(default_factory=list)
+
+    def to_json(self) -> dict:
+        return {"best": self.best, "seconds": self.seconds,
+                "trials": [{"params": t.params, "seconds": t.seconds} for t in self.trials]}
+
+
+def pick_best(trials: list[Trial]) -> Trial:
+    """Fastest trial; ties go to the earlier candidate (the candidate lists start with the defaults)."""
+    if not trials:
+        raise ValueError("no trials")
+    best = trials[0]
+    for t in trials[1:]:
+        if t.seconds < best.seconds:
+            best = t
+    return best
+
+
+class TuningCache:
+    """JSON file of tuned launch shapes, keyed by sweep_key / batch_key / width_key."""
+
+    def __init__(self, path: str = DEFAULT_CACHE):
+        self.path = path
+        self.entries: dict = {}
+        if os.path.exists(path):
+            with open(path) as f:
+                data = json.load(f)
+            self.entries = data.get("entries", {})
+
+    def get(self, key: str):
+        e = self.entries.get(key)
+        return None if e is None else e["best"]
+
+    def put(self, result: TuneResult):
+        self.entries[result.key] = result.to_json()
+
+    def save(self):
+        os.makedirs(os.path.dirname(self.path) or ".", exist_ok=True)
+        tmp = self.path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump({"format": 1, "entries": self.entries}, f, indent=1, sort_keys=True)
+        os.replace(tmp, self.path)
+
+
+def time_call(fn, repeats: int = 3, sync=None) -> float:
+    """Best wall time of `repeats` calls of fn() (after one warm-up), with `sync` after each."""
+    fn()
+    if sync:
+        sync()
+    best = math.inf
+    for _ in range(repeats):
+        t0 = time.perf_counter()
+        fn()
+        if sync:
+            sync()
+        best = min(best, time.perf_counter() - t0)
+    return best
+
+
+# --------------------------------------------------------------------------
+# GPU-side tuning (needs the library and a device)
+# --------------------------------------------------------------------------
+def _gpu_timer():
+    import torch
+
+    def timed(fn, repeats=3):
+        fn()
+        torch.cuda.synchronize()
+        best = math.inf
+        for _ in range(repeats):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            best = min(best, e0.elapsed_time(e1) * 1e-3)
+        return best
+    return timed
+
+
+def tune_sweep(H, R: int, cache: TuningCache | None = None, sweeps: int = 8, candidates=None,
+               repeats: int = 3, L=None) -> TuneResult:
+    """Time the fused sweep of H at block width R under each candidate launch shape."""
+    import torch
+    from . import kpm as K
+
+    timed = _gpu_timer()
+    V = torch.zeros((H.N, R), dtype=H.torch_dtype, device="cuda")
+    W = torch.zeros_like(V)
+    V[:, :] = 1.0 / math.sqrt(H.N)
+    eta = torch.zeros((2, R, 2), dtype=torch.float64, device="cuda")
+    saved = K.get_sweep_tuning()
+    trials = []
+    try:
+        if candidates is None:
+            K.set_sweep_tuning(lattice=2)
+            candidates = sweep_candidates(R, K.sweep_kernel(H, R) == "lattice_kernel")
+        for c in candidates:
+            K.set_sweep_tuning(**c)
+
+            def run():
+                for _ in range(sweeps):
+                    K.aug_spmmv(H, V, W, 2.0 / H.a, -2.0 * H.b / H.a, -1.0, "full", eta)
+            trials.append(Trial(dict(c), timed(run, repeats) / sweeps))
+    finally:
+        K.set_sweep_tuning(**saved)
+    best = pick_best(trials)
+    res = TuneResult(sweep_key(H.dtype, R, H.N, L), best.params, best.seconds, trials)
+    if cache is not None:
+        cache.put(res)
+    return res
+
+
+def tune_batched(Hs, V0s, M: int, cache: TuningCache | None = None, candidates=None,
+                 repeats: int = 2) -> TuneResult:
+    """Time kpm_moments_batched on the caller's batch under each candidate launch shape."""
+    import torch
+    from . import kpm as K
+
+    timed = _gpu_timer()
+    R = V0s[0].shape[1]
+    mu = torch.empty((len(Hs), R, M), dtype=torch.float64, device="cuda")
+    if candidates is None:
+        candidates = batch_candidates(8 if Hs[0].dtype == K.C128 else 16)
+    saved = K.get_batch_tuning()
+    trials = []
+    try:
+        for c in candidates:
+            K.set_batch_tuning(**c)
+            trials.append(Trial(dict(c), timed(lambda: K.moments_batched(Hs, V0s, M, mu=mu, check=False),
+                                               repeats)))
+    finally:
+        K.set_batch_tuning(**saved)
+    best = pick_best(trials)
+    res = TuneResult(batch_key(Hs[0].dtype, R, len(Hs), sum(H.N for H in Hs)), best.params, best.seconds,
+                     trials)
+    if cache is not None:
+        cache.put(res)
+    return res
+
+
+def tune_block_width(H, S: int, cache: TuningCache | None = None, sweeps: int = 8,
+                     repeats: int = 3) -> TuneResult:
+    """Block width R minimising the time per random vector for S vectors (S/R passes)."""
+    import torch
+    from . import kpm as K
+
+    timed = _gpu_timer()
+    trials = []
+    for R in block_widths(S):
+        V = torch.zeros((H.N, R), dtype=H.torch_dtype, device="cuda")
+        W = torch.zeros_like(V)
+        eta = torch.zeros((2, R, 2), dtype=torch.float64, device="cuda")
+
+        def run():
+            for _ in range(sweeps):
+                K.aug_spmmv(H, V, W, 2.0 / H.a, -2.0 * H.b / H.a, -1.0, "full", eta)
+        per_sweep = timed(run, repeats) / sweeps
+        trials.append(Trial({"R": R}, per_sweep * (S // R)))
+        del V, W
+    best = pick_best(trials)
+    res = TuneResult(width_key(H.dtype, S, H.N), best.params, best.seconds, trials)
+    if cache is not None:
+        cache.put(res)
+    return res
+
+
+def apply_sweep(cache: TuningCache, H, R: int, L=None) -> bool:
+    """Set the cached sweep tuning for (H, R); False if the cache has none."""
+    from . import kpm as K
+    best = cache.get(sweep_key(H.dtype, R, H.N, L))
+    if best is None:
+        return False
+    K.set_sweep_tuning(**{k: int(best[k]) for k in SWEEP_FIELDS})
+    return True
+
+
+def apply_batched(cache: TuningCache, Hs, R: int) -> bool:
+    from . import kpm as K
+    best = cache.get(batch_key(Hs[0].dtype, R, len(Hs), sum(H.N for H in Hs)))
+    if best is None:
+        return False
+    K.set_batch_tuning(**{k: int(best[k]) for k in BATCH_FIELDS})
+    return True

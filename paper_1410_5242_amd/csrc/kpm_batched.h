@@ -147,8 +147,17 @@ template <typename T> struct Pair;
 template <> struct Pair<float> { using type = float __attribute__((ext_vector_type(2))); };
 template <> struct Pair<double> { using type = double __attribute__((ext_vector_type(2))); };
 
+// Waves per SIMD to allocate registers for: kMinWaves<T>, or fewer where
+// the workgroup's LDS already limits the workgroups per CU.
 template <typename T, int R, int WAVES>
-__global__ void __launch_bounds__(64 * WAVES, kMinWaves<T>)
+constexpr int min_waves() {
+    const int wg_per_cu = kLdsMax / lds_bytes<T, R, WAVES>();
+    const int occ = wg_per_cu * WAVES / 4;
+    return occ < 1 ? 1 : (occ < kMinWaves<T> ? occ : kMinWaves<T>);
+}
+
+template <typename T, int R, int WAVES>
+__global__ void __launch_bounds__(64 * WAVES, (min_waves<T, R, WAVES>()))
 batched_kernel(const BatchInst* __restrict__ insts, const int32_t* __restrict__ order, int n_inst,
                int* __restrict__ counter, int* __restrict__ flag, int M) {
     using S = Shape<T, R>;

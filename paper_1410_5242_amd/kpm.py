@@ -65,7 +65,10 @@ _LIB = None
 EXPORTS = ("kpm_build_hamiltonian", "kpm_hamiltonian_info", "kpm_export_csr",
            "kpm_destroy_hamiltonian", "kpm_aug_spmmv", "kpm_moments", "kpm_dos",
            "kpm_set_sweep_tuning", "kpm_get_sweep_tuning", "kpm_sweep_kernel", "kpm_sweep_profile_enable", "kpm_sweep_profile_read", "kpm_moments_batched",
-           "kpm_set_batch_tuning", "kpm_get_batch_tuning", "kpm_last_error", "kpm_version")
+           "kpm_set_batch_tuning", "kpm_get_batch_tuning", "kpm_mlp_create", "kpm_mlp_destroy",
+           "kpm_mlp_param_count", "kpm_mlp_set_params", "kpm_mlp_get_params", "kpm_mlp_get_grads",
+           "kpm_mlp_forward", "kpm_mlp_backward", "kpm_mlp_adam_step", "kpm_mlp_train_step",
+           "kpm_mlp_gemm_bf16", "kpm_last_error", "kpm_version")
 
 
 def lib():
@@ -110,6 +113,26 @@ def lib():
     L.kpm_set_batch_tuning.argtypes = [ctypes.POINTER(BatchTuning)]
     L.kpm_get_batch_tuning.restype = ctypes.c_int
     L.kpm_get_batch_tuning.argtypes = [ctypes.POINTER(BatchTuning)]
+    flt = ctypes.c_float
+    L.kpm_mlp_create.restype = ctypes.c_int
+    L.kpm_mlp_create.argtypes = [i32, i32, i32, i32, ctypes.POINTER(vp)]
+    L.kpm_mlp_destroy.restype = None
+    L.kpm_mlp_destroy.argtypes = [vp]
+    L.kpm_mlp_param_count.restype = ctypes.c_int
+    L.kpm_mlp_param_count.argtypes = [vp, ctypes.POINTER(i64)]
+    for name in ("kpm_mlp_set_params", "kpm_mlp_get_params", "kpm_mlp_get_grads"):
+        getattr(L, name).restype = ctypes.c_int
+        getattr(L, name).argtypes = [vp, vp]
+    L.kpm_mlp_forward.restype = ctypes.c_int
+    L.kpm_mlp_forward.argtypes = [vp, vp, i32, vp, vp, vp]
+    L.kpm_mlp_backward.restype = ctypes.c_int
+    L.kpm_mlp_backward.argtypes = [vp, vp, vp, vp, i32, flt, vp, vp]
+    L.kpm_mlp_adam_step.restype = ctypes.c_int
+    L.kpm_mlp_adam_step.argtypes = [vp, flt, flt, flt, flt, vp]
+    L.kpm_mlp_train_step.restype = ctypes.c_int
+    L.kpm_mlp_train_step.argtypes = [vp, vp, vp, vp, i32, flt, flt, vp, vp]
+    L.kpm_mlp_gemm_bf16.restype = ctypes.c_int
+    L.kpm_mlp_gemm_bf16.argtypes = [vp, vp, i32, i32, i32, i32, i32, vp, vp]
     L.kpm_last_error.restype = ctypes.c_char_p
     L.kpm_last_error.argtypes = []
     L.kpm_version.restype = ctypes.c_char_p
@@ -304,6 +327,120 @@ def sweep_profile_read():
     n, tot, lo, hi = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
     _check(lib().kpm_sweep_profile_read(n, tot, lo, hi))
     return n.value, tot.value, lo.value, hi.value
+
+
+MLP_PARAM_ORDER = ("W1", "b1", "W2", "b2", "W3", "b3", "W4", "b4", "w5", "b5")
+
+
+def flatten_params(P: dict) -> np.ndarray:
+    """Parameter dict (W1 [n_in][H], b1, ..., w5 [H] or [H][1], b5) -> flat float32 vector."""
+    return np.concatenate([np.asarray(P[k], dtype=np.float64).reshape(-1) for k in MLP_PARAM_ORDER]).astype(np.float32)
+
+
+def unflatten_params(flat: np.ndarray, n_in: int, hidden: int, n_out: int) -> dict:
+    shapes = {"W1": (n_in, hidden), "b1": (hidden,), "W2": (hidden, hidden), "b2": (hidden,),
+              "W3": (hidden, hidden), "b3": (hidden,), "W4": (hidden, n_out), "b4": (n_out,),
+              "w5": (hidden, 1), "b5": (1,)}
+    out, o = {}, 0
+    for k in MLP_PARAM_ORDER:
+        n = int(np.prod(shapes[k]))
+        out[k] = np.asarray(flat[o:o + n], dtype=np.float64).reshape(shapes[k])
+        o += n
+    return out
+
+
+class MLP:
+    """Owning wrapper of a kpm_mlp network (learned DOS reconstruction)."""
+
+    def __init__(self, n_in: int = 129, hidden: int = 512, n_out: int = 512, max_batch: int = 1024):
+        h = ctypes.c_void_p()
+        _check(lib().kpm_mlp_create(int(n_in), int(hidden), int(n_out), int(max_batch), ctypes.byref(h)))
+        self.handle = h
+        self.n_in, self.hidden, self.n_out, self.max_batch = n_in, hidden, n_out, max_batch
+        c = ctypes.c_int64()
+        _check(lib().kpm_mlp_param_count(self.handle, ctypes.byref(c)))
+        self.param_count = c.value
+        self._loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+
+    def close(self):
+        if self.handle:
+            lib().kpm_mlp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, flat) -> None:
+        if isinstance(flat, dict):
+            flat = flatten_params(flat)
+        flat = np.ascontiguousarray(flat, dtype=np.float32)
+        if flat.size != self.param_count:
+            raise ValueError(f"expected {self.param_count} parameters")
+        _check(lib().kpm_mlp_set_params(self.handle, flat.ctypes.data))
+
+    def get_params(self) -> np.ndarray:
+        out = np.zeros(self.param_count, dtype=np.float32)
+        _check(lib().kpm_mlp_get_params(self.handle, out.ctypes.data))
+        return out
+
+    def get_grads(self) -> np.ndarray:
+        out = np.zeros(self.param_count, dtype=np.float32)
+        _check(lib().kpm_mlp_get_grads(self.handle, out.ctypes.data))
+        return out
+
+    def _x(self, x):
+        if x.dtype != torch.float32 or x.dim() != 2 or x.shape[1] != self.n_in:
+            raise ValueError(f"x must be float32 [B][{self.n_in}]")
+        return x
+
+    def forward(self, x: torch.Tensor, stream=None):
+        """(q [B][n_out], e [B]) on the device."""
+        x = self._x(x)
+        B = x.shape[0]
+        q = torch.empty((B, self.n_out), dtype=torch.float32, device=x.device)
+        e = torch.empty(B, dtype=torch.float32, device=x.device)
+        _check(lib().kpm_mlp_forward(self.handle, _dptr(x), B, _dptr(q), _dptr(e), _stream(stream)))
+        return q, e
+
+    def backward(self, x: torch.Tensor, p: torch.Tensor, t: torch.Tensor | None = None, lam: float = 1.0,
+                 stream=None) -> torch.Tensor:
+        x = self._x(x)
+        B = x.shape[0]
+        if p.dtype != torch.float32 or tuple(p.shape) != (B, self.n_out):
+            raise ValueError("p must be float32 [B][n_out]")
+        _check(lib().kpm_mlp_backward(self.handle, _dptr(x), _dptr(p), _dptr(t) if t is not None else None, B,
+                                      float(lam), _dptr(self._loss), _stream(stream)))
+        return self._loss
+
+    def adam_step(self, lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8,
+                  stream=None):
+        _check(lib().kpm_mlp_adam_step(self.handle, float(lr), float(beta1), float(beta2), float(eps),
+                                       _stream(stream)))
+
+    def train_step(self, x, p, t=None, lam: float = 1.0, lr: float = 1e-3, stream=None) -> torch.Tensor:
+        x = self._x(x)
+        B = x.shape[0]
+        _check(lib().kpm_mlp_train_step(self.handle, _dptr(x), _dptr(p), _dptr(t) if t is not None else None, B,
+                                        float(lam), float(lr), _dptr(self._loss), _stream(stream)))
+        return self._loss
+
+
+def gemm_bf16(A: torch.Tensor, B: torch.Tensor, trans_a: bool = False, trans_b: bool = False,
+              stream=None) -> torch.Tensor:
+    """kpm_mlp_gemm_bf16 on BF16 bit patterns (torch.int16 / uint16 / bfloat16 tensors)."""
+    if A.dtype == torch.bfloat16:
+        A = A.view(torch.int16)
+    if B.dtype == torch.bfloat16:
+        B = B.view(torch.int16)
+    M, K = (A.shape[1], A.shape[0]) if trans_a else (A.shape[0], A.shape[1])
+    N = B.shape[0] if trans_b else B.shape[1]
+    C = torch.empty((M, N), dtype=torch.float32, device=A.device)
+    _check(lib().kpm_mlp_gemm_bf16(_dptr(A), _dptr(B), M, N, K, int(trans_a), int(trans_b), _dptr(C),
+                                   _stream(stream)))
+    return C
 
 
 def version() -> str:
