@@ -102,6 +102,100 @@ def cpu_baseline(L, gamma, R, dtype, target_s=15.0):
                       f"{dt:.2f} s; Gflop/s {sweep_flops(Ho.n, R) * sweeps / dt / 1e9:.2f}"}
 
 
+def leg_precision(log_fn=None):
+    """128 x 128 x 64 lattice, gamma = 2, R = 32, M = 2000: complex64 storage with FP64 products
+    against complex128 on the same seed (moments error, DOS L1 error, speed)."""
+    import numpy as np
+    import torch
+    from paper_1410_5242_amd import inputs, kpm
+    L, gamma, R, M, K = (128, 128, 64), 2.0, 32, 2000, 4096
+    pot = inputs.potential(L, gamma, 0)
+    res = {"workload": f"TI {L[0]}x{L[1]}x{L[2]} periodic, gamma={gamma}, R={R}, M={M}, same potential and start "
+                       f"vectors (complex64 block = rounded complex128 block), Jackson DOS on {K} energies"}
+    mus, rhos, times = {}, {}, {}
+    a = b = None
+    for dt in ("c128", "c64"):
+        H = kpm.build_hamiltonian(L, pot, dtype=dt)
+        a, b = H.a, H.b
+        V0 = kpm.random_phase_block(H.N, R, 0, dt)
+        E = torch.from_numpy(H.b + H.a * (-1.0 + (2.0 * np.arange(K) + 1.0) / K)).cuda()
+        mu = kpm.moments(H, V0, M)
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record()
+        kpm.moments(H, V0, M, mu=mu)
+        rho = kpm.dos(mu, H.a, H.b, E)
+        ev[1].record()
+        torch.cuda.synchronize()
+        times[dt] = ev[0].elapsed_time(ev[1]) / 1e3
+        mus[dt], rhos[dt] = mu.cpu().numpy(), rho.cpu().numpy()
+        Sd = 16 if dt == "c128" else 8
+        bps = sweep_bytes(H.N, 13 * H.N, R, Sd, 0 if kpm.sweep_kernel(H, R) == "lattice_kernel" else 4)
+        res[dt] = {"seconds": round(times[dt], 4), "GBps": round(bps * (M // 2) / times[dt] / 1e9, 1),
+                   "sweep_kernel": kpm.sweep_kernel(H, R)}
+        H.close()
+        del V0
+    dE = 2.0 * a / K
+    d = np.abs(mus["c64"] - mus["c128"])
+    res["max_abs_mu_error"] = float(d.max())
+    res["mean_abs_mu_error"] = float(d.mean())
+    res["dos_l1_error"] = float(np.abs(rhos["c64"] - rhos["c128"]).sum() * dE)
+    res["stated_bound"] = {"max_abs_mu_error": 1e-5, "dos_l1_error": 1e-5}
+    res["within_bound"] = bool(res["max_abs_mu_error"] <= 1e-5 and res["dos_l1_error"] <= 1e-5)
+    res["speedup_c64"] = round(times["c128"] / times["c64"], 3)
+    return res
+
+
+def leg_batched():
+    """512 independent realisations, L in {12, 16, 20, 24}, gamma ~ U[0, 4], R = 8, M = 512, complex64:
+    one persistent launch (graph replay), throughput over all instance sweeps."""
+    import numpy as np
+    import torch
+    from paper_1410_5242_amd import autotune, inputs, kpm
+    n, R, M = 512, 8, 512
+    fam = inputs.instance_family(n, (12, 16, 20, 24), 4.0, 0)
+    t0 = time.perf_counter()
+    Hs = [kpm.build_hamiltonian(f["L"], inputs.potential(f["L"], f["gamma"], f["pot_seed"]), dtype="c64")
+          for f in fam]
+    V0s = [kpm.random_phase_block(H.N, R, f["vec_seed"], "c64") for f, H in zip(fam, Hs)]
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    cache = autotune.TuningCache()
+    tuned = autotune.apply_batched(cache, Hs, R)
+    mu = kpm.moments_batched(Hs, V0s, M, graph=True)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(3):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record()
+        kpm.moments_batched(Hs, V0s, M, mu=mu, check=False, graph=True)
+        ev[1].record()
+        torch.cuda.synchronize()
+        ts.append(ev[0].elapsed_time(ev[1]) / 1e3)
+    t = min(ts)
+    rows = sum(H.N for H in Hs)
+    bps = sum(sweep_bytes(H.N, 13 * H.N, R, 8) for H in Hs)
+    m = mu.cpu().numpy()
+    out = {"workload": f"{n} instances, L in {{12,16,20,24}} (sum N = {rows}), gamma ~ U[0,4], R={R}, M={M}, "
+                       f"complex64 + FP64 products, one persistent launch replayed from a HIP graph",
+           "seconds": round(t, 4), "build_s": round(build_s, 2),
+           "GBps": round(bps * (M // 2) / t / 1e9, 1), "pct_hbm_peak": round(100 * bps * (M // 2) / t / 1e9 / HBM_PEAK_GBS, 1),
+           "gflops": round(sum(sweep_flops(H.N, R) for H in Hs) * (M // 2) / t / 1e9, 1),
+           "bytes_per_all_instance_sweep": bps, "tuning": kpm.get_batch_tuning(), "autotuned": tuned,
+           "mu0_max_dev": float(np.abs(m[:, :, 0] - 1.0).max())}
+    kpm.reset_batch_tuning()
+    for H in Hs:
+        H.close()
+    return out
+
+
+def leg_time_to_dos():
+    from paper_1410_5242_amd import learned, time_to_dos
+    if not os.path.exists(learned.WEIGHTS):
+        return {"skipped": "no trained network weights at " + os.path.relpath(learned.WEIGHTS, ROOT)}
+    return time_to_dos.run(log=log)
+
+
 COPY_BYTES = 1 << 30
 
 
@@ -145,6 +239,9 @@ def main():
                     help="short run for hardware counters: a 1 GiB device copy (the calibration kernel "
                          "of known traffic) and --probe-sweeps fused sweeps of the workload")
     ap.add_argument("--probe-sweeps", type=int, default=8)
+    ap.add_argument("--legs", default="precision,batched,time_to_dos",
+                    help="extra measurements after the headline step: any of precision, batched, "
+                         "time_to_dos (comma separated), or none")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU sharding is a design, "
@@ -261,6 +358,14 @@ def main():
         },
     }
     H.close()
+    del V0
+    legs = [x for x in args.legs.split(",") if x and x != "none"]
+    for name, fn in (("precision", leg_precision), ("batched", leg_batched), ("time_to_dos", leg_time_to_dos)):
+        if name in legs:
+            log(f"[bench] leg {name}")
+            out[name] = fn()
+            torch.cuda.synchronize()
+            torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(L, gamma, R, dtype, args.cpu_target_s)

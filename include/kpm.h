@@ -144,6 +144,37 @@ kpm_status kpm_moments(const kpm_hamiltonian* H, const void* V0, int32_t R, int3
 kpm_status kpm_dos(const double* mu, int32_t R, int32_t M, int32_t kernel, double kparam,
                    double a, double b, const double* E, int32_t K, double* rho, void* stream);
 
+/* Random-phase start block for the stochastic trace (section "Problem
+ * Description"; the distribution of the random vectors is not fixed by the
+ * paper, this is the library's reading): V device [N][R] in dtype,
+ *   V[i][r] = exp(2 pi i u_ir) / sqrt(N),
+ * u_ir = (top 53 bits of SplitMix64 output) / 2^53 at counter c = i R + r:
+ * state key + (c + 1) * 0x9E3779B97F4A7C15 with key = mix(seed +
+ * 0x9E3779B97F4A7C15), mix the SplitMix64 finaliser (Steele, Lea, Flood,
+ * OOPSLA 2014).  Computed in FP64, rounded to the storage precision; every
+ * column has unit norm up to rounding.  Errors: KPM_EINVAL. */
+kpm_status kpm_random_phase_block(void* V, int64_t N, int32_t R, int32_t dtype, uint64_t seed, void* stream);
+
+/* kpm_dos for n_inst instances in one launch, from a prefix of their
+ * moments: instance i uses mu[i][r][n] = mu[(i R + r) ld + n] for n < M
+ * (ld >= M; a prefix of an M'-moment run equals an M-moment run with the
+ * same start vectors), the damping kernel for M moments and its own
+ * scaling a[i], b[i] (device arrays), on the shared energy grid E [K].
+ * masses = 0: rho [n_inst][K] is the density per unit energy; masses != 0:
+ * each row is divided by its sum (in index order), i.e. the DOS mass per
+ * bin of a uniform grid.  All pointers device.  n_inst <= 65535.
+ * Errors: KPM_EINVAL. */
+kpm_status kpm_dos_batched(const double* mu, int32_t n_inst, int32_t R, int32_t ld, int32_t M, int32_t kernel,
+                           double kparam, const double* a, const double* b, const double* E, int32_t K,
+                           int32_t masses, double* rho, void* stream);
+
+/* Input features of the learned reconstruction: x[i][f] = (1/R) sum_r
+ * mu[(i R + r) ld + f] (FP32) for f < n_mom (the stochastic trace of the
+ * first n_mom moments), then x[i][n_mom] = extra[i] when extra is non-NULL
+ * (e.g. the disorder strength).  All pointers device.  Errors: KPM_EINVAL. */
+kpm_status kpm_moment_features(const double* mu, int32_t n_inst, int32_t R, int32_t ld, int32_t n_mom,
+                               const float* extra, float* x, void* stream);
+
 /* Launch shape of the fused sweep kernel (process-wide, not thread-safe;
  * results do not depend on it beyond the order of floating-point sums):
  *   wg_per_cu    workgroups (of 4 waves) per compute unit in the persistent
@@ -160,10 +191,13 @@ kpm_status kpm_dos(const double* mu, int32_t R, int32_t M, int32_t kernel, doubl
  *                between runs only to rounding.  Zero: static mapping
  *                (workgroup g takes range g % xcd_ways), bitwise
  *                reproducible; default 0
- *   prefetch     generic sweep: before a wave streams its tiles it touches
- *                every line of their matrix rows and old W rows; lattice
- *                sweep: the matrix rows of a site arrive through one vector
- *                load issued a step ahead instead of scalar loads; default 0
+ *   prefetch     0, 1 or 2.  Generic sweep: 1 = before a wave streams its
+ *                tiles it touches every line of their matrix rows and old
+ *                W rows (0 and 2: no touch pass).  Lattice sweep: how the matrix rows of a site
+ *                reach the FMAs: 0 scalar loads when the row is computed,
+ *                1 one vector load a step ahead handed over lane by lane,
+ *                2 scalar loads whose lines a vector load pulled into L2 a
+ *                step ahead; default 2
  *   lattice      1 (default): at R = 32, on lattices with at least 128
  *                4 x 4-site pencils, use the cache-blocked sweep that keeps a
  *                ring of z-planes of V in LDS (of the other fields only

@@ -44,8 +44,26 @@ def lib():
         L.oracle_kpm_direct.argtypes = L.oracle_kpm_eta.argtypes
         L.oracle_threads.restype = ctypes.c_int
         L.oracle_threads.argtypes = []
+        L.oracle_splitmix64_next.restype = ctypes.c_uint64
+        L.oracle_splitmix64_next.argtypes = [p]
+        L.oracle_phase_block.restype = None
+        L.oracle_phase_block.argtypes = [ctypes.c_int64, ctypes.c_int, ctypes.c_uint64, p]
         _LIB = L
     return _LIB
+
+
+def splitmix64_sequence(state: int, n: int) -> list:
+    """First n outputs of SplitMix64 (Steele, Lea, Flood 2014) from the given state."""
+    st = np.array([state], dtype=np.uint64)
+    return [int(lib().oracle_splitmix64_next(_ptr(st))) for _ in range(n)]
+
+
+def phase_block_counter(N: int, R: int, seed: int) -> np.ndarray:
+    """[N][R] random-phase start block exp(2 pi i u_ir)/sqrt(N), u from SplitMix64 at counter
+    i R + r (reading of the start-vector step; see kpm_oracle.c)."""
+    out = np.zeros(2 * N * R, dtype=np.float64)
+    lib().oracle_phase_block(int(N), int(R), int(seed) & 0xFFFFFFFFFFFFFFFF, _ptr(out))
+    return out.view(np.complex128).reshape(N, R)
 
 
 def lib_threads() -> int:

@@ -296,3 +296,41 @@ int oracle_kpm_direct(int64_t N, const int64_t* rowptr, const int32_t* col,
     free(nu0); free(prev); free(cur); free(nxt); free(d);
     return 0;
 }
+
+/* ------------------------------------------------------------------------- */
+/* Random-phase start block from a counter-based generator (reading of the
+ * start-vector step of the stochastic trace, section "Problem Description",
+ * whose distribution the paper does not fix).  Generator: SplitMix64
+ * (Steele, Lea, Flood, "Fast splittable pseudorandom number generators",
+ * OOPSLA 2014): state advances by the odd constant 0x9E3779B97F4A7C15 and
+ * each output is the state passed through the 64-bit finaliser below.
+ * Element (i, r) of an [N][R] block (counter c = i R + r) draws the output
+ * for state key + (c + 1) * gamma with key = mix(seed + gamma); u is its top
+ * 53 bits over 2^53 and the element is exp(2 pi i u) / sqrt(N).            */
+#define SM_GAMMA 0x9E3779B97F4A7C15ULL
+
+static uint64_t sm_mix(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+uint64_t oracle_splitmix64_next(uint64_t* state)
+{
+    *state += SM_GAMMA;
+    return sm_mix(*state);
+}
+
+void oracle_phase_block(int64_t N, int R, uint64_t seed, double* out_ri)
+{
+    const uint64_t key = sm_mix(seed + SM_GAMMA);
+    const double scale = 1.0 / sqrt((double)N);
+    for (int64_t c = 0; c < N * (int64_t)R; ++c) {
+        const uint64_t z = sm_mix(key + (uint64_t)(c + 1) * SM_GAMMA);
+        const double u = (double)(z >> 11) * (1.0 / 9007199254740992.0);
+        const double phi = 6.283185307179586476925286766559 * u;   /* 2 pi */
+        out_ri[2 * c] = cos(phi) * scale;
+        out_ri[2 * c + 1] = sin(phi) * scale;
+    }
+}

@@ -148,5 +148,11 @@ hipError_t launch_zero_ints(int* p, int n, hipStream_t s);
 hipError_t launch_check_moments(const double* mu, int R, int M, int* flag, hipStream_t s);
 hipError_t launch_dos(const double* mu, int R, int M, int kernel, double kparam, double a,
                       double b, const double* E, int K, double* rho, hipStream_t s);
+hipError_t launch_dos_batched(const double* mu, int n_inst, int R, int ld, int M, int kernel, double kparam,
+                              const double* a, const double* b, const double* E, int K, int masses,
+                              double* rho, hipStream_t s);
+hipError_t launch_phase_block(void* V, int64_t N, int R, int dtype, uint64_t seed, hipStream_t s);
+hipError_t launch_features(const double* mu, int n_inst, int R, int ld, int n_mom, const float* extra,
+                           float* x, hipStream_t s);
 
 }  // namespace kpm

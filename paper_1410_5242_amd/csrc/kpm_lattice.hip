@@ -108,7 +108,12 @@ __device__ inline T wload(const T* p, bool nt) {
     return nt ? __builtin_nontemporal_load(p) : *p;
 }
 
-template <typename T, int VARIANT, bool VEC_VALS, int STREAM>
+// VALS: how the matrix rows reach the FMAs as wave-uniform operands.
+//   0  scalar buffer loads when the row is processed
+//   1  one vector load per site a step ahead, v_readlane per entry
+//   2  scalar loads, with the site's rows pulled into L2 by a vector load a
+//      step ahead (the scalar loads then wait on L2, not on HBM)
+template <typename T, int VARIANT, int VALS, int STREAM>
 __global__ void __launch_bounds__(kThreadsL)
 lattice_kernel(const T* __restrict__ val, const T* __restrict__ V, T* __restrict__ W,
                T alpha, T beta, T gamma, double* __restrict__ partials,
@@ -139,9 +144,12 @@ lattice_kernel(const T* __restrict__ val, const T* __restrict__ V, T* __restrict
     const int k_lo = static_cast<int>(static_cast<int64_t>(ntiles) * xcd / X);
     const int k_hi = static_cast<int>(static_cast<int64_t>(ntiles) * (xcd + 1) / X);
 
+    constexpr bool VEC_VALS = VALS == 1;
+    unsigned sink = 0;   // keeps the L2 warm-up loads of VALS == 2
+
     for (int k = k_lo + slot; k < k_hi; k += per) {
         const int x0 = (k % ntx) * kP, y0 = (k / ntx) * kP;
-        const int Lxv = min(kP, Lx - x0), Lyv = min(kP, Ly - y0);   // valid extent of the tile
+        const int Lxv = min(kP, Lx - x0), Lyv = min(kP, Ly - y0);   // valid extent of the tile (>= 2)
         const int x = x0 + ti, y = y0 + tj;
         const bool active = ti < Lxv && tj < Lyv;                     // wave-uniform
         const int64_t sxy = static_cast<int64_t>(x) + static_cast<int64_t>(Lx) * y;
@@ -150,14 +158,35 @@ lattice_kernel(const T* __restrict__ val, const T* __restrict__ V, T* __restrict
         nb[1] = xy_neighbour(x + 1, y, Lx, Ly, px, py, x0, y0, Lxv, Lyv);
         nb[2] = xy_neighbour(x, y - 1, Lx, Ly, px, py, x0, y0, Lxv, Lyv);
         nb[3] = xy_neighbour(x, y + 1, Lx, Ly, px, py, x0, y0, Lxv, Lyv);
+        // A tile is at least 2 sites wide in x and y, so a site has at most
+        // one neighbour across the tile edge in x and one in y: halo slot 0
+        // holds the x one (direction hx), slot 1 the y one (direction hy).
+        const int hx = nb[0].kind == 2 ? 0 : (nb[1].kind == 2 ? 1 : -1);
+        const int hy = nb[2].kind == 2 ? 2 : (nb[3].kind == 2 ? 3 : -1);
 
         // plane index of step s' (with periodic wrap); -1 when it does not exist
         auto plane_of = [&](int sp) -> int {
             if (sp >= 0 && sp < Lz) return sp;
             return pz ? (sp + Lz) % Lz : -1;
         };
+        // the four rows of each halo neighbour of this site in plane zp
+        auto load_halo = [&](int zp, T (&h)[2][4]) {
+            if (hx >= 0) {
+                const int64_t nbase = 4 * (static_cast<int64_t>(nb[hx].idx) + plane_sites * zp);
+#pragma unroll
+                for (int o = 0; o < 4; ++o) h[0][o] = gload<T>(vrs, lane, nbase + o);
+            }
+            if (hy >= 0) {
+                const int64_t nbase = 4 * (static_cast<int64_t>(nb[hy].idx) + plane_sites * zp);
+#pragma unroll
+                for (int o = 0; o < 4; ++o) h[1][o] = gload<T>(vrs, lane, nbase + o);
+            }
+        };
 
-        // prologue: planes -1, 0, 1 into ring slots 3, 0, 1
+        // prologue: planes -1, 0, 1 into ring slots 3, 0, 1; halo, old W and
+        // matrix rows of step 0
+        T h_c[2][4], w_c[4];
+        typename SiteRec<T>::V hv_c{};
         if (active) {
             for (int sp = -1; sp <= 1; ++sp) {
                 const int zp = plane_of(sp);
@@ -166,11 +195,7 @@ lattice_kernel(const T* __restrict__ val, const T* __restrict__ V, T* __restrict
 #pragma unroll
                 for (int o = 0; o < 4; ++o) ring[sp & 3][wave][o][lane] = gload<T>(vrs, lane, base + o);
             }
-        }
-        // old W and matrix rows of step 0
-        T w_c[4];
-        typename SiteRec<T>::V hv_c{};
-        if (active) {
+            load_halo(0, h_c);
             const int64_t base = 4 * sxy;
 #pragma unroll
             for (int o = 0; o < 4; ++o) {
@@ -182,22 +207,15 @@ lattice_kernel(const T* __restrict__ val, const T* __restrict__ V, T* __restrict
         __syncthreads();
 
         for (int s = 0; s < Lz; ++s) {
-            // Edge neighbours of this step first (they mostly hit L2), then the
-            // loads for later steps: plane s + 2 and the old W of step s + 1.
-            // Loads complete in issue order, so waiting for the edge rows does
-            // not wait for the later ones.
+            // Loads for later steps only: the halo and old W rows of step
+            // s + 1, plane s + 2 and (VALS 1, 2) the matrix rows of step s + 1.
+            // Nothing this step computes waits on them.
             const int zn2 = plane_of(s + 2);
             const int zn1 = (s + 1 < Lz) ? s + 1 : -1;
-            T h_c[4][4], p_n[4], w_n[4];
+            T h_n[2][4], p_n[4], w_n[4];
             typename SiteRec<T>::V hv_n{};
             if (active) {
-#pragma unroll
-                for (int d = 0; d < 4; ++d) {
-                    if (nb[d].kind != 2) continue;
-                    const int64_t nbase = 4 * (static_cast<int64_t>(nb[d].idx) + plane_sites * s);
-#pragma unroll
-                    for (int o = 0; o < 4; ++o) h_c[d][o] = gload<T>(vrs, lane, nbase + o);
-                }
+                if (zn1 >= 0) load_halo(zn1, h_n);
                 if (zn2 >= 0) {
                     const int64_t base = 4 * (sxy + plane_sites * zn2);
 #pragma unroll
@@ -210,7 +228,7 @@ lattice_kernel(const T* __restrict__ val, const T* __restrict__ V, T* __restrict
                         if constexpr (STREAM & 1) w_n[o] = need_w ? __builtin_nontemporal_load(W + (base + o) * kE + lane) : T(0);
                         else w_n[o] = need_w ? W[(base + o) * kE + lane] : T(0);
                     }
-                    if constexpr (VEC_VALS) hv_n = SiteRec<T>::load(val + base * 2 * kWidth, lane);
+                    if constexpr (VALS != 0) hv_n = SiteRec<T>::load(val + base * 2 * kWidth, lane);
                 }
             }
             const bool zdn = plane_of(s - 1) >= 0, zup = plane_of(s + 1) >= 0;
@@ -230,8 +248,9 @@ lattice_kernel(const T* __restrict__ val, const T* __restrict__ V, T* __restrict
                             v[sl] = ring[s & 3][nb[d].idx][o][lane];
                             v[sl + 1] = ring[s & 3][nb[d].idx][o ^ 3][lane];
                         } else if (nb[d].kind == 2) {
-                            v[sl] = h_c[d][o];
-                            v[sl + 1] = h_c[d][o ^ 3];
+                            const int hs = d < 2 ? 0 : 1;
+                            v[sl] = h_c[hs][o];
+                            v[sl + 1] = h_c[hs][o ^ 3];
                         } else {
                             v[sl] = v[sl + 1] = T(0);
                         }
@@ -281,11 +300,20 @@ lattice_kernel(const T* __restrict__ val, const T* __restrict__ V, T* __restrict
                 for (int o = 0; o < 4; ++o) ring[(s + 2) & 3][wave][o][lane] = p_n[o];
             }
 #pragma unroll
-            for (int o = 0; o < 4; ++o) w_c[o] = w_n[o];
-            hv_c = hv_n;
+            for (int o = 0; o < 4; ++o) {
+                w_c[o] = w_n[o];
+                h_c[0][o] = h_n[0][o];
+                h_c[1][o] = h_n[1][o];
+            }
+            if constexpr (VALS == 2) {
+                sink ^= static_cast<unsigned>(__builtin_amdgcn_readfirstlane(hv_n.x));
+            } else {
+                hv_c = hv_n;
+            }
             __syncthreads();
         }
     }
+    asm volatile("" ::"s"(sink));
 
     if constexpr (VARIANT == KPM_FULL) {
         const double e = acc_e + swap_pair(acc_e);
@@ -310,18 +338,24 @@ template <typename T, int STREAM>
 hipError_t launch_ts(int variant, const LatticeArgs& a, hipStream_t s) {
     const int ntx = (a.L[0] + kP - 1) / kP, nty = (a.L[1] + kP - 1) / kP;
     const int ntiles = ntx * nty;
-#define KPM_LAUNCH(VAR, VEC)                                                                     \
-    lattice_kernel<T, VAR, VEC, STREAM><<<a.grid, kThreadsL, 0, s>>>(                            \
+#define KPM_LAUNCH(VAR, VALS)                                                                    \
+    lattice_kernel<T, VAR, VALS, STREAM><<<a.grid, kThreadsL, 0, s>>>(                           \
         static_cast<const T*>(a.val), static_cast<const T*>(a.V), static_cast<T*>(a.W),          \
         static_cast<T>(a.alpha), static_cast<T>(a.beta), static_cast<T>(a.gamma), a.partials,  \
         a.L[0], a.L[1], a.L[2], a.periodic[0], a.periodic[1], a.periodic[2], ntx, ntiles)
-    const bool vec = a.prefetch != 0;
+#define KPM_LAUNCH_V(VAR)                          \
+    switch (a.prefetch) {                          \
+    case 1: KPM_LAUNCH(VAR, 1); break;             \
+    case 2: KPM_LAUNCH(VAR, 2); break;             \
+    default: KPM_LAUNCH(VAR, 0); break;            \
+    }
     switch (variant) {
-    case KPM_FULL: if (vec) KPM_LAUNCH(KPM_FULL, true); else KPM_LAUNCH(KPM_FULL, false); break;
-    case KPM_NODOT: if (vec) KPM_LAUNCH(KPM_NODOT, true); else KPM_LAUNCH(KPM_NODOT, false); break;
-    case KPM_PLAIN: if (vec) KPM_LAUNCH(KPM_PLAIN, true); else KPM_LAUNCH(KPM_PLAIN, false); break;
+    case KPM_FULL: KPM_LAUNCH_V(KPM_FULL); break;
+    case KPM_NODOT: KPM_LAUNCH_V(KPM_NODOT); break;
+    case KPM_PLAIN: KPM_LAUNCH_V(KPM_PLAIN); break;
     default: return hipErrorInvalidValue;
     }
+#undef KPM_LAUNCH_V
 #undef KPM_LAUNCH
     return hipGetLastError();
 }
@@ -345,6 +379,9 @@ int lattice_tiles(const kpm_hamiltonian* H) {
 
 bool lattice_supported(const kpm_hamiltonian* H, int R) {
     if (R != lattice::kR) return false;
+    // every tile must be at least 2 sites wide in x and y (at most one
+    // neighbour across each tile edge): no side with L mod 4 == 1
+    if (H->L[0] % lattice::kP == 1 || H->L[1] % lattice::kP == 1) return false;
     const uint64_t vbytes = static_cast<uint64_t>(H->nrows) * 2 * R *
                             (H->dtype == KPM_C128 ? sizeof(double) : sizeof(float));
     return vbytes < (1ull << 32) && H->L[0] > 0;

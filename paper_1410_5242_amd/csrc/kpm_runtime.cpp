@@ -503,14 +503,51 @@ kpm_status kpm_dos(const double* mu, int32_t R, int32_t M, int32_t kernel, doubl
     return KPM_OK;
 }
 
+kpm_status kpm_random_phase_block(void* V, int64_t N, int32_t R, int32_t dtype, uint64_t seed, void* stream) {
+    g_error.clear();
+    if (!V) return fail(KPM_EINVAL, "V is NULL");
+    if (N <= 0 || R <= 0) return fail(KPM_EINVAL, "N and R must be positive");
+    if (dtype != KPM_C128 && dtype != KPM_C64) return fail(KPM_EINVAL, "unknown dtype");
+    if (N > (INT64_MAX / 64) / R || N * R > (static_cast<int64_t>(INT32_MAX) * 256))
+        return fail(KPM_EINVAL, "block too large");
+    KPM_HIP(launch_phase_block(V, N, R, dtype, seed, static_cast<hipStream_t>(stream)), "phase block kernel");
+    return KPM_OK;
+}
+
+kpm_status kpm_dos_batched(const double* mu, int32_t n_inst, int32_t R, int32_t ld, int32_t M, int32_t kernel,
+                           double kparam, const double* a, const double* b, const double* E, int32_t K,
+                           int32_t masses, double* rho, void* stream) {
+    g_error.clear();
+    if (!mu || !a || !b || !E || !rho) return fail(KPM_EINVAL, "mu, a, b, E or rho is NULL");
+    if (n_inst <= 0 || R <= 0 || M <= 0 || K <= 0 || ld < M) return fail(KPM_EINVAL, "need n_inst, R, M, K > 0 and ld >= M");
+    if (n_inst > 65535) return fail(KPM_EINVAL, "at most 65535 instances per call");
+    if (kernel != KPM_JACKSON && kernel != KPM_DIRICHLET && kernel != KPM_LORENTZ)
+        return fail(KPM_EINVAL, "unknown kernel");
+    if (kernel == KPM_LORENTZ && !(kparam > 0.0)) return fail(KPM_EINVAL, "Lorentz kernel needs kparam > 0");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    KPM_HIP(launch_dos_batched(mu, n_inst, R, ld, M, kernel, kparam, a, b, E, K, masses ? 1 : 0, rho, s),
+            "dos kernel");
+    return KPM_OK;
+}
+
+kpm_status kpm_moment_features(const double* mu, int32_t n_inst, int32_t R, int32_t ld, int32_t n_mom,
+                               const float* extra, float* x, void* stream) {
+    g_error.clear();
+    if (!mu || !x) return fail(KPM_EINVAL, "mu or x is NULL");
+    if (n_inst <= 0 || R <= 0 || n_mom <= 0 || ld < n_mom) return fail(KPM_EINVAL, "need n_inst, R, n_mom > 0 and ld >= n_mom");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    KPM_HIP(launch_features(mu, n_inst, R, ld, n_mom, extra, x, s), "features kernel");
+    return KPM_OK;
+}
+
 kpm_status kpm_set_sweep_tuning(const kpm_sweep_tuning* t) {
     g_error.clear();
     if (!t) {
-        set_tuning(kpm_sweep_tuning{0, kXcds, 8, 16, 0, 0, 3, 1});
+        set_tuning(kpm_sweep_tuning{0, kXcds, 8, 16, 0, 2, 3, 1});
         return KPM_OK;
     }
     if (t->wg_per_cu < 0 || t->xcd_ways < 0 || t->chunk_tiles < 0 || t->pencil < 0 || t->dynamic < 0 ||
-        t->prefetch < 0 || t->stream < 0 || t->stream > 3 || t->lattice < 0 || t->lattice > 2)
+        t->prefetch < 0 || t->prefetch > 2 || t->stream < 0 || t->stream > 3 || t->lattice < 0 || t->lattice > 2)
         return fail(KPM_EINVAL, "tuning fields must be >= 0");
     if (t->wg_per_cu > 64 || t->xcd_ways > 64 || t->chunk_tiles > (1 << 20))
         return fail(KPM_EINVAL, "tuning field out of range");

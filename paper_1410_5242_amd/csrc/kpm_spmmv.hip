@@ -61,7 +61,7 @@ check_moments_kernel(const double* __restrict__ mu, int R, int M, int* __restric
 }  // namespace
 
 namespace {
-kpm_sweep_tuning g_tuning = {0, kXcds, 8, 16, 0, 0, 3, 1};
+kpm_sweep_tuning g_tuning = {0, kXcds, 8, 16, 0, 2, 3, 1};
 }
 
 kpm_sweep_tuning get_tuning() { return g_tuning; }
@@ -92,7 +92,7 @@ hipError_t launch_sweep(int dtype, int R, int variant, const SweepArgs& a_in, hi
     a.xcd_ways = g_tuning.xcd_ways > 0 ? g_tuning.xcd_ways : 1;
     a.chunk = g_tuning.chunk_tiles > 0 ? g_tuning.chunk_tiles : 1;
     if (!g_tuning.dynamic) a.queue = nullptr;
-    a.prefetch = g_tuning.prefetch;
+    a.prefetch = g_tuning.prefetch == 1 ? 1 : 0;   // the generic sweep's touch pass is option 1 only
     a.stream = g_tuning.stream;
     if (dtype == KPM_C128) return R >= 32 ? launch_sweep_c128_large(R, variant, a, s)
                                           : launch_sweep_c128_small(R, variant, a, s);

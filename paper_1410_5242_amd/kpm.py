@@ -68,7 +68,8 @@ EXPORTS = ("kpm_build_hamiltonian", "kpm_hamiltonian_info", "kpm_export_csr",
            "kpm_set_batch_tuning", "kpm_get_batch_tuning", "kpm_mlp_create", "kpm_mlp_destroy",
            "kpm_mlp_param_count", "kpm_mlp_set_params", "kpm_mlp_get_params", "kpm_mlp_get_grads",
            "kpm_mlp_forward", "kpm_mlp_backward", "kpm_mlp_adam_step", "kpm_mlp_train_step",
-           "kpm_mlp_gemm_bf16", "kpm_last_error", "kpm_version")
+           "kpm_mlp_gemm_bf16", "kpm_dos_batched", "kpm_moment_features", "kpm_random_phase_block",
+           "kpm_last_error", "kpm_version")
 
 
 def lib():
@@ -133,6 +134,12 @@ def lib():
     L.kpm_mlp_train_step.argtypes = [vp, vp, vp, vp, i32, flt, flt, vp, vp]
     L.kpm_mlp_gemm_bf16.restype = ctypes.c_int
     L.kpm_mlp_gemm_bf16.argtypes = [vp, vp, i32, i32, i32, i32, i32, vp, vp]
+    L.kpm_dos_batched.restype = ctypes.c_int
+    L.kpm_dos_batched.argtypes = [vp, i32, i32, i32, i32, i32, dbl, vp, vp, vp, i32, i32, vp, vp]
+    L.kpm_moment_features.restype = ctypes.c_int
+    L.kpm_moment_features.argtypes = [vp, i32, i32, i32, i32, vp, vp, vp]
+    L.kpm_random_phase_block.restype = ctypes.c_int
+    L.kpm_random_phase_block.argtypes = [vp, i64, i32, i32, ctypes.c_uint64, vp]
     L.kpm_last_error.restype = ctypes.c_char_p
     L.kpm_last_error.argtypes = []
     L.kpm_version.restype = ctypes.c_char_p
@@ -291,8 +298,43 @@ def dos(mu: torch.Tensor, a: float, b: float, E: torch.Tensor, kernel: str = "ja
     return rho
 
 
+def random_phase_block(N: int, R: int, seed: int, dtype: str = "c128", out: torch.Tensor | None = None,
+                       stream=None) -> torch.Tensor:
+    """kpm_random_phase_block: [N][R] random-phase start block drawn on the device."""
+    dt = _DTYPES[dtype]
+    if out is None:
+        out = torch.empty((N, R), dtype=_TORCH_DTYPE[dt], device="cuda")
+    _check(lib().kpm_random_phase_block(_dptr(out), int(N), int(R), dt, int(seed) & 0xFFFFFFFFFFFFFFFF,
+                                        _stream(stream)))
+    return out
+
+
+def dos_batched(mu: torch.Tensor, a: torch.Tensor, b: torch.Tensor, E: torch.Tensor, M: int | None = None,
+                kernel: str = "jackson", kparam: float = 0.0, masses: bool = False,
+                rho: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """kpm_dos_batched: rho [n][K] from mu [n][R][ld] (first M moments), per-instance a, b [n]."""
+    n, R, ld = mu.shape
+    M = ld if M is None else int(M)
+    K = E.numel()
+    if rho is None:
+        rho = torch.empty((n, K), dtype=torch.float64, device=E.device)
+    _check(lib().kpm_dos_batched(_dptr(mu), n, R, ld, M, _KERNELS[kernel], float(kparam), _dptr(a), _dptr(b),
+                                 _dptr(E), K, 1 if masses else 0, _dptr(rho), _stream(stream)))
+    return rho
+
+
+def moment_features(mu: torch.Tensor, n_mom: int, extra: torch.Tensor | None = None,
+                    stream=None) -> torch.Tensor:
+    """kpm_moment_features: [n][n_mom (+1)] float32 features from mu [n][R][ld]."""
+    n, R, ld = mu.shape
+    x = torch.empty((n, n_mom + (1 if extra is not None else 0)), dtype=torch.float32, device=mu.device)
+    _check(lib().kpm_moment_features(_dptr(mu), n, R, ld, int(n_mom), _dptr(extra) if extra is not None else None,
+                                     _dptr(x), _stream(stream)))
+    return x
+
+
 def set_sweep_tuning(wg_per_cu: int = 0, xcd_ways: int = 8, chunk_tiles: int = 8, pencil: int = 16,
-                     dynamic: int = 0, prefetch: int = 0, stream: int = 3, lattice: int = 1):
+                     dynamic: int = 0, prefetch: int = 2, stream: int = 3, lattice: int = 1):
     """kpm_set_sweep_tuning: launch shape and site order of the sweep kernel (process-wide)."""
     _check(lib().kpm_set_sweep_tuning(ctypes.byref(SweepTuning(wg_per_cu, xcd_ways, chunk_tiles, pencil,
                                                                dynamic, prefetch, stream, lattice))))

@@ -1,0 +1,118 @@
+"""Time to a density of states within a stated L1 error, plain vs optimised.
+
+Workload: held-out instances of the learned-reconstruction family (cubic
+lattices L = 16 .. 24, disorder gamma ~ U[0, 4], R = 16 random vectors, the
+fixed family scaling).  Truth: the complex128 Jackson DOS at M = 2048 with
+the same vectors; every shorter run is a prefix of it, so the L1 error
+sum_k |rho - rho_truth| dE on the 512-bin grid measures truncation (or
+reconstruction) only.  For a target eps, the KPM variants use the smallest
+M in {64, ..., 2048} whose mean L1 error over the instances is <= eps.
+
+Variants, each timed from device-resident Hamiltonians and start blocks to
+the DOS of every instance on the host (building H is reported apart):
+  plain    complex128, one kpm_moments + kpm_dos per instance
+  mixed    complex64 storage, FP64 products, one call per instance
+  batched  complex64, all instances in one kpm_moments_batched launch
+           plus one kpm_dos_batched
+  learned  batched complex64 run to M = 128, network, and a batched plain
+           rerun at the eps-M of the instances whose predicted error
+           exceeds eps (fallback)
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+import torch
+
+from . import kpm as K
+from . import learned as LN
+
+M_CHOICES = (64, 128, 256, 512, 1024, 2048)
+
+
+def _sync():
+    torch.cuda.synchronize()
+
+
+def run(n_inst: int = 1000, eps_list=(0.05, 0.02), per_instance_sample: int = 100, seed: int = LN.TEST_SEED + 7,
+        weights: str = LN.WEIGHTS, log=print) -> dict:
+    R = LN.R_TRUTH
+    fam = LN.family(n_inst, seed)
+    t0 = time.perf_counter()
+    H128 = LN.build(fam, "c128")
+    H64 = LN.build(fam, "c64")
+    _sync()
+    build_s = time.perf_counter() - t0
+    V128 = LN.start_blocks(fam, H128, R, "c128")
+    V64 = LN.start_blocks(fam, H64, R, "c64")
+    E = LN.energy_grid()
+    a = torch.full((n_inst,), LN.A_FAMILY, dtype=torch.float64, device="cuda")
+    b = torch.full((n_inst,), LN.B_FAMILY, dtype=torch.float64, device="cuda")
+    log(f"[time-to-dos] {n_inst} instances built ({build_s:.1f} s); truth run")
+    mu_truth = K.moments_batched(H128, V128, LN.M_TRUTH)
+    p = K.dos_batched(mu_truth, a, b, E, masses=True)
+    err_M = {M: float(LN.l1(K.dos_batched(mu_truth, a, b, E, M=M, masses=True), p).mean()) for M in M_CHOICES}
+    net, _ = LN.load_weights(weights, max_batch=1024)
+    out = {"n_instances": n_inst, "R": R, "truth_M": LN.M_TRUTH, "build_s": round(build_s, 2),
+           "kpm_mean_l1_by_M": {str(k): round(v, 5) for k, v in err_M.items()},
+           "per_instance_variants_timed_on": per_instance_sample, "targets": {}}
+    rho = torch.empty((n_inst, LN.K_BINS), dtype=torch.float64, device="cuda")
+    ns = min(per_instance_sample, n_inst)
+
+    for eps in eps_list:
+        M = next(m for m in M_CHOICES if err_M[m] <= eps)
+        res = {"M": M}
+        # plain / mixed: one call pair per instance, timed on the first ns and scaled
+        for name, Hs, Vs in (("plain_c128", H128, V128), ("mixed_c64", H64, V64)):
+            mu = torch.empty((R, M), dtype=torch.float64, device="cuda")
+            K.moments(Hs[0], Vs[0], M, mu=mu)
+            _sync()
+            t0 = time.perf_counter()
+            for i in range(ns):
+                K.moments(Hs[i], Vs[i], M, mu=mu, check=False)
+                K.dos(mu, LN.A_FAMILY, LN.B_FAMILY, E, rho=rho[i])
+            host = rho[:ns].cpu()
+            dt = (time.perf_counter() - t0) * n_inst / ns
+            res[name] = {"seconds": round(dt, 3), "timed_instances": ns, "mean_l1": round(err_M[M], 5)}
+            del host
+        # batched: one launch for all instances
+        K.moments_batched(H64[:8], V64[:8], M)
+        _sync()
+        t0 = time.perf_counter()
+        mu_b = K.moments_batched(H64, V64, M, check=False)
+        q_b = K.dos_batched(mu_b, a, b, E, masses=True)
+        host = q_b.cpu()
+        dt = time.perf_counter() - t0
+        res["batched_c64"] = {"seconds": round(dt, 3), "mean_l1": round(float(LN.l1(q_b, p).mean()), 5)}
+        # learned: batched short run, network, fallback reruns at M
+        mu_s = torch.empty((n_inst, R, LN.N_MOM), dtype=torch.float64, device="cuda")
+        _sync()
+        t0 = time.perf_counter()
+        K.moments_batched(H64, V64, LN.N_MOM, mu=mu_s, check=False)
+        x = LN.features(mu_s, fam)
+        q, e = LN.predict(net, x)
+        fb = e > eps
+        idx = torch.nonzero(fb).flatten().tolist()
+        out_q = q.double()
+        if idx:
+            mu_f = K.moments_batched([H64[i] for i in idx], [V64[i] for i in idx], M, check=False)
+            out_q[fb] = K.dos_batched(mu_f, a[:len(idx)], b[:len(idx)], E, masses=True)
+        host = out_q.cpu()
+        dt = time.perf_counter() - t0
+        err = LN.l1(out_q, p)
+        res["learned"] = {"seconds": round(dt, 3), "mean_l1": round(float(err.mean()), 5),
+                          "max_l1": round(float(err.max()), 5),
+                          "fallback_fraction": round(len(idx) / n_inst, 4),
+                          "accepted_over_eps_fraction": round(float(((err > eps) & ~fb).double().mean()), 4)}
+        del host
+        base = res["plain_c128"]["seconds"]
+        for k in ("mixed_c64", "batched_c64", "learned"):
+            res[k]["speedup_vs_plain"] = round(base / max(res[k]["seconds"], 1e-9), 2)
+        out["targets"][str(eps)] = res
+        log(f"[time-to-dos] eps {eps}: M={M} " + " ".join(f"{k}={v['seconds']}s" for k, v in res.items()
+                                                          if isinstance(v, dict)))
+    for H in H128 + H64:
+        H.close()
+    net.close()
+    return out

@@ -191,11 +191,12 @@ def test_moments_are_bitwise_deterministic_static_mapping():
     dict(lattice=0, dynamic=0, prefetch=0), dict(lattice=0, stream=3),
     dict(lattice=0, dynamic=0, pencil=0, xcd_ways=1, chunk_tiles=3),
     dict(lattice=0, wg_per_cu=2, dynamic=1, pencil=5), dict(lattice=2), dict(lattice=2, prefetch=0),
+    dict(lattice=2, prefetch=2), dict(lattice=2, prefetch=1),
 ])
 def test_launch_shapes_agree(tuning):
     # the launch shape and site order change only the order of the FP64 sums
     K = kpm()
-    L, M, R = (11, 9, 10), 200, 32
+    L, M, R = (11, 10, 9), 200, 32
     say("launch shape", tuning)
     pot, Ho, a, b = oracle_problem(L, 1.0, 6)
     v0 = inputs.phase_block(Ho.n, R, 6)
@@ -212,24 +213,28 @@ def test_launch_shapes_agree(tuning):
 # the cache-blocked lattice sweep (R = 32): tile edges, ragged tiles, open sides
 # --------------------------------------------------------------------------
 LATTICE_GEOMETRIES = [
-    ((4, 4, 4), (1, 1, 1)), ((5, 7, 3), (1, 1, 1)), ((3, 3, 3), (1, 1, 1)),
-    ((6, 5, 4), (0, 1, 1)), ((4, 9, 5), (1, 0, 1)), ((8, 8, 6), (1, 1, 0)),
-    ((2, 3, 5), (0, 1, 1)), ((1, 1, 7), (0, 0, 1)), ((9, 4, 1), (1, 1, 0)), ((13, 6, 4), (0, 0, 0)),
+    ((4, 4, 4), (1, 1, 1)), ((6, 7, 3), (1, 1, 1)), ((3, 3, 3), (1, 1, 1)),
+    ((6, 6, 4), (0, 1, 1)), ((4, 10, 5), (1, 0, 1)), ((8, 8, 6), (1, 1, 0)),
+    ((2, 3, 5), (0, 1, 1)), ((7, 6, 1), (1, 1, 0)), ((11, 6, 4), (0, 0, 0)), ((10, 3, 9), (1, 1, 1)),
 ]
 
 
 @pytest.mark.parametrize("L,periodic", LATTICE_GEOMETRIES)
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
-def test_lattice_sweep_matches_oracle(L, periodic, dtype):
+@pytest.mark.parametrize("vals", [0, 2])
+def test_lattice_sweep_matches_oracle(L, periodic, dtype, vals):
     K = kpm()
     M, R = 40, 32
-    say("lattice", L, periodic, dtype)
+    say("lattice", L, periodic, dtype, "vals", vals)
     pot, Ho, a, b = oracle_problem(L, 1.5, 11, periodic=periodic)
     v0 = inputs.phase_block(Ho.n, R, 12)
     ref_eta = O.kpm_eta(Ho, a, b, v0, M)
     ref = O.mu_from_eta(ref_eta)
     try:
-        K.set_sweep_tuning(lattice=2)
+        K.set_sweep_tuning(lattice=2, prefetch=vals)
+        H = K.build_hamiltonian(L, pot, periodic=periodic, dtype=dtype)
+        assert K.sweep_kernel(H, R) == "lattice_kernel"
+        H.close()
         mu, eta = gpu_moments(L, pot, v0, M, dtype=dtype, periodic=periodic, eta=True)
         K.set_sweep_tuning(lattice=0)
         mu_g, _ = gpu_moments(L, pot, v0, M, dtype=dtype, periodic=periodic)
@@ -243,9 +248,27 @@ def test_lattice_sweep_matches_oracle(L, periodic, dtype):
         assert np.abs(got_eta - ref_eta).max() <= TOL_C128
 
 
+@pytest.mark.parametrize("L", [(5, 4, 4), (4, 9, 3), (1, 1, 7)])
+def test_lattice_sweep_falls_back_for_one_site_tail_tiles(L):
+    # a side with L mod 4 == 1 would leave tiles one site wide: the generic sweep runs
+    K = kpm()
+    M, R = 24, 32
+    pot, Ho, a, b = oracle_problem(L, 1.0, 4, periodic=(0, 0, 1))
+    v0 = inputs.phase_block(Ho.n, R, 5)
+    try:
+        K.set_sweep_tuning(lattice=2)
+        H = K.build_hamiltonian(L, pot, periodic=(0, 0, 1))
+        assert K.sweep_kernel(H, R) == "aug_spmmv_kernel"
+        H.close()
+        mu, _ = gpu_moments(L, pot, v0, M, periodic=(0, 0, 1))
+    finally:
+        K.reset_sweep_tuning()
+    assert np.abs(mu - O.kpm_moments(Ho, a, b, v0, M)).max() <= TOL_C128
+
+
 def test_lattice_single_sweep_variants():
     K = kpm()
-    L, R = (6, 5, 7), 32
+    L, R = (6, 6, 7), 32
     pot, Ho, a, b = oracle_problem(L, 1.0, 13, periodic=(1, 0, 1))
     Hd = Ho.dense()
     H = K.build_hamiltonian(L, pot, periodic=(1, 0, 1))
@@ -408,3 +431,21 @@ def test_full_size_benchmark_workload():
     mu_short = K.moments(H, V0, 64).cpu().numpy()
     assert np.array_equal(mu_short, mu[:, :64])
     H.close()
+
+
+# --------------------------------------------------------------------------
+# a3: start block drawn on the device (counter-based SplitMix64)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("N,R,seed", [(1, 1, 0), (2048, 1, 0), (4100, 8, 3), (1000, 32, 2**63 + 5)])
+def test_random_phase_block_matches_oracle_generator(N, R, seed):
+    K = kpm()
+    say("phase block", N, R, seed)
+    ref = O.phase_block_counter(N, R, seed)
+    v = K.random_phase_block(N, R, seed, "c128")
+    torch.cuda.synchronize()
+    got = v.cpu().numpy()
+    # same generator on both sides: values agree to the last bits of cos / sin
+    assert np.abs(got - ref).max() <= 1e-14 / np.sqrt(N)
+    v64 = K.random_phase_block(N, R, seed, "c64")
+    torch.cuda.synchronize()
+    assert np.abs(v64.cpu().numpy() - ref.astype(np.complex64)).max() <= 1e-7 / np.sqrt(N)
