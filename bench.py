@@ -189,6 +189,46 @@ def leg_batched():
     return out
 
 
+def leg_variants(sweeps: int = 10):
+    """Single fused sweeps on the 64^3 complex128 lattice for every block width R and the three
+    variants (the paper's split of the sweep into plain SpMMV, the update without scalar
+    products, and the full fused sweep): GB/s from the library's per-launch HIP events."""
+    import torch
+    from paper_1410_5242_amd import inputs, kpm
+    L = (64, 64, 64)
+    H = kpm.build_hamiltonian(L, inputs.potential(L, 1.0, 0))
+    N, Sd = H.N, 16
+    out = {"workload": f"TI {L[0]}x{L[1]}x{L[2]} periodic, complex128, {sweeps} sweeps per point", "points": []}
+    for R in kpm.SUPPORTED_R:
+        V = kpm.random_phase_block(N, R, 1, "c128")
+        W = kpm.random_phase_block(N, R, 2, "c128")
+        eta = torch.zeros((2, R, 2), dtype=torch.float64, device="cuda")
+        kernel = kpm.sweep_kernel(H, R)
+        Si = 0 if kernel == "lattice_kernel" else 4
+        for var in ("full", "nodot", "plain"):
+            e = eta if var == "full" else None
+            kpm.aug_spmmv(H, V, W, 2.0 / H.a, -2.0 * H.b / H.a, -1.0, var, e)
+            torch.cuda.synchronize()
+            kpm.sweep_profile_read()
+            kpm.sweep_profile_enable(True)
+            for _ in range(sweeps):
+                kpm.aug_spmmv(H, V, W, 2.0 / H.a, -2.0 * H.b / H.a, -1.0, var, e)
+            torch.cuda.synchronize()
+            kpm.sweep_profile_enable(False)
+            n, tot, lo, hi = kpm.sweep_profile_read()
+            avg_s = tot / n * 1e-3
+            vec_streams = 2 if var == "plain" else 3
+            byts = 13 * N * (Sd + Si) + vec_streams * R * Sd * N
+            pt = {"R": R, "variant": var, "kernel": kernel, "avg_us": round(avg_s * 1e6, 1),
+                  "GBps": round(byts / avg_s / 1e9, 1), "bytes": byts}
+            if var == "full":
+                pt["gflops"] = round(sweep_flops(N, R) / avg_s / 1e9, 1)
+            out["points"].append(pt)
+        del V, W
+    H.close()
+    return out
+
+
 def leg_time_to_dos():
     from paper_1410_5242_amd import learned, time_to_dos
     if not os.path.exists(learned.WEIGHTS):
@@ -239,8 +279,8 @@ def main():
                     help="short run for hardware counters: a 1 GiB device copy (the calibration kernel "
                          "of known traffic) and --probe-sweeps fused sweeps of the workload")
     ap.add_argument("--probe-sweeps", type=int, default=8)
-    ap.add_argument("--legs", default="precision,batched,time_to_dos",
-                    help="extra measurements after the headline step: any of precision, batched, "
+    ap.add_argument("--legs", default="variants,precision,batched,time_to_dos",
+                    help="extra measurements after the headline step: any of variants, precision, batched, "
                          "time_to_dos (comma separated), or none")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -360,7 +400,8 @@ def main():
     H.close()
     del V0
     legs = [x for x in args.legs.split(",") if x and x != "none"]
-    for name, fn in (("precision", leg_precision), ("batched", leg_batched), ("time_to_dos", leg_time_to_dos)):
+    for name, fn in (("variants", leg_variants), ("precision", leg_precision), ("batched", leg_batched),
+                     ("time_to_dos", leg_time_to_dos)):
         if name in legs:
             log(f"[bench] leg {name}")
             out[name] = fn()

@@ -113,6 +113,7 @@ __device__ inline T wload(const T* p, bool nt) {
 //   1  one vector load per site a step ahead, v_readlane per entry
 //   2  scalar loads, with the site's rows pulled into L2 by a vector load a
 //      step ahead (the scalar loads then wait on L2, not on HBM)
+
 template <typename T, int VARIANT, int VALS, int STREAM>
 __global__ void __launch_bounds__(kThreadsL)
 lattice_kernel(const T* __restrict__ val, const T* __restrict__ V, T* __restrict__ W,
@@ -259,21 +260,22 @@ lattice_kernel(const T* __restrict__ val, const T* __restrict__ V, T* __restrict
                     v[10] = zdn ? ring[(s - 1) & 3][wave][o ^ 2][lane] : T(0);
                     v[11] = zup ? ring[(s + 1) & 3][wave][o][lane] : T(0);
                     v[12] = zup ? ring[(s + 1) & 3][wave][o ^ 2][lane] : T(0);
-                    T A = T(0), B = T(0);
+                    // two partial sums per product: shorter FMA dependency chains
+                    T A[2] = {T(0), T(0)}, B[2] = {T(0), T(0)};
                     if constexpr (VEC_VALS) {
 #pragma unroll
                         for (int j = 0; j < kWidth; ++j) {
-                            A = fma(SiteRec<T>::re(hv_c, kWidth * o + j), v[j], A);
-                            B = fma(SiteRec<T>::im(hv_c, kWidth * o + j), v[j], B);
+                            A[j & 1] = fma(SiteRec<T>::re(hv_c, kWidth * o + j), v[j], A[j & 1]);
+                            B[j & 1] = fma(SiteRec<T>::im(hv_c, kWidth * o + j), v[j], B[j & 1]);
                         }
                     } else {
 #pragma unroll
                         for (int j = 0; j < kWidth; ++j) {
-                            A = fma(from_words<T>(wv + (2 * j) * wpv), v[j], A);
-                            B = fma(from_words<T>(wv + (2 * j + 1) * wpv), v[j], B);
+                            A[j & 1] = fma(from_words<T>(wv + (2 * j) * wpv), v[j], A[j & 1]);
+                            B[j & 1] = fma(from_words<T>(wv + (2 * j + 1) * wpv), v[j], B[j & 1]);
                         }
                     }
-                    const T hv = fma(sgn, swap_pair(B), A);
+                    const T hv = fma(sgn, swap_pair(B[0] + B[1]), A[0] + A[1]);
                     T* wr = W + row * kE + lane;
                     if constexpr (VARIANT == KPM_PLAIN) {
                         if constexpr (STREAM & 2) __builtin_nontemporal_store(hv, wr);
