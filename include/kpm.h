@@ -177,8 +177,10 @@ kpm_status kpm_moment_features(const double* mu, int32_t n_inst, int32_t R, int3
 
 /* Launch shape of the fused sweep kernel (process-wide, not thread-safe;
  * results do not depend on it beyond the order of floating-point sums):
- *   wg_per_cu    workgroups (of 4 waves) per compute unit in the persistent
- *                grid; 0 selects 8 (32 resident waves per CU)
+ *   wg_per_cu    workgroups per compute unit in the persistent grid; 0
+ *                selects 8 for the scalar-operand sweep (4-wave workgroups,
+ *                32 resident waves per CU) and 16 waves per CU for the
+ *                staged-gather sweep
  *   xcd_ways     row tiles are split into this many contiguous ranges, one
  *                per accelerator die, matching the round-robin dispatch of
  *                workgroups to the 8 XCDs; 1 disables it; default 8
@@ -213,6 +215,15 @@ kpm_status kpm_moment_features(const double* mu, int32_t n_inst, int32_t R, int3
  *                gathers for the z neighbours were fetched one plane
  *                earlier; 0 keeps the natural row order; default 16.  The
  *                storage order of H and of the vector blocks never changes.
+ *   gather       which generic sweep runs where the lattice sweep does not:
+ *                0 (default) the staged-gather sweep for R != 32 and the
+ *                scalar-operand sweep for R = 32; 1 the staged-gather sweep
+ *                for every R; 2 the scalar-operand sweep for every R.  The
+ *                staged-gather sweep (one lane per 16 bytes of a block row,
+ *                matrix rows copied into LDS a pass ahead) uses only
+ *                wg_per_cu and xcd_ways of the fields above, and needs the
+ *                vector block and the matrix to stay below 4 GiB (otherwise
+ *                the scalar-operand sweep runs).
  * kpm_set_sweep_tuning(NULL) restores the defaults.  Errors: KPM_EINVAL
  * (negative field). */
 typedef struct {
@@ -224,13 +235,15 @@ typedef struct {
     int32_t prefetch;
     int32_t stream;
     int32_t lattice;
+    int32_t gather;
 } kpm_sweep_tuning;
 kpm_status kpm_set_sweep_tuning(const kpm_sweep_tuning* tuning);
 kpm_status kpm_get_sweep_tuning(kpm_sweep_tuning* tuning);
 
 /* Which sweep kernel kpm_moments / kpm_aug_spmmv launch for H at block
- * width R under the current tuning: *kernel = 0 generic gather sweep,
- * 1 cache-blocked lattice sweep.  Errors: KPM_EINVAL. */
+ * width R under the current tuning: *kernel = 0 scalar-operand gather
+ * sweep, 1 cache-blocked lattice sweep, 2 staged-gather sweep.
+ * Errors: KPM_EINVAL. */
 kpm_status kpm_sweep_kernel(const kpm_hamiltonian* H, int32_t R, int32_t* kernel);
 
 /* Sweep-kernel timing for measurement tools.  While enabled (process-wide,

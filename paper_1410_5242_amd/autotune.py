@@ -33,7 +33,8 @@ DEFAULT_CACHE = os.environ.get(
 
 DTYPE_NAMES = {0: "c128", 1: "c64"}
 
-SWEEP_FIELDS = ("wg_per_cu", "xcd_ways", "chunk_tiles", "pencil", "dynamic", "prefetch", "stream", "lattice")
+SWEEP_FIELDS = ("wg_per_cu", "xcd_ways", "chunk_tiles", "pencil", "dynamic", "prefetch", "stream", "lattice",
+                "gather")
 BATCH_FIELDS = ("waves", "wg_per_cu", "dynamic")
 
 
@@ -57,16 +58,22 @@ def width_key(dtype: int, S: int, N: int) -> str:
 
 def sweep_candidates(R: int, lattice_ok: bool) -> list[dict]:
     """Launch shapes of the fused sweep worth timing at block width R."""
-    base = dict(wg_per_cu=0, xcd_ways=8, chunk_tiles=8, pencil=16, dynamic=0, prefetch=0, stream=3, lattice=0)
+    base = dict(wg_per_cu=0, xcd_ways=8, chunk_tiles=8, pencil=16, dynamic=0, prefetch=2, stream=3, lattice=0,
+                gather=1)
     out = []
+    # staged-gather sweep: workgroups per CU and die-aware ranges
+    for wg in (0, 1, 2, 4):
+        for xcd in (8, 1):
+            out.append(dict(base, wg_per_cu=wg, xcd_ways=xcd))
+    # scalar-operand sweep
     for wg in (4, 8):
         for chunk in (4, 8, 16):
             for pencil in (0, 16):
                 for stream in (0, 3):
-                    c = dict(base, wg_per_cu=wg, chunk_tiles=chunk, pencil=pencil, stream=stream)
-                    out.append(c)
+                    out.append(dict(base, gather=2, prefetch=0, wg_per_cu=wg, chunk_tiles=chunk, pencil=pencil,
+                                    stream=stream))
     if lattice_ok:
-        for prefetch in (0, 1):
+        for prefetch in (0, 1, 2):
             for stream in (0, 1, 2, 3):
                 out.append(dict(base, lattice=2, prefetch=prefetch, stream=stream))
     return out
@@ -275,7 +282,7 @@ def apply_sweep(cache: TuningCache, H, R: int, L=None) -> bool:
     best = cache.get(sweep_key(H.dtype, R, H.N, L))
     if best is None:
         return False
-    K.set_sweep_tuning(**{k: int(best[k]) for k in SWEEP_FIELDS})
+    K.set_sweep_tuning(**{k: int(best[k]) for k in SWEEP_FIELDS if k in best})
     return True
 
 
@@ -284,5 +291,5 @@ def apply_batched(cache: TuningCache, Hs, R: int) -> bool:
     best = cache.get(batch_key(Hs[0].dtype, R, len(Hs), sum(H.N for H in Hs)))
     if best is None:
         return False
-    K.set_batch_tuning(**{k: int(best[k]) for k in BATCH_FIELDS})
+    K.set_batch_tuning(**{k: int(best[k]) for k in BATCH_FIELDS if k in best})
     return True

@@ -131,8 +131,14 @@ int device_cus();
 kpm_sweep_tuning get_tuning();
 void set_tuning(const kpm_sweep_tuning& t);
 
-// Grid size (workgroups) the sweep kernel uses for this dtype / R.
-int sweep_grid(int dtype, int R);
+// Which generic sweep kernel runs for this dtype / R / N (see kpm_sweep_tuning::gather):
+// true = the staged-gather sweep, false = the scalar-operand sweep.
+bool use_gather(int dtype, int R, int64_t nrows);
+// Grid size (workgroups) of the generic sweep kernel for this dtype / R / N.
+int sweep_grid(int dtype, int R, int64_t nrows);
+hipError_t launch_gather(int dtype, int R, int variant, const SweepArgs& a, hipStream_t s);
+int gather_waves(int dtype, int R);
+int gather_lds(int dtype, int R);
 hipError_t launch_sweep(int dtype, int R, int variant, const SweepArgs& a, hipStream_t s);
 // per-precision instantiations of the sweep kernel (R <= 16 and R >= 32)
 hipError_t launch_sweep_c128_small(int R, int variant, const SweepArgs& a, hipStream_t s);

@@ -88,7 +88,7 @@ bool use_lattice(const kpm_hamiltonian* H, int R) {
 }
 
 int launch_grid(const kpm_hamiltonian* H, int R) {
-    return use_lattice(H, R) ? lattice_grid(H) : sweep_grid(H->dtype, R);
+    return use_lattice(H, R) ? lattice_grid(H) : sweep_grid(H->dtype, R, H->nrows);
 }
 
 kpm_status ensure_partials(kpm_hamiltonian* H, int R, int slots) {
@@ -543,11 +543,12 @@ kpm_status kpm_moment_features(const double* mu, int32_t n_inst, int32_t R, int3
 kpm_status kpm_set_sweep_tuning(const kpm_sweep_tuning* t) {
     g_error.clear();
     if (!t) {
-        set_tuning(kpm_sweep_tuning{0, kXcds, 8, 16, 0, 2, 3, 1});
+        set_tuning(kpm_sweep_tuning{0, kXcds, 8, 16, 0, 2, 3, 1, 0});
         return KPM_OK;
     }
     if (t->wg_per_cu < 0 || t->xcd_ways < 0 || t->chunk_tiles < 0 || t->pencil < 0 || t->dynamic < 0 ||
-        t->prefetch < 0 || t->prefetch > 2 || t->stream < 0 || t->stream > 3 || t->lattice < 0 || t->lattice > 2)
+        t->prefetch < 0 || t->prefetch > 2 || t->stream < 0 || t->stream > 3 || t->lattice < 0 || t->lattice > 2 ||
+        t->gather < 0 || t->gather > 2)
         return fail(KPM_EINVAL, "tuning fields must be >= 0");
     if (t->wg_per_cu > 64 || t->xcd_ways > 64 || t->chunk_tiles > (1 << 20))
         return fail(KPM_EINVAL, "tuning field out of range");
@@ -565,7 +566,7 @@ kpm_status kpm_get_sweep_tuning(kpm_sweep_tuning* t) {
 kpm_status kpm_sweep_kernel(const kpm_hamiltonian* Hc, int32_t R, int32_t* kernel) {
     g_error.clear();
     if (!Hc || !kernel) return fail(KPM_EINVAL, "H or kernel is NULL");
-    *kernel = use_lattice(Hc, R) ? 1 : 0;
+    *kernel = use_lattice(Hc, R) ? 1 : (use_gather(Hc->dtype, R, Hc->nrows) ? 2 : 0);
     return KPM_OK;
 }
 

@@ -61,7 +61,7 @@ check_moments_kernel(const double* __restrict__ mu, int R, int M, int* __restric
 }  // namespace
 
 namespace {
-kpm_sweep_tuning g_tuning = {0, kXcds, 8, 16, 0, 2, 3, 1};
+kpm_sweep_tuning g_tuning = {0, kXcds, 8, 16, 0, 2, 3, 1, 0};
 }
 
 kpm_sweep_tuning get_tuning() { return g_tuning; }
@@ -79,10 +79,27 @@ int device_cus() {
     return cached[dev];
 }
 
-int sweep_grid(int dtype, int R) {
-    (void)dtype;
-    (void)R;
-    const int per_cu = g_tuning.wg_per_cu > 0 ? g_tuning.wg_per_cu : 8;   // 32 waves per CU
+bool use_gather(int dtype, int R, int64_t nrows) {
+    if (g_tuning.gather == 2) return false;
+    // 32-bit buffer offsets with room for the read-ahead past the last pass
+    const uint64_t rs = dtype == KPM_C128 ? 8 : 4;
+    const uint64_t lim = (1ull << 32) - (1ull << 24);
+    const uint64_t n = static_cast<uint64_t>(nrows);
+    if (n * R * 2 * rs >= lim || n * kWidth * 2 * rs >= lim) return false;
+    return g_tuning.gather == 1 || R != 32;
+}
+
+int sweep_grid(int dtype, int R, int64_t nrows) {
+    int per_cu;
+    if (use_gather(dtype, R, nrows)) {
+        // 16 waves per CU by default, no more workgroups than the LDS holds
+        const int w = gather_waves(dtype, R);
+        const int fit = (160 * 1024) / gather_lds(dtype, R);
+        per_cu = g_tuning.wg_per_cu > 0 ? g_tuning.wg_per_cu : 16 / w;
+        if (per_cu > fit) per_cu = fit > 0 ? fit : 1;
+    } else {
+        per_cu = g_tuning.wg_per_cu > 0 ? g_tuning.wg_per_cu : 8;   // 32 waves per CU
+    }
     const int g = device_cus() * per_cu;
     return (g + kXcds - 1) / kXcds * kXcds;
 }
@@ -90,9 +107,10 @@ int sweep_grid(int dtype, int R) {
 hipError_t launch_sweep(int dtype, int R, int variant, const SweepArgs& a_in, hipStream_t s) {
     SweepArgs a = a_in;
     a.xcd_ways = g_tuning.xcd_ways > 0 ? g_tuning.xcd_ways : 1;
+    if (use_gather(dtype, R, a.nrows)) return launch_gather(dtype, R, variant, a, s);
     a.chunk = g_tuning.chunk_tiles > 0 ? g_tuning.chunk_tiles : 1;
     if (!g_tuning.dynamic) a.queue = nullptr;
-    a.prefetch = g_tuning.prefetch == 1 ? 1 : 0;   // the generic sweep's touch pass is option 1 only
+    a.prefetch = g_tuning.prefetch == 1 ? 1 : 0;   // the touch pass is option 1 only
     a.stream = g_tuning.stream;
     if (dtype == KPM_C128) return R >= 32 ? launch_sweep_c128_large(R, variant, a, s)
                                           : launch_sweep_c128_small(R, variant, a, s);

@@ -37,7 +37,7 @@ class KPMError(RuntimeError):
 class SweepTuning(ctypes.Structure):
     _fields_ = [("wg_per_cu", ctypes.c_int32), ("xcd_ways", ctypes.c_int32), ("chunk_tiles", ctypes.c_int32),
                 ("pencil", ctypes.c_int32), ("dynamic", ctypes.c_int32), ("prefetch", ctypes.c_int32),
-                ("stream", ctypes.c_int32), ("lattice", ctypes.c_int32)]
+                ("stream", ctypes.c_int32), ("lattice", ctypes.c_int32), ("gather", ctypes.c_int32)]
 
 
 class BatchTuning(ctypes.Structure):
@@ -334,10 +334,10 @@ def moment_features(mu: torch.Tensor, n_mom: int, extra: torch.Tensor | None = N
 
 
 def set_sweep_tuning(wg_per_cu: int = 0, xcd_ways: int = 8, chunk_tiles: int = 8, pencil: int = 16,
-                     dynamic: int = 0, prefetch: int = 2, stream: int = 3, lattice: int = 1):
+                     dynamic: int = 0, prefetch: int = 2, stream: int = 3, lattice: int = 1, gather: int = 0):
     """kpm_set_sweep_tuning: launch shape and site order of the sweep kernel (process-wide)."""
     _check(lib().kpm_set_sweep_tuning(ctypes.byref(SweepTuning(wg_per_cu, xcd_ways, chunk_tiles, pencil,
-                                                               dynamic, prefetch, stream, lattice))))
+                                                               dynamic, prefetch, stream, lattice, gather))))
 
 
 def reset_sweep_tuning():
@@ -349,14 +349,14 @@ def get_sweep_tuning():
     _check(lib().kpm_get_sweep_tuning(ctypes.byref(t)))
     return {"wg_per_cu": t.wg_per_cu, "xcd_ways": t.xcd_ways, "chunk_tiles": t.chunk_tiles, "pencil": t.pencil,
             "dynamic": t.dynamic, "prefetch": t.prefetch, "stream": t.stream,
-            "lattice": t.lattice}
+            "lattice": t.lattice, "gather": t.gather}
 
 
 def sweep_kernel(H: Hamiltonian, R: int) -> str:
     """kpm_sweep_kernel: name of the sweep kernel used for H at block width R."""
     k = ctypes.c_int32()
     _check(lib().kpm_sweep_kernel(H.handle, int(R), ctypes.byref(k)))
-    return "lattice_kernel" if k.value == 1 else "aug_spmmv_kernel"
+    return {0: "aug_spmmv_kernel", 1: "lattice_kernel", 2: "gather_sweep_kernel"}[k.value]
 
 
 def sweep_profile_enable(on: bool = True):

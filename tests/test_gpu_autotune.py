@@ -35,8 +35,10 @@ def test_tune_sweep_then_moments_match_oracle(tmp_path):
     say("tune sweep", L, R)
     pot = inputs.potential(L, 1.0, 4)
     H = K.build_hamiltonian(L, pot)
-    cands = [dict(wg_per_cu=wg, xcd_ways=8, chunk_tiles=ch, pencil=p, dynamic=0, prefetch=0, stream=st, lattice=lat)
-             for wg, ch, p, st, lat in [(8, 8, 16, 3, 1), (4, 4, 0, 0, 0), (8, 16, 16, 3, 0), (4, 8, 0, 3, 2)]]
+    cands = [dict(wg_per_cu=wg, xcd_ways=8, chunk_tiles=ch, pencil=p, dynamic=0, prefetch=pf, stream=st, lattice=lat,
+                  gather=g)
+             for wg, ch, p, pf, st, lat, g in [(8, 8, 16, 2, 3, 1, 0), (4, 4, 0, 0, 0, 0, 2), (8, 16, 16, 0, 3, 0, 2),
+                                               (4, 8, 0, 2, 3, 2, 0), (2, 8, 16, 0, 3, 0, 1)]]
     cache = A.TuningCache(str(tmp_path / "t.json"))
     res = A.tune_sweep(H, R, cache=cache, candidates=cands, sweeps=4, repeats=2, L=L)
     assert res.best in cands and len(res.trials) == len(cands)
@@ -45,7 +47,7 @@ def test_tune_sweep_then_moments_match_oracle(tmp_path):
     K.reset_sweep_tuning()
     assert A.apply_sweep(A.TuningCache(cache.path), H, R, L=L)
     got = K.get_sweep_tuning()
-    assert all(got[k] == res.best[k] for k in A.SWEEP_FIELDS)
+    assert all(got[k] == res.best[k] for k in res.best)
     Ho = O.ti_hamiltonian(L, pot)
     a, b = O.scaling(*O.gershgorin(Ho))
     v0 = inputs.phase_block(Ho.n, R, 9)

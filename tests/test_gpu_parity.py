@@ -449,3 +449,27 @@ def test_random_phase_block_matches_oracle_generator(N, R, seed):
     v64 = K.random_phase_block(N, R, seed, "c64")
     torch.cuda.synchronize()
     assert np.abs(v64.cpu().numpy() - ref.astype(np.complex64)).max() <= 1e-7 / np.sqrt(N)
+
+
+# --------------------------------------------------------------------------
+# both generic sweeps (staged-gather and scalar-operand) at every block width
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("gather", [1, 2])
+@pytest.mark.parametrize("R", [1, 2, 8, 32, 64])
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_generic_sweeps_match_oracle(gather, R, dtype):
+    K = kpm()
+    L, M = (7, 6, 5), 48
+    say("generic sweep gather", gather, "R", R, dtype)
+    pot, Ho, a, b = oracle_problem(L, 1.0, 21, periodic=(1, 1, 0))
+    v0 = inputs.phase_block(Ho.n, R, 22)
+    ref = O.kpm_moments(Ho, a, b, v0, M)
+    try:
+        K.set_sweep_tuning(lattice=0, gather=gather)
+        H = K.build_hamiltonian(L, pot, periodic=(1, 1, 0), dtype=dtype)
+        assert K.sweep_kernel(H, R) == ("gather_sweep_kernel" if gather == 1 else "aug_spmmv_kernel")
+        H.close()
+        mu, _ = gpu_moments(L, pot, v0, M, dtype=dtype, periodic=(1, 1, 0))
+    finally:
+        K.reset_sweep_tuning()
+    assert np.abs(mu - ref).max() <= (TOL_C128 if dtype == "c128" else TOL_C64)
