@@ -87,10 +87,11 @@ def cpu_baseline(L, gamma, R, dtype, target_s=15.0):
     Ho = O.ti_hamiltonian(L, pot)
     a, b = O.scaling(*O.gershgorin(Ho))
     v0 = inputs.phase_block(Ho.n, R, 0)
+    O.kpm_eta(Ho, a, b, v0, 2)                 # first touch of the oracle's buffers
     t0 = time.perf_counter()
-    O.kpm_eta(Ho, a, b, v0, 2)
-    t1 = time.perf_counter() - t0
-    sweeps = int(max(1, min(64, target_s / max(t1, 1e-3))))
+    O.kpm_eta(Ho, a, b, v0, 8)
+    t1 = (time.perf_counter() - t0) / 4.0      # per sweep
+    sweeps = int(max(1, min(512, target_s / max(t1, 1e-3))))
     t0 = time.perf_counter()
     O.kpm_eta(Ho, a, b, v0, 2 * sweeps)
     dt = time.perf_counter() - t0
