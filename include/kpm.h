@@ -224,6 +224,11 @@ kpm_status kpm_moment_features(const double* mu, int32_t n_inst, int32_t R, int3
  *                wg_per_cu and xcd_ways of the fields above, and needs the
  *                vector block and the matrix to stay below 4 GiB (otherwise
  *                the scalar-operand sweep runs).
+ *   tile_order   lattice sweep: how pencils are dealt to the 8 dies: 0
+ *                (default) each die a 2-D block of tiles (so that most edge
+ *                rows a tile gathers belong to tiles of its own die, in its
+ *                own L2), 1 each die a contiguous run of tile rows, 2 no die
+ *                mapping.  Only the work distribution changes.
  * kpm_set_sweep_tuning(NULL) restores the defaults.  Errors: KPM_EINVAL
  * (negative field). */
 typedef struct {
@@ -236,6 +241,7 @@ typedef struct {
     int32_t stream;
     int32_t lattice;
     int32_t gather;
+    int32_t tile_order;
 } kpm_sweep_tuning;
 kpm_status kpm_set_sweep_tuning(const kpm_sweep_tuning* tuning);
 kpm_status kpm_get_sweep_tuning(kpm_sweep_tuning* tuning);

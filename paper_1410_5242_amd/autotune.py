@@ -34,7 +34,7 @@ DEFAULT_CACHE = os.environ.get(
 DTYPE_NAMES = {0: "c128", 1: "c64"}
 
 SWEEP_FIELDS = ("wg_per_cu", "xcd_ways", "chunk_tiles", "pencil", "dynamic", "prefetch", "stream", "lattice",
-                "gather")
+                "gather", "tile_order")
 BATCH_FIELDS = ("waves", "wg_per_cu", "dynamic")
 
 
@@ -59,7 +59,7 @@ def width_key(dtype: int, S: int, N: int) -> str:
 def sweep_candidates(R: int, lattice_ok: bool) -> list[dict]:
     """Launch shapes of the fused sweep worth timing at block width R."""
     base = dict(wg_per_cu=0, xcd_ways=8, chunk_tiles=8, pencil=16, dynamic=0, prefetch=2, stream=3, lattice=0,
-                gather=1)
+                gather=1, tile_order=0)
     out = []
     # staged-gather sweep: workgroups per CU and die-aware ranges
     for wg in (0, 1, 2, 4):
@@ -73,9 +73,10 @@ def sweep_candidates(R: int, lattice_ok: bool) -> list[dict]:
                     out.append(dict(base, gather=2, prefetch=0, wg_per_cu=wg, chunk_tiles=chunk, pencil=pencil,
                                     stream=stream))
     if lattice_ok:
-        for prefetch in (0, 1, 2):
-            for stream in (0, 1, 2, 3):
-                out.append(dict(base, lattice=2, prefetch=prefetch, stream=stream))
+        for prefetch in (0, 2):
+            for stream in (0, 3):
+                for order in (0, 1, 2):
+                    out.append(dict(base, lattice=2, prefetch=prefetch, stream=stream, tile_order=order))
     return out
 
 

@@ -92,6 +92,7 @@ struct LatticeArgs {
     int grid;
     int prefetch;       // matrix rows through one vector load per site (a step ahead)
     int stream;         // non-temporal hint: bit 0 old-W loads, bit 1 new-W stores
+    int order;          // tiles to dies: 0 2-D blocks, 1 runs of tile rows, 2 none
 };
 bool lattice_supported(const kpm_hamiltonian* H, int R);
 int lattice_tiles(const kpm_hamiltonian* H);

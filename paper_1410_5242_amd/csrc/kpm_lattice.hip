@@ -118,7 +118,7 @@ template <typename T, int VARIANT, int VALS, int STREAM>
 __global__ void __launch_bounds__(kThreadsL)
 lattice_kernel(const T* __restrict__ val, const T* __restrict__ V, T* __restrict__ W,
                T alpha, T beta, T gamma, double* __restrict__ partials,
-               int Lx, int Ly, int Lz, int px, int py, int pz, int ntx, int ntiles) {
+               int Lx, int Ly, int Lz, int px, int py, int pz, int ntx, int ntiles, int order) {
     __shared__ T ring[4][kNW][4][kE];
     __shared__ double red[kNW][3][kR];
 
@@ -138,18 +138,29 @@ lattice_kernel(const T* __restrict__ val, const T* __restrict__ V, T* __restrict
     double acc_e = 0.0, acc_or = 0.0, acc_oi = 0.0;
 
     const int ngrid = gridDim.x;
-    const int X = (ngrid % kXcds == 0) ? kXcds : 1;
+    const int X = (order != 2 && ngrid % kXcds == 0) ? kXcds : 1;
     const int xcd = blockIdx.x % X;
     const int slot = blockIdx.x / X;
     const int per = ngrid / X;
     const int k_lo = static_cast<int>(static_cast<int64_t>(ntiles) * xcd / X);
     const int k_hi = static_cast<int>(static_cast<int64_t>(ntiles) * (xcd + 1) / X);
+    const int nty = ntiles / ntx;
+    // order 0: each die takes a 2-D block of (ntx/2) x (nty/4) tiles, so that
+    // most tiles whose edge rows it gathers are its own; order 1: each die
+    // takes a contiguous run of tile rows; order 2: no die mapping
+    const bool blocks = order == 0 && X == kXcds && ntx % 2 == 0 && nty % 4 == 0;
 
     constexpr bool VEC_VALS = VALS == 1;
     unsigned sink = 0;   // keeps the L2 warm-up loads of VALS == 2
 
     for (int k = k_lo + slot; k < k_hi; k += per) {
-        const int x0 = (k % ntx) * kP, y0 = (k / ntx) * kP;
+        int tx = k % ntx, ty = k / ntx;
+        if (blocks) {
+            const int bw = ntx / 2, bh = nty / 4, i = k - k_lo;
+            tx = (xcd % 2) * bw + i % bw;
+            ty = (xcd / 2) * bh + i / bw;
+        }
+        const int x0 = tx * kP, y0 = ty * kP;
         const int Lxv = min(kP, Lx - x0), Lyv = min(kP, Ly - y0);   // valid extent of the tile (>= 2)
         const int x = x0 + ti, y = y0 + tj;
         const bool active = ti < Lxv && tj < Lyv;                     // wave-uniform
@@ -344,7 +355,7 @@ hipError_t launch_ts(int variant, const LatticeArgs& a, hipStream_t s) {
     lattice_kernel<T, VAR, VALS, STREAM><<<a.grid, kThreadsL, 0, s>>>(                           \
         static_cast<const T*>(a.val), static_cast<const T*>(a.V), static_cast<T*>(a.W),          \
         static_cast<T>(a.alpha), static_cast<T>(a.beta), static_cast<T>(a.gamma), a.partials,  \
-        a.L[0], a.L[1], a.L[2], a.periodic[0], a.periodic[1], a.periodic[2], ntx, ntiles)
+        a.L[0], a.L[1], a.L[2], a.periodic[0], a.periodic[1], a.periodic[2], ntx, ntiles, a.order)
 #define KPM_LAUNCH_V(VAR)                          \
     switch (a.prefetch) {                          \
     case 1: KPM_LAUNCH(VAR, 1); break;             \

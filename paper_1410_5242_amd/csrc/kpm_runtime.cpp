@@ -172,7 +172,7 @@ hipError_t launch_any_sweep(kpm_hamiltonian* H, int R, int variant, const SweepA
     if (use_lattice(H, R)) {
         LatticeArgs la{H->val, a.V, a.W, a.alpha, a.beta, a.gamma, a.partials,
                        {H->L[0], H->L[1], H->L[2]}, {H->periodic[0], H->periodic[1], H->periodic[2]}, a.grid,
-                       get_tuning().prefetch, get_tuning().stream};
+                       get_tuning().prefetch, get_tuning().stream, get_tuning().tile_order};
         if (!g_prof.on) return launch_lattice(H->dtype, variant, la, s);
         if (g_prof.used == g_prof.start.size()) {
             hipEvent_t e0, e1;
@@ -543,12 +543,12 @@ kpm_status kpm_moment_features(const double* mu, int32_t n_inst, int32_t R, int3
 kpm_status kpm_set_sweep_tuning(const kpm_sweep_tuning* t) {
     g_error.clear();
     if (!t) {
-        set_tuning(kpm_sweep_tuning{0, kXcds, 8, 16, 0, 2, 3, 1, 0});
+        set_tuning(kpm_sweep_tuning{0, kXcds, 8, 16, 0, 2, 3, 1, 0, 0});
         return KPM_OK;
     }
     if (t->wg_per_cu < 0 || t->xcd_ways < 0 || t->chunk_tiles < 0 || t->pencil < 0 || t->dynamic < 0 ||
         t->prefetch < 0 || t->prefetch > 2 || t->stream < 0 || t->stream > 3 || t->lattice < 0 || t->lattice > 2 ||
-        t->gather < 0 || t->gather > 2)
+        t->gather < 0 || t->gather > 2 || t->tile_order < 0 || t->tile_order > 2)
         return fail(KPM_EINVAL, "tuning fields must be >= 0");
     if (t->wg_per_cu > 64 || t->xcd_ways > 64 || t->chunk_tiles > (1 << 20))
         return fail(KPM_EINVAL, "tuning field out of range");

@@ -37,7 +37,8 @@ class KPMError(RuntimeError):
 class SweepTuning(ctypes.Structure):
     _fields_ = [("wg_per_cu", ctypes.c_int32), ("xcd_ways", ctypes.c_int32), ("chunk_tiles", ctypes.c_int32),
                 ("pencil", ctypes.c_int32), ("dynamic", ctypes.c_int32), ("prefetch", ctypes.c_int32),
-                ("stream", ctypes.c_int32), ("lattice", ctypes.c_int32), ("gather", ctypes.c_int32)]
+                ("stream", ctypes.c_int32), ("lattice", ctypes.c_int32), ("gather", ctypes.c_int32),
+                ("tile_order", ctypes.c_int32)]
 
 
 class BatchTuning(ctypes.Structure):
@@ -334,10 +335,12 @@ def moment_features(mu: torch.Tensor, n_mom: int, extra: torch.Tensor | None = N
 
 
 def set_sweep_tuning(wg_per_cu: int = 0, xcd_ways: int = 8, chunk_tiles: int = 8, pencil: int = 16,
-                     dynamic: int = 0, prefetch: int = 2, stream: int = 3, lattice: int = 1, gather: int = 0):
+                     dynamic: int = 0, prefetch: int = 2, stream: int = 3, lattice: int = 1, gather: int = 0,
+                     tile_order: int = 0):
     """kpm_set_sweep_tuning: launch shape and site order of the sweep kernel (process-wide)."""
     _check(lib().kpm_set_sweep_tuning(ctypes.byref(SweepTuning(wg_per_cu, xcd_ways, chunk_tiles, pencil,
-                                                               dynamic, prefetch, stream, lattice, gather))))
+                                                               dynamic, prefetch, stream, lattice, gather,
+                                                               tile_order))))
 
 
 def reset_sweep_tuning():
@@ -349,7 +352,7 @@ def get_sweep_tuning():
     _check(lib().kpm_get_sweep_tuning(ctypes.byref(t)))
     return {"wg_per_cu": t.wg_per_cu, "xcd_ways": t.xcd_ways, "chunk_tiles": t.chunk_tiles, "pencil": t.pencil,
             "dynamic": t.dynamic, "prefetch": t.prefetch, "stream": t.stream,
-            "lattice": t.lattice, "gather": t.gather}
+            "lattice": t.lattice, "gather": t.gather, "tile_order": t.tile_order}
 
 
 def sweep_kernel(H: Hamiltonian, R: int) -> str:

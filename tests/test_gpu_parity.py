@@ -473,3 +473,20 @@ def test_generic_sweeps_match_oracle(gather, R, dtype):
     finally:
         K.reset_sweep_tuning()
     assert np.abs(mu - ref).max() <= (TOL_C128 if dtype == "c128" else TOL_C64)
+
+
+@pytest.mark.parametrize("order", [0, 1, 2])
+@pytest.mark.parametrize("L", [(8, 16, 5), (16, 16, 3)])
+def test_lattice_tile_orders_match_oracle(order, L):
+    # 2-D tile blocks per die, runs of tile rows, or no die mapping: same moments
+    K = kpm()
+    M, R = 24, 32
+    say("lattice tile order", order, L)
+    pot, Ho, a, b = oracle_problem(L, 1.0, 31)
+    v0 = inputs.phase_block(Ho.n, R, 32)
+    try:
+        K.set_sweep_tuning(lattice=2, tile_order=order)
+        mu, _ = gpu_moments(L, pot, v0, M)
+    finally:
+        K.reset_sweep_tuning()
+    assert np.abs(mu - O.kpm_moments(Ho, a, b, v0, M)).max() <= TOL_C128
