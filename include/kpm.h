@@ -195,16 +195,18 @@ kpm_status kpm_moment_features(const double* mu, int32_t n_inst, int32_t R, int3
  *                reproducible; default 0
  *   prefetch     0, 1 or 2.  Generic sweep: 1 = before a wave streams its
  *                tiles it touches every line of their matrix rows and old
- *                W rows (0 and 2: no touch pass).  Lattice sweep: how the matrix rows of a site
- *                reach the FMAs: 0 scalar loads when the row is computed,
- *                1 one vector load a step ahead handed over lane by lane,
- *                2 scalar loads whose lines a vector load pulled into L2 a
- *                step ahead; default 2
+ *                W rows (0 and 2: no touch pass).  Lattice sweep: how the
+ *                matrix rows of a site reach the FMAs: 2 one vector load a
+ *                step ahead, handed over lane by lane; 1 scalar loads whose
+ *                lines a vector load pulled into L2 a step ahead; 0 scalar
+ *                loads when the row is computed; default 2
  *   lattice      1 (default): at R = 32, on lattices with at least 128
  *                4 x 4-site pencils, use the cache-blocked sweep that keeps a
  *                ring of z-planes of V in LDS (of the other fields only
- *                `prefetch` applies to it); 2: use it whenever R = 32; 0: the
- *                generic gather sweep
+ *                prefetch, stream, tile_order and wg_per_cu apply to it;
+ *                wg_per_cu is capped at the 1 (complex128) or 2 (complex64)
+ *                workgroups whose LDS fits on a CU, default 1); 2: use it
+ *                whenever R = 32; 0: the generic gather sweep
  *   stream       bit 0: old-W loads, bit 1: new-W stores carry the
  *                non-temporal hint (W is touched once per sweep, unlike the
  *                V rows, which are gathered 13 times), so that L2 keeps the
@@ -229,6 +231,10 @@ kpm_status kpm_moment_features(const double* mu, int32_t n_inst, int32_t R, int3
  *                rows a tile gathers belong to tiles of its own die, in its
  *                own L2), 1 each die a contiguous run of tile rows, 2 no die
  *                mapping.  Only the work distribution changes.
+ *   slab         staged-gather sweep: the passes walk the lattice in blocks
+ *                of this many y-lines, each block plane by plane, so that the
+ *                rows gathered for z neighbours were touched a few lines
+ *                earlier; 0 = natural row order; default 4
  * kpm_set_sweep_tuning(NULL) restores the defaults.  Errors: KPM_EINVAL
  * (negative field). */
 typedef struct {
@@ -242,6 +248,7 @@ typedef struct {
     int32_t lattice;
     int32_t gather;
     int32_t tile_order;
+    int32_t slab;
 } kpm_sweep_tuning;
 kpm_status kpm_set_sweep_tuning(const kpm_sweep_tuning* tuning);
 kpm_status kpm_get_sweep_tuning(kpm_sweep_tuning* tuning);
@@ -270,8 +277,8 @@ kpm_status kpm_sweep_profile_read(int64_t* count, double* total_ms, double* min_
  * identity to mu_0 .. mu_{M-1}.  One workgroup owns one instance from the
  * first sweep to its moments; instances are taken longest-first, so the
  * result of an instance is bitwise independent of the batch it is in and
- * of the tuning's mapping (it depends on `waves`, which fixes the order
- * of the sums).
+ * of the tuning's mapping (it depends on `waves` and `slab`, which fix the
+ * order of the sums).
  *   H:   host array [n_inst] of handles, all of one dtype, built on the
  *        current device; the same handle may appear more than once.
  *   V0:  host array [n_inst] of device start blocks [N_i][R] in that dtype
@@ -303,11 +310,15 @@ kpm_status kpm_moments_batched(const kpm_hamiltonian* const* H, const void* cons
  *              longest-first list through an atomic counter (greedy
  *              longest-processing-time); zero: workgroup g takes entries
  *              g, g + grid, ... of that list.
+ *   slab       a workgroup walks its instance's lattice in blocks of this
+ *              many y-lines, each block plane by plane (0 = natural row
+ *              order); default 4.  Only the order of work changes.
  * kpm_set_batch_tuning(NULL) restores the defaults.  Errors: KPM_EINVAL. */
 typedef struct {
     int32_t waves;
     int32_t wg_per_cu;
     int32_t dynamic;
+    int32_t slab;
 } kpm_batch_tuning;
 kpm_status kpm_set_batch_tuning(const kpm_batch_tuning* tuning);
 kpm_status kpm_get_batch_tuning(kpm_batch_tuning* tuning);

@@ -34,8 +34,8 @@ DEFAULT_CACHE = os.environ.get(
 DTYPE_NAMES = {0: "c128", 1: "c64"}
 
 SWEEP_FIELDS = ("wg_per_cu", "xcd_ways", "chunk_tiles", "pencil", "dynamic", "prefetch", "stream", "lattice",
-                "gather", "tile_order")
-BATCH_FIELDS = ("waves", "wg_per_cu", "dynamic")
+                "gather", "tile_order", "slab")
+BATCH_FIELDS = ("waves", "wg_per_cu", "dynamic", "slab")
 
 
 def size_bucket(n: int) -> int:
@@ -59,12 +59,13 @@ def width_key(dtype: int, S: int, N: int) -> str:
 def sweep_candidates(R: int, lattice_ok: bool) -> list[dict]:
     """Launch shapes of the fused sweep worth timing at block width R."""
     base = dict(wg_per_cu=0, xcd_ways=8, chunk_tiles=8, pencil=16, dynamic=0, prefetch=2, stream=3, lattice=0,
-                gather=1, tile_order=0)
+                gather=1, tile_order=0, slab=4)
     out = []
     # staged-gather sweep: workgroups per CU and die-aware ranges
     for wg in (0, 1, 2, 4):
         for xcd in (8, 1):
-            out.append(dict(base, wg_per_cu=wg, xcd_ways=xcd))
+            for slab in (0, 2, 4, 8):
+                out.append(dict(base, wg_per_cu=wg, xcd_ways=xcd, slab=slab))
     # scalar-operand sweep
     for wg in (4, 8):
         for chunk in (4, 8, 16):
@@ -89,7 +90,8 @@ def batch_candidates(max_waves: int = 16) -> list[dict]:
             if waves * per_cu > 32:
                 continue
             for dyn in (1, 0):
-                out.append(dict(waves=waves, wg_per_cu=per_cu, dynamic=dyn))
+                for slab in (0, 2, 4, 8):
+                    out.append(dict(waves=waves, wg_per_cu=per_cu, dynamic=dyn, slab=slab))
     return out
 
 

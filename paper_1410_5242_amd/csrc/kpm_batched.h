@@ -75,6 +75,62 @@ struct Shape {
     static constexpr bool kAhead = kLoadsV * kVecV + kLoadsC * kVecC <= 16;
 };
 
+// Order in which the passes of a sweep visit a lattice's rows (site n =
+// x + Lx (y + Ly z), rows 4n .. 4n + 3).  The lattice is cut into blocks of
+// `lines` consecutive y-lines; blocks are walked one after the other, each
+// plane by plane, so that the rows a pass gathers for its z neighbours were
+// touched one block-plane earlier (a few lines of the lattice instead of a
+// whole plane).  A block-plane is a contiguous row range; passes cover it in
+// pieces of rpw rows, the last piece possibly shorter.  lines >= Ly (or 0)
+// is the natural row order, one plane at a time.
+struct Slabs {
+    int64_t plane_rows = 0, line_rows = 0;
+    int64_t pf = 0, pl = 0;          // passes per block-plane: full block, last block
+    int64_t nfull = 0, npass = 0;    // passes in the full blocks, in total
+    int64_t rows_full = 0, rows_last = 0;
+    int Lz = 1, lines = 1, nblk = 0, rpw = 1;
+
+    __host__ __device__ void init(int Lx, int Ly, int Lz_, int lines_, int rpw_) {
+        Lz = Lz_;
+        rpw = rpw_;
+        lines = (lines_ <= 0 || lines_ > Ly) ? Ly : lines_;
+        line_rows = 4 * static_cast<int64_t>(Lx);
+        plane_rows = line_rows * Ly;
+        nblk = Ly / lines;
+        rows_full = line_rows * lines;
+        rows_last = line_rows * (Ly - nblk * lines);
+        pf = (rows_full + rpw - 1) / rpw;
+        pl = (rows_last + rpw - 1) / rpw;
+        nfull = static_cast<int64_t>(nblk) * Lz * pf;
+        npass = nfull + static_cast<int64_t>(Lz) * pl;
+    }
+    // first row of pass p and its number of rows (0 rows, first row past the
+    // lattice, for p >= npass)
+    __host__ __device__ void pass(int64_t p, int64_t& row0, int64_t& nrows) const {
+        if (p >= npass) {
+            row0 = plane_rows * Lz;
+            nrows = 0;
+            return;
+        }
+        int64_t b, r, per_plane, rows_blk;
+        if (p < nfull) {
+            per_plane = pf;
+            rows_blk = rows_full;
+            b = p / (static_cast<int64_t>(Lz) * pf);
+            r = p - b * Lz * pf;
+        } else {
+            per_plane = pl;
+            rows_blk = rows_last;
+            b = nblk;
+            r = p - nfull;
+        }
+        const int64_t z = r / per_plane, o = r - z * per_plane;
+        row0 = z * plane_rows + b * rows_full + o * rpw;
+        const int64_t left = rows_blk - o * rpw;
+        nrows = left < rpw ? left : rpw;
+    }
+};
+
 template <typename T, int R, int WAVES>
 constexpr int lds_bytes() {
     using S = Shape<T, R>;
@@ -159,7 +215,7 @@ constexpr int min_waves() {
 template <typename T, int R, int WAVES>
 __global__ void __launch_bounds__(64 * WAVES, (min_waves<T, R, WAVES>()))
 batched_kernel(const BatchInst* __restrict__ insts, const int32_t* __restrict__ order, int n_inst,
-               int* __restrict__ counter, int* __restrict__ flag, int M) {
+               int* __restrict__ counter, int* __restrict__ flag, int M, int slab) {
     using S = Shape<T, R>;
     constexpr int CPL = S::CPL;
     using LV = Lanes<T, CPL>;
@@ -196,7 +252,9 @@ batched_kernel(const BatchInst* __restrict__ insts, const int32_t* __restrict__ 
         if (idx >= n_inst) break;
         const BatchInst d = insts[order[idx]];
         const int64_t N = d.nrows;
-        const int64_t npass = (N + RPW - 1) / RPW;
+        Slabs sl;
+        sl.init(d.L[0], d.L[1], d.L[2], slab, RPW);
+        const int64_t npass = sl.npass;
         const uint64_t vbytes = static_cast<uint64_t>(N) * R * kCB;
         const __amdgpu_buffer_rsrc_t val_rs = rsrc(d.val, static_cast<uint64_t>(N) * kVW * 4);
         const __amdgpu_buffer_rsrc_t col_rs = rsrc(d.col, static_cast<uint64_t>(N) * kWidth * 4);
@@ -210,11 +268,11 @@ batched_kernel(const BatchInst* __restrict__ insts, const int32_t* __restrict__ 
                 Words<4>::store(Words<4>::load(src, 16 * i), dst, 16 * i);
         }
 
-        // words of pass q's matrix rows (values, then column indices); lanes
-        // past the end of a part fetch words that are never read
-        auto fetch = [&](int64_t q, typename WV::type* wv, typename WC::type* wc) {
-            const unsigned pv = static_cast<unsigned>(q) * (S::kV * 4);
-            const unsigned pc = static_cast<unsigned>(q) * (S::kC * 4);
+        // matrix rows of the pass starting at row r0 (values, then column
+        // indices); lanes past the end of a part fetch words that are never read
+        auto fetch = [&](int64_t r0, typename WV::type* wv, typename WC::type* wc) {
+            const unsigned pv = static_cast<unsigned>(r0) * (kVW * 4);
+            const unsigned pc = static_cast<unsigned>(r0) * (kWidth * 4);
 #pragma unroll
             for (int i = 0; i < S::kLoadsV; ++i)
                 wv[i] = WV::load(val_rs, pv + (lane + 64 * i) * (4 * S::kVecV));
@@ -247,14 +305,16 @@ batched_kernel(const BatchInst* __restrict__ insts, const int32_t* __restrict__ 
             typename WV::type wv[S::kLoadsV];
             typename WC::type wc[S::kLoadsC];
             int buf = 0;
+            int64_t row0, nr;
+            sl.pass(wave, row0, nr);
             if constexpr (S::kAhead) {
-                fetch(wave, wv, wc);
+                fetch(row0, wv, wc);
                 put(stage[wave][0], wv, wc);
             }
             for (int64_t q = wave; q < npass; q += WAVES) {
                 if constexpr (!S::kAhead) {
                     wave_sync();   // every lane has read the slot before it is refilled
-                    fetch(q, wv, wc);
+                    fetch(row0, wv, wc);
                     put(stage[wave][0], wv, wc);
                 }
                 wave_sync();
@@ -266,11 +326,16 @@ batched_kernel(const BatchInst* __restrict__ insts, const int32_t* __restrict__ 
                     const unsigned c = static_cast<unsigned>(st[S::kColOff + sub * kWidth + j]);
                     v[j] = LV::load(vrs, (c * R + cc * CPL) * kCB);
                 }
-                const int64_t row = q * RPW + sub;
-                const unsigned off = static_cast<unsigned>(row * R + cc * CPL) * kCB;
+                const int64_t row = row0 + sub;
+                const bool act = sub < nr;
+                // rows past the end of the pass: an offset past the block, so
+                // the old-W load reads zero and the store is dropped
+                const unsigned off = act ? static_cast<unsigned>(row * R + cc * CPL) * kCB : 0xFFFFFFF0u;
                 const Cv wo = LV::load(wold_rs, off);
                 // matrix rows of this wave's next pass (zeros past the end)
-                if constexpr (S::kAhead) fetch(q + WAVES, wv, wc);
+                int64_t row0n, nrn;
+                sl.pass(q + WAVES, row0n, nrn);
+                if constexpr (S::kAhead) fetch(row0n, wv, wc);
                 const int* sv = st + sub * kVW;
                 Cv acc;
 #pragma unroll
@@ -293,7 +358,6 @@ batched_kernel(const BatchInst* __restrict__ insts, const int32_t* __restrict__ 
                 for (int e = 0; e < 2 * CPL; ++e) wn[e] = fma(alpha, acc[e], beta * v[0][e]) - wo[e];
                 // rows past N: the store is dropped, the products masked
                 LV::store(wn, wrs, off);
-                const bool act = row < N;
 #pragma unroll
                 for (int t = 0; t < CPL; ++t) {
                     const double vr = act ? static_cast<double>(v[0][2 * t]) : 0.0;
@@ -307,6 +371,8 @@ batched_kernel(const BatchInst* __restrict__ insts, const int32_t* __restrict__ 
                     put(stage[wave][buf ^ 1], wv, wc);
                     buf ^= 1;
                 }
+                row0 = row0n;
+                nr = nrn;
             }
             // lanes cc, cc + LPR, ... of a wave hold the same columns
 #pragma unroll
@@ -354,7 +420,8 @@ template <typename T, int R, int WAVES>
 hipError_t launch_waves(const BatchArgs& a, hipStream_t s) {
     if constexpr (instantiable<T, R, WAVES>()) {
         batched_kernel<T, R, WAVES><<<a.grid, 64 * WAVES, 0, s>>>(a.inst, a.order, a.n_inst,
-                                                                  a.dynamic ? a.counter : nullptr, a.flag, a.M);
+                                                                  a.dynamic ? a.counter : nullptr, a.flag, a.M,
+                                                                  a.slab);
         return hipGetLastError();
     } else {
         return hipErrorInvalidValue;

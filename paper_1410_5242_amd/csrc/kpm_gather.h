@@ -12,6 +12,10 @@
 // needs far fewer vector-memory instructions per block row when R < 32,
 // which is what limits a gather-heavy sweep on gfx950.
 //
+// Order: the passes walk the lattice in blocks of `slab` y-lines, each block
+// plane by plane (batch::Slabs), so that the V rows gathered for the z
+// neighbours of a pass were touched a few lines earlier and are still in L2.
+//
 // Work distribution: the passes are split into xcd_ways contiguous ranges,
 // workgroup g takes range g % xcd_ways (the die the dispatcher deals it to)
 // and its waves interleave over the range, so that the rows a die gathers
@@ -54,7 +58,7 @@ template <typename T, int R, int WAVES, int VARIANT>
 __global__ void __launch_bounds__(64 * WAVES, (min_waves<T, R, WAVES>()))
 gather_sweep_kernel(const T* __restrict__ val, const int32_t* __restrict__ col, int64_t N,
                     const T* __restrict__ V, T* __restrict__ W, T alpha, T beta, T gamma,
-                    double* __restrict__ partials, int xcd_ways) {
+                    double* __restrict__ partials, int xcd_ways, int Lx, int Ly, int Lz, int lines) {
     using S = Shape<T, R>;
     constexpr int CPL = S::CPL;
     using LV = Lanes<T, CPL>;
@@ -80,7 +84,9 @@ gather_sweep_kernel(const T* __restrict__ val, const int32_t* __restrict__ col, 
     const int X = (xcd_ways > 1 && ngrid % xcd_ways == 0) ? xcd_ways : 1;
     const int xcd = blockIdx.x % X;
     const int per = ngrid / X;
-    const int64_t npass = (N + RPW - 1) / RPW;
+    batch::Slabs sl;
+    sl.init(Lx, Ly, Lz, lines, RPW);
+    const int64_t npass = sl.npass;
     const int64_t lo = npass * xcd / X, hi = npass * (xcd + 1) / X;
     const int64_t stride = static_cast<int64_t>(per) * WAVES;
     const int64_t q0 = lo + static_cast<int64_t>(blockIdx.x / X) * WAVES + wave;
@@ -94,10 +100,11 @@ gather_sweep_kernel(const T* __restrict__ val, const int32_t* __restrict__ col, 
     const bool need_w = VARIANT != KPM_PLAIN && gamma != T(0);
     const __amdgpu_buffer_rsrc_t wold_rs = rsrc(W, need_w ? vbytes : 0);
 
-    auto fetch = [&](int64_t q, typename WV::type* wv, typename WC::type* wc) {
-        // passes past the die's range (read-ahead) fetch whatever lies there: never read
-        const unsigned pv = static_cast<unsigned>(q) * (S::kV * 4);
-        const unsigned pc = static_cast<unsigned>(q) * (S::kC * 4);
+    // matrix rows of the pass starting at row r0 (values, then column
+    // indices); lanes past the end of a part fetch words that are never read
+    auto fetch = [&](int64_t r0, typename WV::type* wv, typename WC::type* wc) {
+        const unsigned pv = static_cast<unsigned>(r0) * (kVW * 4);
+        const unsigned pc = static_cast<unsigned>(r0) * (kWidth * 4);
 #pragma unroll
         for (int i = 0; i < S::kLoadsV; ++i) wv[i] = WV::load(val_rs, pv + (lane + 64 * i) * (4 * S::kVecV));
 #pragma unroll
@@ -118,14 +125,16 @@ gather_sweep_kernel(const T* __restrict__ val, const int32_t* __restrict__ col, 
     typename WV::type wv[S::kLoadsV];
     typename WC::type wc[S::kLoadsC];
     int buf = 0;
+    int64_t row0, nr;
+    sl.pass(q0, row0, nr);
     if constexpr (S::kAhead) {
-        fetch(q0, wv, wc);
+        fetch(row0, wv, wc);
         put(stage[wave][0], wv, wc);
     }
     for (int64_t q = q0; q < hi; q += stride) {
         if constexpr (!S::kAhead) {
             wave_sync();
-            fetch(q, wv, wc);
+            fetch(row0, wv, wc);
             put(stage[wave][0], wv, wc);
         }
         wave_sync();
@@ -136,10 +145,15 @@ gather_sweep_kernel(const T* __restrict__ val, const int32_t* __restrict__ col, 
             const unsigned c = static_cast<unsigned>(st[S::kColOff + sub * kWidth + j]);
             v[j] = LV::load(vrs, (c * R + cc * CPL) * kCB);
         }
-        const int64_t row = q * RPW + sub;
-        const unsigned off = static_cast<unsigned>(row * R + cc * CPL) * kCB;
+        const int64_t row = row0 + sub;
+        const bool act = sub < nr;
+        // rows past the end of the pass: an offset past the block, so the
+        // old-W load reads zero and the store is dropped
+        const unsigned off = act ? static_cast<unsigned>(row * R + cc * CPL) * kCB : 0xFFFFFFF0u;
         const Cv wo = LV::load(wold_rs, off);
-        if constexpr (S::kAhead) fetch(q + stride, wv, wc);
+        int64_t row0n, nrn;
+        sl.pass(q + stride, row0n, nrn);
+        if constexpr (S::kAhead) fetch(row0n, wv, wc);
         const int* sv = st + sub * kVW;
         Cv acc;
 #pragma unroll
@@ -165,7 +179,6 @@ gather_sweep_kernel(const T* __restrict__ val, const int32_t* __restrict__ col, 
         // rows past N: the store is dropped (offset beyond the block), products masked
         LV::store(wn, wrs, off);
         if constexpr (VARIANT == KPM_FULL) {
-            const bool act = row < N;
 #pragma unroll
             for (int t = 0; t < CPL; ++t) {
                 const double vr = act ? static_cast<double>(v[0][2 * t]) : 0.0;
@@ -180,6 +193,8 @@ gather_sweep_kernel(const T* __restrict__ val, const int32_t* __restrict__ col, 
             put(stage[wave][buf ^ 1], wv, wc);
             buf ^= 1;
         }
+        row0 = row0n;
+        nr = nrn;
     }
     if constexpr (VARIANT == KPM_FULL) {
 #pragma unroll
@@ -212,7 +227,8 @@ hipError_t launch_v(const SweepArgs& a, hipStream_t s) {
     if constexpr (instantiable<T, R, WAVES>()) {
         gather_sweep_kernel<T, R, WAVES, VARIANT><<<a.grid, 64 * WAVES, 0, s>>>(
             static_cast<const T*>(a.val), a.col, a.nrows, static_cast<const T*>(a.V), static_cast<T*>(a.W),
-            static_cast<T>(a.alpha), static_cast<T>(a.beta), static_cast<T>(a.gamma), a.partials, a.xcd_ways);
+            static_cast<T>(a.alpha), static_cast<T>(a.beta), static_cast<T>(a.gamma), a.partials, a.xcd_ways,
+            a.L[0], a.L[1], a.L[2], a.slab);
         return hipGetLastError();
     } else {
         return hipErrorInvalidValue;

@@ -78,6 +78,8 @@ struct SweepArgs {
     int chunk = 1;
     int prefetch = 1;
     int stream = 0;
+    int L[3] = {0, 0, 0};   // lattice sides of H (rows 4 (x + Lx (y + Ly z)) + o)
+    int slab = 0;           // staged-gather sweep: y-lines per block of the pass order
 };
 
 // Cache-blocked sweep for the library's lattice Hamiltonians at R = 32.
@@ -111,6 +113,8 @@ struct BatchInst {
     int64_t nrows;          // N
     double inv_a;           // 1/a
     double shift;           // b/a
+    int32_t L[3];           // lattice sides (rows 4 (x + Lx (y + Ly z)) + o)
+    int32_t pad;
 };
 
 struct BatchArgs {
@@ -123,6 +127,7 @@ struct BatchArgs {
     int grid;
     int waves;              // waves per workgroup: 4, 8 or 16
     int dynamic;
+    int slab;               // y-lines per block of the pass order (0: natural order)
 };
 hipError_t launch_batched(int dtype, int R, const BatchArgs& a, hipStream_t s);
 // Largest workgroup (in waves, <= 16) that can run this dtype and R.

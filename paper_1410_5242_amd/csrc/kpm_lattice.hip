@@ -14,11 +14,27 @@
 // sites lives in LDS, so the diagonal, both z neighbours and every in-tile x
 // and y neighbour are read from LDS; only neighbours across the tile edge
 // are gathered from memory (and mostly hit L2, since the adjacent tiles of
-// a die fetch the same plane at the same time).  While plane s is
-// computed, plane s + 2 of V and the old W rows and matrix rows of plane
-// s + 1 are already in flight, so a step waits only on its own
-// edge-neighbour loads.  Matrix values are read once per sweep; the column
-// indices are implied by the slot order and are not read.
+// a die fetch the same plane at the same time).  Matrix values are read
+// once per sweep; the column indices are implied by the slot order and are
+// not read.
+//
+// Pipelining.  During step s a wave has in flight: V of plane s + 2 (stored
+// to the ring at the end of the step), the edge neighbours and matrix record
+// of step s + 1, and (issued after the compute) the old W rows of step
+// s + 1.  Three rules keep those loads in flight instead of being waited on
+// early:
+//   * every wave issues the same memory instructions every step: an access
+//     that must not happen uses a buffer descriptor of size 0 (loads read 0,
+//     stores are dropped) instead of a branch, so the compiler's counts of
+//     outstanding memory operations stay exact;
+//   * the register sets of consecutive steps alternate (the step loop is
+//     unrolled by two), so no value is copied out of a register whose load
+//     is still pending;
+//   * per axis, the neighbour that may lie across the tile edge ("outer")
+//     is always taken from registers and the other ("inner") from LDS; which
+//     matrix slots they pair with is wave-uniform and is resolved by where
+//     the scalar words are fetched from (or which lane is read), so the
+//     product loop has no data-dependent selects.
 //
 // Work distribution: tiles are numbered row-major over the tile grid and
 // split into 8 contiguous ranges; workgroup g takes range g % 8 (the die the
@@ -47,8 +63,35 @@ __device__ inline T gload(__amdgpu_buffer_rsrc_t rs, int lane, int64_t row) {
                                  static_cast<unsigned>(row * kE * static_cast<int64_t>(sizeof(T))));
 }
 
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+
+// Row `row` of W through a buffer descriptor (one lane offset VGPR shared by
+// every access); NT selects the non-temporal cache policy.
+template <typename T, bool NT>
+__device__ inline T wload(__amdgpu_buffer_rsrc_t rs, int lane, int64_t row) {
+    const unsigned voff = static_cast<unsigned>(lane * sizeof(T));
+    const unsigned soff = static_cast<unsigned>(row * kE * static_cast<int64_t>(sizeof(T)));
+    constexpr int aux = NT ? 2 : 0;
+    if constexpr (sizeof(T) == 8)
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(rs, voff, soff, aux));
+    else
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(rs, voff, soff, aux));
+}
+template <typename T, bool NT>
+__device__ inline void wstore(T x, __amdgpu_buffer_rsrc_t rs, int lane, int64_t row) {
+    const unsigned voff = static_cast<unsigned>(lane * sizeof(T));
+    const unsigned soff = static_cast<unsigned>(row * kE * static_cast<int64_t>(sizeof(T)));
+    constexpr int aux = NT ? 2 : 0;
+    if constexpr (sizeof(T) == 8)
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, x), rs, voff, soff, aux);
+    else
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), rs, voff, soff, aux);
+}
+
 // The matrix rows of one site (4 rows x 13 complex entries) are one
-// contiguous record; lane l < 52 of a wave loads entry l % 13 of row l / 13
+// contiguous record; lane l < 52 of a wave loads the entry of row l / 13
+// that product l % 13 of that row needs (lane_off; lanes past 52 repeat the
+// last entry)
 // (16 bytes in complex128, 8 in complex64) with a single vector load, and
 // v_readlane hands each entry to the FMAs as a wave-uniform scalar operand.
 // Unlike scalar loads (which complete out of order, so every wait drains all
@@ -56,8 +99,9 @@ __device__ inline T gload(__amdgpu_buffer_rsrc_t rs, int lane, int64_t row) {
 template <typename T> struct SiteRec;
 template <> struct SiteRec<double> {
     using V = int4;
-    static __device__ V load(const double* site_vals, int lane) {
-        return lane < 4 * kWidth ? reinterpret_cast<const int4*>(site_vals)[lane] : int4{0, 0, 0, 0};
+    static __device__ V load(__amdgpu_buffer_rsrc_t rs, unsigned lane_off, int64_t site) {
+        const auto w = __builtin_amdgcn_raw_buffer_load_b128(rs, lane_off, static_cast<unsigned>(site * 4 * kWidth * 16), 0);
+        return int4{static_cast<int>(w[0]), static_cast<int>(w[1]), static_cast<int>(w[2]), static_cast<int>(w[3])};
     }
     static __device__ double re(const V& v, int l) {
         return __hiloint2double(__builtin_amdgcn_readlane(v.y, l), __builtin_amdgcn_readlane(v.x, l));
@@ -68,12 +112,44 @@ template <> struct SiteRec<double> {
 };
 template <> struct SiteRec<float> {
     using V = int2;
-    static __device__ V load(const float* site_vals, int lane) {
-        return lane < 4 * kWidth ? reinterpret_cast<const int2*>(site_vals)[lane] : int2{0, 0};
+    static __device__ V load(__amdgpu_buffer_rsrc_t rs, unsigned lane_off, int64_t site) {
+        const auto w = __builtin_amdgcn_raw_buffer_load_b64(rs, lane_off, static_cast<unsigned>(site * 4 * kWidth * 8), 0);
+        return int2{static_cast<int>(w[0]), static_cast<int>(w[1])};
     }
     static __device__ float re(const V& v, int l) { return __int_as_float(__builtin_amdgcn_readlane(v.x, l)); }
     static __device__ float im(const V& v, int l) { return __int_as_float(__builtin_amdgcn_readlane(v.y, l)); }
 };
+
+// Exchange with lane ^ 1 (DPP quad_perm [1, 0, 3, 2]); every lane of the wave
+// is active in this kernel, so the "old" operand is never used.
+__device__ inline double swap_lanes(double x) {
+    const int lo = __double2loint(x), hi = __double2hiint(x);
+    return __hiloint2double(__builtin_amdgcn_update_dpp(hi, hi, 0xB1, 0xF, 0xF, false),
+                            __builtin_amdgcn_update_dpp(lo, lo, 0xB1, 0xF, 0xF, false));
+}
+__device__ inline float swap_lanes(float x) {
+    const int b = __float_as_int(x);
+    return __int_as_float(__builtin_amdgcn_update_dpp(b, b, 0xB1, 0xF, 0xF, false));
+}
+
+// Values a step carries for the next one: V rows of the (at most two)
+// neighbours across the tile edge, old W rows, and the matrix-row record.
+template <typename T> struct StepRegs {
+    T h[2][4];
+    T w[4];
+    typename SiteRec<T>::V hv;   // VALS 1
+    unsigned warm;               // VALS 2
+};
+
+// VALS 2: one dword of every 128-byte line that the site's matrix record
+// (4 rows x 13 complex entries) touches; lanes past the last line repeat the
+// record's last dword.
+template <typename T>
+__device__ inline unsigned warm_load(__amdgpu_buffer_rsrc_t rs, int lane, int64_t site) {
+    constexpr int kRec = 4 * kWidth * 2 * static_cast<int>(sizeof(T));
+    const unsigned voff = static_cast<unsigned>(min(lane * 128, kRec - 4));
+    return __builtin_amdgcn_raw_buffer_load_b32(rs, voff, static_cast<unsigned>(site * kRec), 2);
+}
 
 // Neighbour in the x-y plane: absent (open side), in this tile (LDS, local
 // wave index) or outside it (global, site index within a plane).
@@ -120,6 +196,7 @@ lattice_kernel(const T* __restrict__ val, const T* __restrict__ V, T* __restrict
                T alpha, T beta, T gamma, double* __restrict__ partials,
                int Lx, int Ly, int Lz, int px, int py, int pz, int ntx, int ntiles, int order) {
     __shared__ T ring[4][kNW][4][kE];
+    __shared__ T zrow[4][kE];          // rows of zeros: neighbours beyond an open side
     __shared__ double red[kNW][3][kR];
 
     const int lane = threadIdx.x & 63;
@@ -130,10 +207,27 @@ lattice_kernel(const T* __restrict__ val, const T* __restrict__ V, T* __restrict
     const bool need_w = VARIANT != KPM_PLAIN && gamma != T(0);
     constexpr int kValWords = 2 * kWidth * static_cast<int>(sizeof(T)) / 4;
     constexpr int wpv = static_cast<int>(sizeof(T)) / 4;
-    const v4i32 val_rs = scalar_rsrc(val, 0xFFFFFFFFu);
-    const __amdgpu_buffer_rsrc_t vrs = __builtin_amdgcn_make_buffer_rsrc(
-        const_cast<T*>(V), 0, static_cast<int>(0xFFFFFFFFu), sweep::kBufferWord3);
     const int64_t plane_sites = static_cast<int64_t>(Lx) * Ly;
+    const int64_t nrows = 4 * plane_sites * Lz;
+    // Every global access goes through a buffer descriptor clipped to its
+    // array.  An access that must not happen (inactive wave, step past the
+    // end of the pencil, no halo neighbour, no old W) uses a descriptor of
+    // size 0: loads return 0 and stores are dropped, so every wave issues
+    // the same sequence of memory instructions each step and the compiler's
+    // memory-counter waits stay exact.
+    const unsigned vbytes = static_cast<unsigned>(nrows * kE * static_cast<int64_t>(sizeof(T)));
+    const unsigned mbytes = static_cast<unsigned>(nrows * 2 * kWidth * static_cast<int64_t>(sizeof(T)));
+    auto rsrc = [](const void* p, unsigned bytes) {
+        return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, static_cast<int>(bytes),
+                                                 sweep::kBufferWord3);
+    };
+    // descriptors are rebuilt where used (only the size word differs), which
+    // keeps fewer scalar registers live than holding both variants
+    auto vrs = [&](bool on) { return rsrc(V, on ? vbytes : 0u); };
+    auto wrs = [&](bool on) { return rsrc(W, on ? vbytes : 0u); };
+    auto mrs = [&](bool on) { return rsrc(val, on ? mbytes : 0u); };
+
+    if (wave < 4) zrow[wave][lane] = T(0);
 
     double acc_e = 0.0, acc_or = 0.0, acc_oi = 0.0;
 
@@ -164,167 +258,214 @@ lattice_kernel(const T* __restrict__ val, const T* __restrict__ V, T* __restrict
         const int Lxv = min(kP, Lx - x0), Lyv = min(kP, Ly - y0);   // valid extent of the tile (>= 2)
         const int x = x0 + ti, y = y0 + tj;
         const bool active = ti < Lxv && tj < Lyv;                     // wave-uniform
-        const int64_t sxy = static_cast<int64_t>(x) + static_cast<int64_t>(Lx) * y;
+        // an inactive wave (tile cut by the lattice edge) runs the same code
+        // on its own ring slot (zeros) with every global access disabled
+        const int64_t sxy = active ? static_cast<int64_t>(x) + static_cast<int64_t>(Lx) * y : 0;
         Nb nb[4];
         nb[0] = xy_neighbour(x - 1, y, Lx, Ly, px, py, x0, y0, Lxv, Lyv);
         nb[1] = xy_neighbour(x + 1, y, Lx, Ly, px, py, x0, y0, Lxv, Lyv);
         nb[2] = xy_neighbour(x, y - 1, Lx, Ly, px, py, x0, y0, Lxv, Lyv);
         nb[3] = xy_neighbour(x, y + 1, Lx, Ly, px, py, x0, y0, Lxv, Lyv);
         // A tile is at least 2 sites wide in x and y, so a site has at most
-        // one neighbour across the tile edge in x and one in y: halo slot 0
-        // holds the x one (direction hx), slot 1 the y one (direction hy).
-        const int hx = nb[0].kind == 2 ? 0 : (nb[1].kind == 2 ? 1 : -1);
-        const int hy = nb[2].kind == 2 ? 2 : (nb[3].kind == 2 ? 3 : -1);
+        // one neighbour across the tile edge in x and one in y.  Per axis,
+        // the "outer" neighbour lives in registers (r.h[axis]): the one
+        // across the tile edge, gathered from memory a step ahead, else
+        // (interior site, or a side beyond an open boundary) copied from LDS
+        // at the start of the step.  The "inner" one is read from LDS (ring
+        // slot of an in-tile site, or zero rows).  Only constant indices into
+        // nb: a run-time index would place the array in scratch memory.
+        auto outer_of = [&](const Nb& m, const Nb& p) -> int {
+            if (m.kind == 2) return 0;
+            if (p.kind == 2) return 1;
+            if (p.kind == 0) return 1;
+            if (m.kind == 0) return 0;
+            return 1;
+        };
+        const int dox = outer_of(nb[0], nb[1]), doy = outer_of(nb[2], nb[3]);
+        const Nb ox = dox ? nb[1] : nb[0], ix = dox ? nb[0] : nb[1];
+        const Nb oy = doy ? nb[3] : nb[2], iy = doy ? nb[2] : nb[3];
+        const bool hx_on = active && ox.kind == 2, hy_on = active && oy.kind == 2;
+        // VALS 1: lane l holds the matrix entry of product l % 13 of row l / 13
+        // (product order: slot 0, outer x pair, inner x pair, outer y pair,
+        // inner y pair, slots 9..12), so every hand-over reads a fixed lane
+        unsigned rec_off = 0;
+        if constexpr (VALS == 1) {
+            const int e = min(lane, 4 * kWidth - 1), r = e / kWidth, j = e % kWidth;
+            int sl = j;
+            if (j >= 1 && j <= 4) sl = (j <= 2) ? j + 2 * dox : j - 2 * dox;
+            if (j >= 5 && j <= 8) sl = (j <= 6) ? j + 2 * doy : j - 2 * doy;
+            rec_off = static_cast<unsigned>((r * kWidth + sl) * 2 * static_cast<int>(sizeof(T)));
+        }
+        const int64_t hxs = hx_on ? ox.idx : 0;   // halo sites (within a plane)
+        const int64_t hys = hy_on ? oy.idx : 0;
+        const __amdgpu_buffer_rsrc_t wst = wrs(active);   // new-W stores
+        const v4i32 val_rs = scalar_rsrc(val, active ? mbytes : 0u);
 
         // plane index of step s' (with periodic wrap); -1 when it does not exist
         auto plane_of = [&](int sp) -> int {
             if (sp >= 0 && sp < Lz) return sp;
             return pz ? (sp + Lz) % Lz : -1;
         };
-        // the four rows of each halo neighbour of this site in plane zp
-        auto load_halo = [&](int zp, T (&h)[2][4]) {
-            if (hx >= 0) {
-                const int64_t nbase = 4 * (static_cast<int64_t>(nb[hx].idx) + plane_sites * zp);
+        // halo neighbours, old W rows and (VALS 1) matrix rows of the step in
+        // plane zp (on = the step exists)
+        auto load_step = [&](bool on, int zp, StepRegs<T>& r) {
+            const int64_t z = on ? zp : 0;
+            const __amdgpu_buffer_rsrc_t hx = vrs(on && hx_on);
+            const __amdgpu_buffer_rsrc_t hy = vrs(on && hy_on);
 #pragma unroll
-                for (int o = 0; o < 4; ++o) h[0][o] = gload<T>(vrs, lane, nbase + o);
-            }
-            if (hy >= 0) {
-                const int64_t nbase = 4 * (static_cast<int64_t>(nb[hy].idx) + plane_sites * zp);
+            for (int o = 0; o < 4; ++o) r.h[0][o] = gload<T>(hx, lane, 4 * (hxs + plane_sites * z) + o);
 #pragma unroll
-                for (int o = 0; o < 4; ++o) h[1][o] = gload<T>(vrs, lane, nbase + o);
-            }
+            for (int o = 0; o < 4; ++o) r.h[1][o] = gload<T>(hy, lane, 4 * (hys + plane_sites * z) + o);
+            const int64_t base = 4 * (sxy + plane_sites * z);
+            if constexpr (VALS == 1) r.hv = SiteRec<T>::load(mrs(on && active), rec_off, base / 4);
+        };
+        // this site's rows of V in plane zp (zeros when off)
+        auto load_wold = [&](bool on, int zp, StepRegs<T>& r) {
+            const __amdgpu_buffer_rsrc_t wl = wrs(on && active && need_w);
+            const int64_t base = 4 * (sxy + plane_sites * (on ? zp : 0));
+#pragma unroll
+            for (int o = 0; o < 4; ++o) r.w[o] = wload<T, (STREAM & 1) != 0>(wl, lane, base + o);
+        };
+        auto load_plane = [&](bool on, int zp, T (&p)[4]) {
+            const __amdgpu_buffer_rsrc_t rs = vrs(on && active);
+            const int64_t base = 4 * (sxy + plane_sites * (on ? zp : 0));
+#pragma unroll
+            for (int o = 0; o < 4; ++o) p[o] = gload<T>(rs, lane, base + o);
         };
 
-        // prologue: planes -1, 0, 1 into ring slots 3, 0, 1; halo, old W and
-        // matrix rows of step 0
-        T h_c[2][4], w_c[4];
-        typename SiteRec<T>::V hv_c{};
-        if (active) {
-            for (int sp = -1; sp <= 1; ++sp) {
-                const int zp = plane_of(sp);
-                if (zp < 0) continue;
-                const int64_t base = 4 * (sxy + plane_sites * zp);
+        // One z-step.  Register sets alternate between even and odd steps,
+        // so nothing is copied out of a set whose loads are still in flight:
+        //   cur    halo, old W and matrix rows of step s (loaded in step s - 1)
+        //   nxt    receives those of step s + 1
+        //   p      receives V of plane s + 2, stored to the ring at the end
+        //          of the step
+        // Loads are issued warm-up first, then the plane, then the rest, so
+        // the waits at the end of the step leave the later loads in flight.
+        auto step = [&](int s, StepRegs<T>& cur, StepRegs<T>& nxt) {
+            const bool on1 = s + 1 < Lz;                       // step s + 1 exists
+            const int zn2 = on1 ? plane_of(s + 2) : -1;        // plane used by step s + 1
+            T p[4];
+            if constexpr (VALS == 2)
+                nxt.warm = warm_load<T>(mrs(on1 && active), lane, sxy + plane_sites * (on1 ? s + 1 : 0));
+            load_plane(zn2 >= 0, zn2, p);
+            load_step(on1, s + 1, nxt);
+
+            // outer neighbours not gathered from memory: copy from LDS
+            if (ox.kind != 2) {
+                const T* src = ox.kind == 1 ? &ring[s & 3][ox.idx][0][lane] : &zrow[0][lane];
 #pragma unroll
-                for (int o = 0; o < 4; ++o) ring[sp & 3][wave][o][lane] = gload<T>(vrs, lane, base + o);
+                for (int o = 0; o < 4; ++o) cur.h[0][o] = src[o * kE];
             }
-            load_halo(0, h_c);
-            const int64_t base = 4 * sxy;
+            if (oy.kind != 2) {
+                const T* src = oy.kind == 1 ? &ring[s & 3][oy.idx][0][lane] : &zrow[0][lane];
+#pragma unroll
+                for (int o = 0; o < 4; ++o) cur.h[1][o] = src[o * kE];
+            }
+            const T* inx = ix.kind == 1 ? &ring[s & 3][ix.idx][0][lane] : &zrow[0][lane];
+            const T* iny = iy.kind == 1 ? &ring[s & 3][iy.idx][0][lane] : &zrow[0][lane];
+            const T* zdn = plane_of(s - 1) >= 0 ? &ring[(s - 1) & 3][wave][0][lane] : &zrow[0][lane];
+            const T* zup = plane_of(s + 1) >= 0 ? &ring[(s + 1) & 3][wave][0][lane] : &zrow[0][lane];
+            const int64_t site = sxy + plane_sites * s;
 #pragma unroll
             for (int o = 0; o < 4; ++o) {
-                if constexpr (STREAM & 1) w_c[o] = need_w ? __builtin_nontemporal_load(W + (base + o) * kE + lane) : T(0);
-                else w_c[o] = need_w ? W[(base + o) * kE + lane] : T(0);
+                const int64_t row = 4 * site + o;
+                // matrix entries as scalar words, in product order: slot 0,
+                // the outer and inner x pairs, the outer and inner y pairs,
+                // slots 9..12.  Which pair is outer is wave-uniform (dox,
+                // doy) and is chosen by where the words are loaded from, not
+                // by moving vector data.
+                int wv[VEC_VALS ? 1 : kValWords];
+                if constexpr (!VEC_VALS) {
+                    constexpr int SW = 2 * wpv;   // words per slot
+                    const unsigned rb = static_cast<unsigned>(row * kValWords * 4);
+                    sload<SW>(val_rs, rb, wv);
+                    sload<2 * SW>(val_rs, rb + (1 + 2 * dox) * SW * 4, wv + SW);
+                    sload<2 * SW>(val_rs, rb + (3 - 2 * dox) * SW * 4, wv + 3 * SW);
+                    sload<2 * SW>(val_rs, rb + (5 + 2 * doy) * SW * 4, wv + 5 * SW);
+                    sload<2 * SW>(val_rs, rb + (7 - 2 * doy) * SW * 4, wv + 7 * SW);
+                    sload<4 * SW>(val_rs, rb + 9 * SW * 4, wv + 9 * SW);
+                }
+                T v[kWidth];
+                v[0] = ring[s & 3][wave][o][lane];
+                v[1] = cur.h[0][o];
+                v[2] = cur.h[0][o ^ 3];
+                v[3] = inx[o * kE];
+                v[4] = inx[(o ^ 3) * kE];
+                v[5] = cur.h[1][o];
+                v[6] = cur.h[1][o ^ 3];
+                v[7] = iny[o * kE];
+                v[8] = iny[(o ^ 3) * kE];
+                v[9] = zdn[o * kE];
+                v[10] = zdn[(o ^ 2) * kE];
+                v[11] = zup[o * kE];
+                v[12] = zup[(o ^ 2) * kE];
+                T A = T(0), B = T(0);
+                if constexpr (VEC_VALS) {
+#pragma unroll
+                    for (int j = 0; j < kWidth; ++j) {
+                        A = fma(SiteRec<T>::re(cur.hv, kWidth * o + j), v[j], A);
+                        B = fma(SiteRec<T>::im(cur.hv, kWidth * o + j), v[j], B);
+                    }
+                } else {
+#pragma unroll
+                    for (int j = 0; j < kWidth; ++j) {
+                        A = fma(from_words<T>(wv + (2 * j) * wpv), v[j], A);
+                        B = fma(from_words<T>(wv + (2 * j + 1) * wpv), v[j], B);
+                    }
+                }
+                const T hv = fma(sgn, swap_lanes(B), A);
+                if constexpr (VARIANT == KPM_PLAIN) {
+                    wstore<T, (STREAM & 2) != 0>(hv, wst, lane, row);
+                } else {
+                    // cur.w holds zeros when no old W is read (need_w false)
+                    const T w = fma(gamma, cur.w[o], fma(alpha, hv, beta * v[0]));
+                    wstore<T, (STREAM & 2) != 0>(w, wst, lane, row);
+                    if constexpr (VARIANT == KPM_FULL) {
+                        const double vd = static_cast<double>(v[0]);
+                        const double vsw = static_cast<double>(swap_lanes(v[0]));
+                        const double wd = static_cast<double>(w);
+                        acc_e = fma(vd, vd, acc_e);
+                        acc_or = fma(wd, vd, acc_or);
+                        acc_oi = fma(wd, vsw, acc_oi);
+                    }
+                }
             }
-            if constexpr (VEC_VALS) hv_c = SiteRec<T>::load(val + base * 2 * kWidth, lane);
+            // plane s + 2 (zeros when it does not exist) replaces plane s - 2,
+            // last read in step s - 1
+            load_wold(on1, s + 1, nxt);
+#pragma unroll
+            for (int o = 0; o < 4; ++o) ring[(s + 2) & 3][wave][o][lane] = p[o];
+            // VALS 2: consume the warm-up load (older than the plane just stored)
+            if constexpr (VALS == 2) sink ^= static_cast<unsigned>(__builtin_amdgcn_readfirstlane(nxt.warm));
+            __syncthreads();
+        };
+
+        // prologue: planes -1, 0, 1 into ring slots 3, 0, 1 (zeros where a
+        // plane does not exist); halo, old W and matrix rows of step 0
+        {
+            T q[3][4];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const int zp = plane_of(i - 1);
+                load_plane(zp >= 0, zp, q[i]);
+            }
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+#pragma unroll
+                for (int o = 0; o < 4; ++o) ring[(i + 3) & 3][wave][o][lane] = q[i][o];
+            }
         }
+        StepRegs<T> ra, rb;
+        load_step(true, 0, ra);
+        load_wold(true, 0, ra);
         __syncthreads();
 
-        for (int s = 0; s < Lz; ++s) {
-            // Loads for later steps only: the halo and old W rows of step
-            // s + 1, plane s + 2 and (VALS 1, 2) the matrix rows of step s + 1.
-            // Nothing this step computes waits on them.
-            const int zn2 = plane_of(s + 2);
-            const int zn1 = (s + 1 < Lz) ? s + 1 : -1;
-            T h_n[2][4], p_n[4], w_n[4];
-            typename SiteRec<T>::V hv_n{};
-            if (active) {
-                if (zn1 >= 0) load_halo(zn1, h_n);
-                if (zn2 >= 0) {
-                    const int64_t base = 4 * (sxy + plane_sites * zn2);
-#pragma unroll
-                    for (int o = 0; o < 4; ++o) p_n[o] = gload<T>(vrs, lane, base + o);
-                }
-                if (zn1 >= 0) {
-                    const int64_t base = 4 * (sxy + plane_sites * zn1);
-#pragma unroll
-                    for (int o = 0; o < 4; ++o) {
-                        if constexpr (STREAM & 1) w_n[o] = need_w ? __builtin_nontemporal_load(W + (base + o) * kE + lane) : T(0);
-                        else w_n[o] = need_w ? W[(base + o) * kE + lane] : T(0);
-                    }
-                    if constexpr (VALS != 0) hv_n = SiteRec<T>::load(val + base * 2 * kWidth, lane);
-                }
-            }
-            const bool zdn = plane_of(s - 1) >= 0, zup = plane_of(s + 1) >= 0;
-            if (active) {
-                const int64_t site = sxy + plane_sites * s;
-#pragma unroll
-                for (int o = 0; o < 4; ++o) {
-                    const int64_t row = 4 * site + o;
-                    int wv[VEC_VALS ? 1 : kValWords];
-                    if constexpr (!VEC_VALS) sload<kValWords>(val_rs, static_cast<unsigned>(row * kValWords * 4), wv);
-                    T v[kWidth];
-                    v[0] = ring[s & 3][wave][o][lane];
-#pragma unroll
-                    for (int d = 0; d < 4; ++d) {
-                        const int sl = 1 + 2 * d;
-                        if (nb[d].kind == 1) {
-                            v[sl] = ring[s & 3][nb[d].idx][o][lane];
-                            v[sl + 1] = ring[s & 3][nb[d].idx][o ^ 3][lane];
-                        } else if (nb[d].kind == 2) {
-                            const int hs = d < 2 ? 0 : 1;
-                            v[sl] = h_c[hs][o];
-                            v[sl + 1] = h_c[hs][o ^ 3];
-                        } else {
-                            v[sl] = v[sl + 1] = T(0);
-                        }
-                    }
-                    v[9] = zdn ? ring[(s - 1) & 3][wave][o][lane] : T(0);
-                    v[10] = zdn ? ring[(s - 1) & 3][wave][o ^ 2][lane] : T(0);
-                    v[11] = zup ? ring[(s + 1) & 3][wave][o][lane] : T(0);
-                    v[12] = zup ? ring[(s + 1) & 3][wave][o ^ 2][lane] : T(0);
-                    // two partial sums per product: shorter FMA dependency chains
-                    T A[2] = {T(0), T(0)}, B[2] = {T(0), T(0)};
-                    if constexpr (VEC_VALS) {
-#pragma unroll
-                        for (int j = 0; j < kWidth; ++j) {
-                            A[j & 1] = fma(SiteRec<T>::re(hv_c, kWidth * o + j), v[j], A[j & 1]);
-                            B[j & 1] = fma(SiteRec<T>::im(hv_c, kWidth * o + j), v[j], B[j & 1]);
-                        }
-                    } else {
-#pragma unroll
-                        for (int j = 0; j < kWidth; ++j) {
-                            A[j & 1] = fma(from_words<T>(wv + (2 * j) * wpv), v[j], A[j & 1]);
-                            B[j & 1] = fma(from_words<T>(wv + (2 * j + 1) * wpv), v[j], B[j & 1]);
-                        }
-                    }
-                    const T hv = fma(sgn, swap_pair(B[0] + B[1]), A[0] + A[1]);
-                    T* wr = W + row * kE + lane;
-                    if constexpr (VARIANT == KPM_PLAIN) {
-                        if constexpr (STREAM & 2) __builtin_nontemporal_store(hv, wr);
-                        else *wr = hv;
-                    } else {
-                        T w = fma(alpha, hv, beta * v[0]);
-                        if (need_w) w = fma(gamma, w_c[o], w);
-                        if constexpr (STREAM & 2) __builtin_nontemporal_store(w, wr);
-                        else *wr = w;
-                        if constexpr (VARIANT == KPM_FULL) {
-                            const double vd = static_cast<double>(v[0]);
-                            const double vsw = static_cast<double>(swap_pair(v[0]));
-                            const double wd = static_cast<double>(w);
-                            acc_e = fma(vd, vd, acc_e);
-                            acc_or = fma(wd, vd, acc_or);
-                            acc_oi = fma(wd, vsw, acc_oi);
-                        }
-                    }
-                }
-            }
-            // plane s + 2 replaces plane s - 2 (last read in step s - 1)
-            if (active && zn2 >= 0) {
-#pragma unroll
-                for (int o = 0; o < 4; ++o) ring[(s + 2) & 3][wave][o][lane] = p_n[o];
-            }
-#pragma unroll
-            for (int o = 0; o < 4; ++o) {
-                w_c[o] = w_n[o];
-                h_c[0][o] = h_n[0][o];
-                h_c[1][o] = h_n[1][o];
-            }
-            if constexpr (VALS == 2) {
-                sink ^= static_cast<unsigned>(__builtin_amdgcn_readfirstlane(hv_n.x));
-            } else {
-                hv_c = hv_n;
-            }
-            __syncthreads();
+        int s = 0;
+        for (; s + 1 < Lz; s += 2) {
+            step(s, ra, rb);
+            step(s + 1, rb, ra);
         }
+        if (s < Lz) step(s, ra, rb);
     }
     asm volatile("" ::"s"(sink));
 
@@ -356,10 +497,13 @@ hipError_t launch_ts(int variant, const LatticeArgs& a, hipStream_t s) {
         static_cast<const T*>(a.val), static_cast<const T*>(a.V), static_cast<T*>(a.W),          \
         static_cast<T>(a.alpha), static_cast<T>(a.beta), static_cast<T>(a.gamma), a.partials,  \
         a.L[0], a.L[1], a.L[2], a.periodic[0], a.periodic[1], a.periodic[2], ntx, ntiles, a.order)
+// tuning `prefetch`: 2 (default) the site's matrix record a step ahead in
+// registers (VALS 1), 1 scalar loads after an L2 warm-up (VALS 2), 0 plain
+// scalar loads
 #define KPM_LAUNCH_V(VAR)                          \
     switch (a.prefetch) {                          \
-    case 1: KPM_LAUNCH(VAR, 1); break;             \
-    case 2: KPM_LAUNCH(VAR, 2); break;             \
+    case 2: KPM_LAUNCH(VAR, 1); break;             \
+    case 1: KPM_LAUNCH(VAR, 2); break;             \
     default: KPM_LAUNCH(VAR, 0); break;            \
     }
     switch (variant) {
@@ -407,7 +551,11 @@ int lattice_grid(const kpm_hamiltonian* H) {
         hipDeviceProp_t p;
         if (hipGetDeviceProperties(&p, dev) == hipSuccess) cus = p.multiProcessorCount;
     }
-    const int per_cu = (H->dtype == KPM_C128) ? 1 : 2;   // LDS: 140 KB or 76 KB per workgroup
+    // LDS per workgroup: 142 KB (complex128) or 77 KB (complex64), so at
+    // most 1 or 2 workgroups fit on a CU; default 1
+    const int max_per_cu = (H->dtype == KPM_C128) ? 1 : 2;
+    const int want = get_tuning().wg_per_cu;
+    const int per_cu = want > 0 ? (want < max_per_cu ? want : max_per_cu) : 1;
     int g = cus * per_cu;
     if (g > ntiles) g = ntiles;
     if (g >= kXcds) g -= g % kXcds;

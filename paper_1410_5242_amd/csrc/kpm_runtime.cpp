@@ -193,7 +193,7 @@ hipError_t launch_any_sweep(kpm_hamiltonian* H, int R, int variant, const SweepA
 }
 
 // ---- batched solver: process-wide state, one set per device ----
-kpm_batch_tuning g_batch_tuning = {0, 0, 1};
+kpm_batch_tuning g_batch_tuning = {0, 0, 1, 4};
 
 struct BatchState {
     BatchInst* inst = nullptr;          // device instance table
@@ -212,7 +212,7 @@ struct BatchState {
     // what the captured graph was made for
     std::vector<BatchInst> key_inst;
     std::vector<int32_t> key_order;
-    int key_dtype = -1, key_R = 0, key_M = 0, key_grid = 0, key_waves = 0, key_dynamic = -1;
+    int key_dtype = -1, key_R = 0, key_M = 0, key_grid = 0, key_waves = 0, key_dynamic = -1, key_slab = -1;
 };
 std::vector<BatchState> g_batch;
 
@@ -227,7 +227,8 @@ void drop_graph(BatchState& b) {
 
 bool same_inst(const BatchInst& x, const BatchInst& y) {
     return x.val == y.val && x.col == y.col && x.v0 == y.v0 && x.a == y.a && x.b == y.b && x.eta == y.eta &&
-           x.mu == y.mu && x.nrows == y.nrows && x.inv_a == y.inv_a && x.shift == y.shift;
+           x.mu == y.mu && x.nrows == y.nrows && x.inv_a == y.inv_a && x.shift == y.shift && x.L[0] == y.L[0] &&
+           x.L[1] == y.L[1] && x.L[2] == y.L[2];
 }
 
 }  // namespace
@@ -421,6 +422,7 @@ kpm_status kpm_aug_spmmv(const kpm_hamiltonian* Hc, const void* V, void* W, int3
     SweepArgs a{H->val, H->col, H->nrows, V, W, H->sched, alpha, beta, gamma,
                 dots ? H->ws.partials : nullptr, launch_grid(H, R)};
     a.queue = H->ws.queue;
+    for (int j = 0; j < 3; ++j) a.L[j] = H->L[j];
     const int launch_variant = (variant == KPM_FULL && !dots) ? KPM_NODOT : variant;
     KPM_HIP(launch_any_sweep(H, R, launch_variant, a, s), "sweep kernel");
     if (dots) KPM_HIP(launch_reduce_partials(H->ws.partials, 1, a.grid, R, 0, eta, s), "reduce kernel");
@@ -465,6 +467,7 @@ kpm_status kpm_moments(const kpm_hamiltonian* Hc, const void* V0, int32_t R, int
         SweepArgs a{H->val, H->col, H->nrows, nullptr, nullptr, H->sched, 0.0, 0.0, 0.0,
                     H->ws.partials + sl * slot_elems, grid};
         a.queue = H->ws.queue + sl * kXcds;
+        for (int j = 0; j < 3; ++j) a.L[j] = H->L[j];
         if (k == 0) {
             // nu_1 = Htilde nu_0 = (1/a) H nu_0 - (b/a) nu_0
             a.V = A; a.W = B; a.alpha = inv_a; a.beta = -H->b * inv_a; a.gamma = 0.0;
@@ -543,12 +546,12 @@ kpm_status kpm_moment_features(const double* mu, int32_t n_inst, int32_t R, int3
 kpm_status kpm_set_sweep_tuning(const kpm_sweep_tuning* t) {
     g_error.clear();
     if (!t) {
-        set_tuning(kpm_sweep_tuning{0, kXcds, 8, 16, 0, 2, 3, 1, 0, 0});
+        set_tuning(kpm_sweep_tuning{0, kXcds, 8, 16, 0, 2, 3, 1, 0, 0, 4});
         return KPM_OK;
     }
     if (t->wg_per_cu < 0 || t->xcd_ways < 0 || t->chunk_tiles < 0 || t->pencil < 0 || t->dynamic < 0 ||
         t->prefetch < 0 || t->prefetch > 2 || t->stream < 0 || t->stream > 3 || t->lattice < 0 || t->lattice > 2 ||
-        t->gather < 0 || t->gather > 2 || t->tile_order < 0 || t->tile_order > 2)
+        t->gather < 0 || t->gather > 2 || t->tile_order < 0 || t->tile_order > 2 || t->slab < 0)
         return fail(KPM_EINVAL, "tuning fields must be >= 0");
     if (t->wg_per_cu > 64 || t->xcd_ways > 64 || t->chunk_tiles > (1 << 20))
         return fail(KPM_EINVAL, "tuning field out of range");
@@ -598,13 +601,14 @@ kpm_status kpm_sweep_profile_read(int64_t* count, double* total_ms, double* min_
 kpm_status kpm_set_batch_tuning(const kpm_batch_tuning* t) {
     g_error.clear();
     if (!t) {
-        g_batch_tuning = kpm_batch_tuning{0, 0, 1};
+        g_batch_tuning = kpm_batch_tuning{0, 0, 1, 4};
         return KPM_OK;
     }
     if (t->waves != 0 && t->waves != 4 && t->waves != 8 && t->waves != 16)
         return fail(KPM_EINVAL, "waves must be 0, 4, 8 or 16");
     if (t->wg_per_cu < 0 || t->wg_per_cu > 16) return fail(KPM_EINVAL, "wg_per_cu must be in [0, 16]");
     if (t->dynamic < 0) return fail(KPM_EINVAL, "dynamic must be >= 0");
+    if (t->slab < 0) return fail(KPM_EINVAL, "slab must be >= 0");
     g_batch_tuning = *t;
     return KPM_OK;
 }
@@ -673,7 +677,8 @@ kpm_status kpm_moments_batched(const kpm_hamiltonian* const* H, const void* cons
         const size_t blk = (static_cast<size_t>(H[i]->nrows) * 2 * R * rs + 255) / 256 * 256;
         char* base = static_cast<char*>(b.vec) + voff[i];
         inst[i] = BatchInst{H[i]->val, H[i]->col, V0[i], base, base + blk, b.eta + eta_per * i,
-                            mu + static_cast<size_t>(i) * R * M, H[i]->nrows, 1.0 / H[i]->a, H[i]->b / H[i]->a};
+                            mu + static_cast<size_t>(i) * R * M, H[i]->nrows, 1.0 / H[i]->a, H[i]->b / H[i]->a,
+                            {H[i]->L[0], H[i]->L[1], H[i]->L[2]}, 0};
     }
     // longest first (greedy longest-processing-time order), ties by index
     std::vector<int32_t> order(n_inst);
@@ -691,11 +696,12 @@ kpm_status kpm_moments_batched(const kpm_hamiltonian* const* H, const void* cons
     int grid = device_cus() * per_cu;
     if (grid > n_inst) grid = n_inst;
     const int dynamic = g_batch_tuning.dynamic ? 1 : 0;
-    BatchArgs args{b.inst, b.order, n_inst, b.ints, b.ints + 1, M, grid, waves, dynamic};
+    BatchArgs args{b.inst, b.order, n_inst, b.ints, b.ints + 1, M, grid, waves, dynamic, g_batch_tuning.slab};
 
     const bool use_graph = (flags & KPM_BATCH_GRAPH) != 0;
     bool hit = use_graph && b.exec && b.key_dtype == dtype && b.key_R == R && b.key_M == M &&
                b.key_grid == grid && b.key_waves == waves && b.key_dynamic == dynamic &&
+               b.key_slab == g_batch_tuning.slab &&
                b.key_inst.size() == inst.size() && b.key_order == order;
     for (size_t i = 0; hit && i < inst.size(); ++i) hit = same_inst(b.key_inst[i], inst[i]);
 
@@ -730,6 +736,7 @@ kpm_status kpm_moments_batched(const kpm_hamiltonian* const* H, const void* cons
             b.key_grid = grid;
             b.key_waves = waves;
             b.key_dynamic = dynamic;
+            b.key_slab = g_batch_tuning.slab;
             KPM_HIP(hipGraphLaunch(b.exec, s), "hipGraphLaunch");
         } else {
             KPM_HIP(launch_zero_ints(b.ints, 2, s), "zero kernel");

@@ -61,7 +61,7 @@ check_moments_kernel(const double* __restrict__ mu, int R, int M, int* __restric
 }  // namespace
 
 namespace {
-kpm_sweep_tuning g_tuning = {0, kXcds, 8, 16, 0, 2, 3, 1, 0, 0};
+kpm_sweep_tuning g_tuning = {0, kXcds, 8, 16, 0, 2, 3, 1, 0, 0, 4};
 }
 
 kpm_sweep_tuning get_tuning() { return g_tuning; }
@@ -107,6 +107,7 @@ int sweep_grid(int dtype, int R, int64_t nrows) {
 hipError_t launch_sweep(int dtype, int R, int variant, const SweepArgs& a_in, hipStream_t s) {
     SweepArgs a = a_in;
     a.xcd_ways = g_tuning.xcd_ways > 0 ? g_tuning.xcd_ways : 1;
+    a.slab = g_tuning.slab;
     if (use_gather(dtype, R, a.nrows)) return launch_gather(dtype, R, variant, a, s);
     a.chunk = g_tuning.chunk_tiles > 0 ? g_tuning.chunk_tiles : 1;
     if (!g_tuning.dynamic) a.queue = nullptr;

@@ -38,11 +38,12 @@ class SweepTuning(ctypes.Structure):
     _fields_ = [("wg_per_cu", ctypes.c_int32), ("xcd_ways", ctypes.c_int32), ("chunk_tiles", ctypes.c_int32),
                 ("pencil", ctypes.c_int32), ("dynamic", ctypes.c_int32), ("prefetch", ctypes.c_int32),
                 ("stream", ctypes.c_int32), ("lattice", ctypes.c_int32), ("gather", ctypes.c_int32),
-                ("tile_order", ctypes.c_int32)]
+                ("tile_order", ctypes.c_int32), ("slab", ctypes.c_int32)]
 
 
 class BatchTuning(ctypes.Structure):
-    _fields_ = [("waves", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32), ("dynamic", ctypes.c_int32)]
+    _fields_ = [("waves", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32), ("dynamic", ctypes.c_int32),
+                ("slab", ctypes.c_int32)]
 
 
 BATCH_CHECK, BATCH_GRAPH = 1, 2
@@ -272,9 +273,9 @@ def moments_batched(Hs, V0s, M: int, mu: torch.Tensor | None = None, check: bool
     return mu
 
 
-def set_batch_tuning(waves: int = 0, wg_per_cu: int = 0, dynamic: int = 1):
+def set_batch_tuning(waves: int = 0, wg_per_cu: int = 0, dynamic: int = 1, slab: int = 4):
     """kpm_set_batch_tuning: launch shape of the batched solver (process-wide)."""
-    _check(lib().kpm_set_batch_tuning(ctypes.byref(BatchTuning(waves, wg_per_cu, dynamic))))
+    _check(lib().kpm_set_batch_tuning(ctypes.byref(BatchTuning(waves, wg_per_cu, dynamic, slab))))
 
 
 def reset_batch_tuning():
@@ -284,7 +285,7 @@ def reset_batch_tuning():
 def get_batch_tuning():
     t = BatchTuning()
     _check(lib().kpm_get_batch_tuning(ctypes.byref(t)))
-    return {"waves": t.waves, "wg_per_cu": t.wg_per_cu, "dynamic": t.dynamic}
+    return {"waves": t.waves, "wg_per_cu": t.wg_per_cu, "dynamic": t.dynamic, "slab": t.slab}
 
 
 def dos(mu: torch.Tensor, a: float, b: float, E: torch.Tensor, kernel: str = "jackson", kparam: float = 0.0,
@@ -336,11 +337,11 @@ def moment_features(mu: torch.Tensor, n_mom: int, extra: torch.Tensor | None = N
 
 def set_sweep_tuning(wg_per_cu: int = 0, xcd_ways: int = 8, chunk_tiles: int = 8, pencil: int = 16,
                      dynamic: int = 0, prefetch: int = 2, stream: int = 3, lattice: int = 1, gather: int = 0,
-                     tile_order: int = 0):
+                     tile_order: int = 0, slab: int = 4):
     """kpm_set_sweep_tuning: launch shape and site order of the sweep kernel (process-wide)."""
     _check(lib().kpm_set_sweep_tuning(ctypes.byref(SweepTuning(wg_per_cu, xcd_ways, chunk_tiles, pencil,
                                                                dynamic, prefetch, stream, lattice, gather,
-                                                               tile_order))))
+                                                               tile_order, slab))))
 
 
 def reset_sweep_tuning():
@@ -352,7 +353,7 @@ def get_sweep_tuning():
     _check(lib().kpm_get_sweep_tuning(ctypes.byref(t)))
     return {"wg_per_cu": t.wg_per_cu, "xcd_ways": t.xcd_ways, "chunk_tiles": t.chunk_tiles, "pencil": t.pencil,
             "dynamic": t.dynamic, "prefetch": t.prefetch, "stream": t.stream,
-            "lattice": t.lattice, "gather": t.gather, "tile_order": t.tile_order}
+            "lattice": t.lattice, "gather": t.gather, "tile_order": t.tile_order, "slab": t.slab}
 
 
 def sweep_kernel(H: Hamiltonian, R: int) -> str:
