@@ -231,10 +231,13 @@ kpm_status kpm_moment_features(const double* mu, int32_t n_inst, int32_t R, int3
  *                rows a tile gathers belong to tiles of its own die, in its
  *                own L2), 1 each die a contiguous run of tile rows, 2 no die
  *                mapping.  Only the work distribution changes.
- *   slab         staged-gather sweep: the passes walk the lattice in blocks
- *                of this many y-lines, each block plane by plane, so that the
- *                rows gathered for z neighbours were touched a few lines
- *                earlier; 0 = natural row order; default 4
+ *   slab         staged-gather sweep at R <= 16: the passes walk the lattice
+ *                in blocks of this many y-lines, each block plane by plane,
+ *                so that the rows gathered for z neighbours were touched a
+ *                few lines earlier (3-8 % at R = 2..16 on 64^3; at larger R
+ *                the index arithmetic costs more occupancy than it saves,
+ *                and the natural order runs); 0 = natural row order;
+ *                default 4
  * kpm_set_sweep_tuning(NULL) restores the defaults.  Errors: KPM_EINVAL
  * (negative field). */
 typedef struct {
@@ -312,7 +315,8 @@ kpm_status kpm_moments_batched(const kpm_hamiltonian* const* H, const void* cons
  *              g, g + grid, ... of that list.
  *   slab       a workgroup walks its instance's lattice in blocks of this
  *              many y-lines, each block plane by plane (0 = natural row
- *              order); default 4.  Only the order of work changes.
+ *              order); default 4 (5 % faster than the natural order on
+ *              the 512-instance family).  Only the order of work changes.
  * kpm_set_batch_tuning(NULL) restores the defaults.  Errors: KPM_EINVAL. */
 typedef struct {
     int32_t waves;

@@ -131,6 +131,43 @@ struct Slabs {
     }
 };
 
+// Natural row order: pass p covers rows p * rpw .. (the last pass ragged).
+// Kernels built without the slab order use this one, which needs no
+// division (the slab order's index arithmetic costs registers even when
+// it is not taken).
+struct RowPasses {
+    int64_t nrows = 0, npass = 0;
+    int rpw = 1;
+    __host__ __device__ void init(int64_t n, int rpw_) {
+        nrows = n;
+        rpw = rpw_;
+        npass = (n + rpw - 1) / rpw;
+    }
+    // nr is always rpw: rows past the end lie outside every buffer
+    // descriptor (loads read 0, stores are dropped) and the kernels mask
+    // their scalar products with row < N, so the pass size stays a
+    // compile-time constant
+    __host__ __device__ void pass(int64_t p, int64_t& row0, int64_t& nr) const {
+        row0 = p < npass ? p * rpw : nrows;
+        nr = rpw;
+    }
+};
+
+// Pass order of a kernel: the slab order (SLAB) or the natural one.
+template <bool SLAB> struct PassOrder;
+template <> struct PassOrder<true> {
+    Slabs o;
+    __device__ void init(int64_t, int Lx, int Ly, int Lz, int lines, int rpw) { o.init(Lx, Ly, Lz, lines, rpw); }
+    __device__ int64_t npass() const { return o.npass; }
+    __device__ void pass(int64_t p, int64_t& row0, int64_t& nr) const { o.pass(p, row0, nr); }
+};
+template <> struct PassOrder<false> {
+    RowPasses o;
+    __device__ void init(int64_t n, int, int, int, int, int rpw) { o.init(n, rpw); }
+    __device__ int64_t npass() const { return o.npass; }
+    __device__ void pass(int64_t p, int64_t& row0, int64_t& nr) const { o.pass(p, row0, nr); }
+};
+
 template <typename T, int R, int WAVES>
 constexpr int lds_bytes() {
     using S = Shape<T, R>;
@@ -212,7 +249,7 @@ constexpr int min_waves() {
     return occ < 1 ? 1 : (occ < kMinWaves<T> ? occ : kMinWaves<T>);
 }
 
-template <typename T, int R, int WAVES>
+template <typename T, int R, int WAVES, bool SLAB>
 __global__ void __launch_bounds__(64 * WAVES, (min_waves<T, R, WAVES>()))
 batched_kernel(const BatchInst* __restrict__ insts, const int32_t* __restrict__ order, int n_inst,
                int* __restrict__ counter, int* __restrict__ flag, int M, int slab) {
@@ -252,9 +289,9 @@ batched_kernel(const BatchInst* __restrict__ insts, const int32_t* __restrict__ 
         if (idx >= n_inst) break;
         const BatchInst d = insts[order[idx]];
         const int64_t N = d.nrows;
-        Slabs sl;
-        sl.init(d.L[0], d.L[1], d.L[2], slab, RPW);
-        const int64_t npass = sl.npass;
+        PassOrder<SLAB> sl;
+        sl.init(N, d.L[0], d.L[1], d.L[2], slab, RPW);
+        const int64_t npass = sl.npass();
         const uint64_t vbytes = static_cast<uint64_t>(N) * R * kCB;
         const __amdgpu_buffer_rsrc_t val_rs = rsrc(d.val, static_cast<uint64_t>(N) * kVW * 4);
         const __amdgpu_buffer_rsrc_t col_rs = rsrc(d.col, static_cast<uint64_t>(N) * kWidth * 4);
@@ -327,10 +364,19 @@ batched_kernel(const BatchInst* __restrict__ insts, const int32_t* __restrict__ 
                     v[j] = LV::load(vrs, (c * R + cc * CPL) * kCB);
                 }
                 const int64_t row = row0 + sub;
-                const bool act = sub < nr;
-                // rows past the end of the pass: an offset past the block, so
-                // the old-W load reads zero and the store is dropped
-                const unsigned off = act ? static_cast<unsigned>(row * R + cc * CPL) * kCB : 0xFFFFFFF0u;
+                // slab order: rows past the end of a pass belong to other
+                // passes and get an offset past the block (the old-W load
+                // reads zero, the store is dropped); natural order: only rows
+                // past N are inactive, and their offsets are past the block
+                bool act;
+                unsigned off;
+                if constexpr (SLAB) {
+                    act = sub < nr;
+                    off = act ? static_cast<unsigned>(row * R + cc * CPL) * kCB : 0xFFFFFFF0u;
+                } else {
+                    act = row < N;
+                    off = static_cast<unsigned>(row * R + cc * CPL) * kCB;
+                }
                 const Cv wo = LV::load(wold_rs, off);
                 // matrix rows of this wave's next pass (zeros past the end)
                 int64_t row0n, nrn;
@@ -419,9 +465,13 @@ batched_kernel(const BatchInst* __restrict__ insts, const int32_t* __restrict__ 
 template <typename T, int R, int WAVES>
 hipError_t launch_waves(const BatchArgs& a, hipStream_t s) {
     if constexpr (instantiable<T, R, WAVES>()) {
-        batched_kernel<T, R, WAVES><<<a.grid, 64 * WAVES, 0, s>>>(a.inst, a.order, a.n_inst,
-                                                                  a.dynamic ? a.counter : nullptr, a.flag, a.M,
-                                                                  a.slab);
+        int* counter = a.dynamic ? a.counter : nullptr;
+        if (a.slab > 0)
+            batched_kernel<T, R, WAVES, true><<<a.grid, 64 * WAVES, 0, s>>>(a.inst, a.order, a.n_inst, counter,
+                                                                          a.flag, a.M, a.slab);
+        else
+            batched_kernel<T, R, WAVES, false><<<a.grid, 64 * WAVES, 0, s>>>(a.inst, a.order, a.n_inst, counter,
+                                                                           a.flag, a.M, 0);
         return hipGetLastError();
     } else {
         return hipErrorInvalidValue;

@@ -54,7 +54,7 @@ constexpr int min_waves() {
 
 // W <- alpha H V + beta V + gamma W (FULL, NODOT) or W <- H V (PLAIN);
 // FULL also writes this workgroup's <V|V>, <W|V> partial.
-template <typename T, int R, int WAVES, int VARIANT>
+template <typename T, int R, int WAVES, int VARIANT, bool SLAB>
 __global__ void __launch_bounds__(64 * WAVES, (min_waves<T, R, WAVES>()))
 gather_sweep_kernel(const T* __restrict__ val, const int32_t* __restrict__ col, int64_t N,
                     const T* __restrict__ V, T* __restrict__ W, T alpha, T beta, T gamma,
@@ -84,9 +84,9 @@ gather_sweep_kernel(const T* __restrict__ val, const int32_t* __restrict__ col, 
     const int X = (xcd_ways > 1 && ngrid % xcd_ways == 0) ? xcd_ways : 1;
     const int xcd = blockIdx.x % X;
     const int per = ngrid / X;
-    batch::Slabs sl;
-    sl.init(Lx, Ly, Lz, lines, RPW);
-    const int64_t npass = sl.npass;
+    batch::PassOrder<SLAB> sl;
+    sl.init(N, Lx, Ly, Lz, lines, RPW);
+    const int64_t npass = sl.npass();
     const int64_t lo = npass * xcd / X, hi = npass * (xcd + 1) / X;
     const int64_t stride = static_cast<int64_t>(per) * WAVES;
     const int64_t q0 = lo + static_cast<int64_t>(blockIdx.x / X) * WAVES + wave;
@@ -146,10 +146,19 @@ gather_sweep_kernel(const T* __restrict__ val, const int32_t* __restrict__ col, 
             v[j] = LV::load(vrs, (c * R + cc * CPL) * kCB);
         }
         const int64_t row = row0 + sub;
-        const bool act = sub < nr;
-        // rows past the end of the pass: an offset past the block, so the
-        // old-W load reads zero and the store is dropped
-        const unsigned off = act ? static_cast<unsigned>(row * R + cc * CPL) * kCB : 0xFFFFFFF0u;
+        // slab order: rows past the end of a pass belong to other passes and
+        // get an offset past the block (the old-W load reads zero, the store
+        // is dropped); natural order: only rows past N are inactive, and
+        // their offsets are past the block
+        bool act;
+        unsigned off;
+        if constexpr (SLAB) {
+            act = sub < nr;
+            off = act ? static_cast<unsigned>(row * R + cc * CPL) * kCB : 0xFFFFFFF0u;
+        } else {
+            act = row < N;
+            off = static_cast<unsigned>(row * R + cc * CPL) * kCB;
+        }
         const Cv wo = LV::load(wold_rs, off);
         int64_t row0n, nrn;
         sl.pass(q + stride, row0n, nrn);
@@ -225,10 +234,19 @@ gather_sweep_kernel(const T* __restrict__ val, const int32_t* __restrict__ col, 
 template <typename T, int R, int WAVES, int VARIANT>
 hipError_t launch_v(const SweepArgs& a, hipStream_t s) {
     if constexpr (instantiable<T, R, WAVES>()) {
-        gather_sweep_kernel<T, R, WAVES, VARIANT><<<a.grid, 64 * WAVES, 0, s>>>(
-            static_cast<const T*>(a.val), a.col, a.nrows, static_cast<const T*>(a.V), static_cast<T*>(a.W),
-            static_cast<T>(a.alpha), static_cast<T>(a.beta), static_cast<T>(a.gamma), a.partials, a.xcd_ways,
-            a.L[0], a.L[1], a.L[2], a.slab);
+        // the slab order only where it changes the order (a lattice, slab <
+        // Ly) and pays: up to R = 16 (beyond, its index arithmetic costs
+        // more occupancy than the shorter z reuse distance saves)
+        if (R <= 16 && a.slab > 0 && a.L[0] > 0 && a.slab < a.L[1])
+            gather_sweep_kernel<T, R, WAVES, VARIANT, true><<<a.grid, 64 * WAVES, 0, s>>>(
+                static_cast<const T*>(a.val), a.col, a.nrows, static_cast<const T*>(a.V), static_cast<T*>(a.W),
+                static_cast<T>(a.alpha), static_cast<T>(a.beta), static_cast<T>(a.gamma), a.partials, a.xcd_ways,
+                a.L[0], a.L[1], a.L[2], a.slab);
+        else
+            gather_sweep_kernel<T, R, WAVES, VARIANT, false><<<a.grid, 64 * WAVES, 0, s>>>(
+                static_cast<const T*>(a.val), a.col, a.nrows, static_cast<const T*>(a.V), static_cast<T*>(a.W),
+                static_cast<T>(a.alpha), static_cast<T>(a.beta), static_cast<T>(a.gamma), a.partials, a.xcd_ways,
+                0, 0, 0, 0);
         return hipGetLastError();
     } else {
         return hipErrorInvalidValue;

@@ -120,6 +120,23 @@ def test_batched_result_independent_of_batch_and_mapping(waves):
     K.reset_batch_tuning()
 
 
+@pytest.mark.parametrize("slab", [1, 3])
+def test_batched_slab_order_matches_oracle(slab):
+    # each workgroup walks its instance in blocks of `slab` y-lines
+    K = kpm()
+    R, M = 8, 40
+    say("batched slab order", slab)
+    batch = make_batch(SHAPES, R, "c128")
+    try:
+        K.set_batch_tuning(slab=slab)
+        mu = run(batch, M)
+    finally:
+        K.reset_batch_tuning()
+    for i, x in enumerate(batch):
+        ref = O.kpm_moments(x["Ho"], x["a"], x["b"], x["v0"], M)
+        assert np.abs(mu[i] - ref).max() <= TOL_C128, i
+
+
 def test_batched_same_handle_repeated_and_many_instances():
     # 300 instances (more than one per CU) that share four Hamiltonians
     K = kpm()

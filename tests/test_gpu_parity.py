@@ -475,6 +475,25 @@ def test_generic_sweeps_match_oracle(gather, R, dtype):
     assert np.abs(mu - ref).max() <= (TOL_C128 if dtype == "c128" else TOL_C64)
 
 
+@pytest.mark.parametrize("slab", [1, 2, 4])
+@pytest.mark.parametrize("R", [1, 8, 64])
+def test_gather_slab_order_matches_oracle(slab, R):
+    # passes in blocks of `slab` y-lines, plane by plane (Ly = 7: the last
+    # block is ragged for slab 2 and 4); only the order of the rows changes
+    K = kpm()
+    L, M = (6, 7, 5), 40
+    say("gather slab order", slab, "R", R)
+    pot, Ho, a, b = oracle_problem(L, 1.0, 23, periodic=(1, 1, 0))
+    v0 = inputs.phase_block(Ho.n, R, 24)
+    ref = O.kpm_moments(Ho, a, b, v0, M)
+    try:
+        K.set_sweep_tuning(lattice=0, gather=1, slab=slab)
+        mu, _ = gpu_moments(L, pot, v0, M, periodic=(1, 1, 0))
+    finally:
+        K.reset_sweep_tuning()
+    assert np.abs(mu - ref).max() <= TOL_C128
+
+
 @pytest.mark.parametrize("order", [0, 1, 2])
 @pytest.mark.parametrize("L", [(8, 16, 5), (16, 16, 3)])
 def test_lattice_tile_orders_match_oracle(order, L):
