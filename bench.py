@@ -196,12 +196,15 @@ def leg_variants(sweeps: int = 10):
     variants (the paper's split of the sweep into plain SpMMV, the update without scalar
     products, and the full fused sweep): GB/s from the library's per-launch HIP events."""
     import torch
-    from paper_1410_5242_amd import inputs, kpm
+    from paper_1410_5242_amd import autotune, inputs, kpm
     L = (64, 64, 64)
     H = kpm.build_hamiltonian(L, inputs.potential(L, 1.0, 0))
     N, Sd = H.N, 16
     out = {"workload": f"TI {L[0]}x{L[1]}x{L[2]} periodic, complex128, {sweeps} sweeps per point", "points": []}
+    cache = autotune.TuningCache()
     for R in kpm.SUPPORTED_R:
+        kpm.reset_sweep_tuning()
+        tuned = autotune.apply_sweep(cache, H, R, L)
         V = kpm.random_phase_block(N, R, 1, "c128")
         W = kpm.random_phase_block(N, R, 2, "c128")
         eta = torch.zeros((2, R, 2), dtype=torch.float64, device="cuda")
@@ -222,11 +225,12 @@ def leg_variants(sweeps: int = 10):
             vec_streams = 2 if var == "plain" else 3
             byts = 13 * N * (Sd + Si) + vec_streams * R * Sd * N
             pt = {"R": R, "variant": var, "kernel": kernel, "avg_us": round(avg_s * 1e6, 1),
-                  "GBps": round(byts / avg_s / 1e9, 1), "bytes": byts}
+                  "GBps": round(byts / avg_s / 1e9, 1), "bytes": byts, "autotuned": tuned}
             if var == "full":
                 pt["gflops"] = round(sweep_flops(N, R) / avg_s / 1e9, 1)
             out["points"].append(pt)
         del V, W
+    kpm.reset_sweep_tuning()
     H.close()
     return out
 
@@ -292,7 +296,7 @@ def main():
 
     import numpy as np
     import torch
-    from paper_1410_5242_amd import inputs, kpm
+    from paper_1410_5242_amd import autotune, inputs, kpm
 
     L, gamma, R, M, dtype, K = WORKLOADS[args.workload]
     dev = torch.device("cuda:0")
@@ -309,6 +313,8 @@ def main():
     E = torch.from_numpy((H.b + H.a * (-1.0 + (2.0 * np.arange(K) + 1.0) / K))).to(dev)
     mu = torch.empty((R, M), dtype=torch.float64, device=dev)
     rho = torch.empty(K, dtype=torch.float64, device=dev)
+    # launch shape from the committed autotuner cache, if it holds this workload
+    autotuned = autotune.apply_sweep(autotune.TuningCache(), H, R, L)
     sweep_kernel = kpm.sweep_kernel(H, R)
     log(f"[bench] built H: N={N} a={H.a:.6f} b={H.b:.6f} ({build_s:.3f} s); sweep kernel {sweep_kernel}")
 
@@ -398,7 +404,9 @@ def main():
             "max_launch_ms": round(sweep_ms_max, 5),
             "algorithmic_bytes_per_launch": bps,
         },
+        "tuning": {"autotuned": autotuned, "sweep": kpm.get_sweep_tuning()},
     }
+    kpm.reset_sweep_tuning()
     H.close()
     del V0
     legs = [x for x in args.legs.split(",") if x and x != "none"]

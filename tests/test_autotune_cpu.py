@@ -62,3 +62,12 @@ def test_time_call_reports_best_of_repeats():
     calls = []
     s = A.time_call(lambda: calls.append(1), repeats=4)
     assert len(calls) == 5 and s >= 0.0
+
+
+def test_pick_best_keeps_default_within_margin():
+    # the first trial is the library default: kept unless beaten by more than the margin
+    t = [A.Trial({"d": 0}, 1.0), A.Trial({"a": 1}, 0.99), A.Trial({"b": 2}, 0.995)]
+    assert A.pick_best(t, margin=0.02).params == {"d": 0}
+    assert A.pick_best(t, margin=0.0).params == {"a": 1}
+    t.append(A.Trial({"c": 3}, 0.95))
+    assert A.pick_best(t, margin=0.02).params == {"c": 3}
