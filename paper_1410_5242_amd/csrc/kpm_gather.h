@@ -27,6 +27,7 @@
 namespace kpm {
 namespace gather {
 
+using batch::kStream;
 using batch::Lanes;
 using batch::Pair;
 using batch::rsrc;
@@ -106,9 +107,9 @@ gather_sweep_kernel(const T* __restrict__ val, const int32_t* __restrict__ col, 
         const unsigned pv = static_cast<unsigned>(r0) * (kVW * 4);
         const unsigned pc = static_cast<unsigned>(r0) * (kWidth * 4);
 #pragma unroll
-        for (int i = 0; i < S::kLoadsV; ++i) wv[i] = WV::load(val_rs, pv + (lane + 64 * i) * (4 * S::kVecV));
+        for (int i = 0; i < S::kLoadsV; ++i) wv[i] = WV::template load<kStream<R>>(val_rs, pv + (lane + 64 * i) * (4 * S::kVecV));
 #pragma unroll
-        for (int i = 0; i < S::kLoadsC; ++i) wc[i] = WC::load(col_rs, pc + (lane + 64 * i) * (4 * S::kVecC));
+        for (int i = 0; i < S::kLoadsC; ++i) wc[i] = WC::template load<kStream<R>>(col_rs, pc + (lane + 64 * i) * (4 * S::kVecC));
     };
     auto put = [&](int* dst, const typename WV::type* wv, const typename WC::type* wc) {
 #pragma unroll
@@ -159,7 +160,7 @@ gather_sweep_kernel(const T* __restrict__ val, const int32_t* __restrict__ col, 
             act = row < N;
             off = static_cast<unsigned>(row * R + cc * CPL) * kCB;
         }
-        const Cv wo = LV::load(wold_rs, off);
+        const Cv wo = LV::template load<kStream<R>>(wold_rs, off);
         int64_t row0n, nrn;
         sl.pass(q + stride, row0n, nrn);
         if constexpr (S::kAhead) fetch(row0n, wv, wc);
@@ -186,7 +187,7 @@ gather_sweep_kernel(const T* __restrict__ val, const int32_t* __restrict__ col, 
             for (int e = 0; e < 2 * CPL; ++e) wn[e] = fma(gamma, wo[e], fma(alpha, acc[e], beta * v[0][e]));
         }
         // rows past N: the store is dropped (offset beyond the block), products masked
-        LV::store(wn, wrs, off);
+        LV::template store<kStream<R>>(wn, wrs, off);
         if constexpr (VARIANT == KPM_FULL) {
 #pragma unroll
             for (int t = 0; t < CPL; ++t) {
