@@ -89,7 +89,8 @@ __device__ inline void wstore(T x, __amdgpu_buffer_rsrc_t rs, int lane, int64_t 
 }
 
 // The matrix rows of one site (4 rows x 13 complex entries) are one
-// contiguous record; lane l < 52 of a wave loads the entry of row l / 13
+// contiguous record, read once per sweep with the non-temporal hint (L2 keeps
+// the V planes instead); lane l < 52 of a wave loads the entry of row l / 13
 // that product l % 13 of that row needs (lane_off; lanes past 52 repeat the
 // last entry)
 // (16 bytes in complex128, 8 in complex64) with a single vector load, and
@@ -100,7 +101,7 @@ template <typename T> struct SiteRec;
 template <> struct SiteRec<double> {
     using V = int4;
     static __device__ V load(__amdgpu_buffer_rsrc_t rs, unsigned lane_off, int64_t site) {
-        const auto w = __builtin_amdgcn_raw_buffer_load_b128(rs, lane_off, static_cast<unsigned>(site * 4 * kWidth * 16), 0);
+        const auto w = __builtin_amdgcn_raw_buffer_load_b128(rs, lane_off, static_cast<unsigned>(site * 4 * kWidth * 16), 2);
         return int4{static_cast<int>(w[0]), static_cast<int>(w[1]), static_cast<int>(w[2]), static_cast<int>(w[3])};
     }
     static __device__ double re(const V& v, int l) {
@@ -113,7 +114,7 @@ template <> struct SiteRec<double> {
 template <> struct SiteRec<float> {
     using V = int2;
     static __device__ V load(__amdgpu_buffer_rsrc_t rs, unsigned lane_off, int64_t site) {
-        const auto w = __builtin_amdgcn_raw_buffer_load_b64(rs, lane_off, static_cast<unsigned>(site * 4 * kWidth * 8), 0);
+        const auto w = __builtin_amdgcn_raw_buffer_load_b64(rs, lane_off, static_cast<unsigned>(site * 4 * kWidth * 8), 2);
         return int2{static_cast<int>(w[0]), static_cast<int>(w[1])};
     }
     static __device__ float re(const V& v, int l) { return __int_as_float(__builtin_amdgcn_readlane(v.x, l)); }
