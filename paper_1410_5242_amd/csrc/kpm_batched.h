@@ -240,7 +240,9 @@ __device__ inline void wave_sync() {
 // W): non-temporal at block widths 4..16, so that L2 keeps the V rows that
 // neighbouring rows gather again (measured on 64^3: 5-9 % faster there and
 // on the batched family; 2-9 % slower at R = 1, 2 and 64, where it stays
-// off).
+// off).  The single-instance sweep uses it only on problems larger than the
+// last-level cache; the batched solver always (its instances together
+// exceed it).
 template <int R>
 constexpr int kStream = (R >= 4 && R <= 16) ? 2 : 0;
 

@@ -55,7 +55,7 @@ constexpr int min_waves() {
 
 // W <- alpha H V + beta V + gamma W (FULL, NODOT) or W <- H V (PLAIN);
 // FULL also writes this workgroup's <V|V>, <W|V> partial.
-template <typename T, int R, int WAVES, int VARIANT, bool SLAB>
+template <typename T, int R, int WAVES, int VARIANT, bool SLAB, int AUX>
 __global__ void __launch_bounds__(64 * WAVES, (min_waves<T, R, WAVES>()))
 gather_sweep_kernel(const T* __restrict__ val, const int32_t* __restrict__ col, int64_t N,
                     const T* __restrict__ V, T* __restrict__ W, T alpha, T beta, T gamma,
@@ -107,9 +107,9 @@ gather_sweep_kernel(const T* __restrict__ val, const int32_t* __restrict__ col, 
         const unsigned pv = static_cast<unsigned>(r0) * (kVW * 4);
         const unsigned pc = static_cast<unsigned>(r0) * (kWidth * 4);
 #pragma unroll
-        for (int i = 0; i < S::kLoadsV; ++i) wv[i] = WV::template load<kStream<R>>(val_rs, pv + (lane + 64 * i) * (4 * S::kVecV));
+        for (int i = 0; i < S::kLoadsV; ++i) wv[i] = WV::template load<AUX>(val_rs, pv + (lane + 64 * i) * (4 * S::kVecV));
 #pragma unroll
-        for (int i = 0; i < S::kLoadsC; ++i) wc[i] = WC::template load<kStream<R>>(col_rs, pc + (lane + 64 * i) * (4 * S::kVecC));
+        for (int i = 0; i < S::kLoadsC; ++i) wc[i] = WC::template load<AUX>(col_rs, pc + (lane + 64 * i) * (4 * S::kVecC));
     };
     auto put = [&](int* dst, const typename WV::type* wv, const typename WC::type* wc) {
 #pragma unroll
@@ -160,7 +160,7 @@ gather_sweep_kernel(const T* __restrict__ val, const int32_t* __restrict__ col, 
             act = row < N;
             off = static_cast<unsigned>(row * R + cc * CPL) * kCB;
         }
-        const Cv wo = LV::template load<kStream<R>>(wold_rs, off);
+        const Cv wo = LV::template load<AUX>(wold_rs, off);
         int64_t row0n, nrn;
         sl.pass(q + stride, row0n, nrn);
         if constexpr (S::kAhead) fetch(row0n, wv, wc);
@@ -187,7 +187,7 @@ gather_sweep_kernel(const T* __restrict__ val, const int32_t* __restrict__ col, 
             for (int e = 0; e < 2 * CPL; ++e) wn[e] = fma(gamma, wo[e], fma(alpha, acc[e], beta * v[0][e]));
         }
         // rows past N: the store is dropped (offset beyond the block), products masked
-        LV::template store<kStream<R>>(wn, wrs, off);
+        LV::template store<AUX>(wn, wrs, off);
         if constexpr (VARIANT == KPM_FULL) {
 #pragma unroll
             for (int t = 0; t < CPL; ++t) {
@@ -232,22 +232,42 @@ gather_sweep_kernel(const T* __restrict__ val, const int32_t* __restrict__ col, 
     }
 }
 
+template <typename T, int R, int WAVES, int VARIANT, bool SLAB, int AUX>
+void launch_k(const SweepArgs& a, hipStream_t s) {
+    gather_sweep_kernel<T, R, WAVES, VARIANT, SLAB, AUX><<<a.grid, 64 * WAVES, 0, s>>>(
+        static_cast<const T*>(a.val), a.col, a.nrows, static_cast<const T*>(a.V), static_cast<T*>(a.W),
+        static_cast<T>(a.alpha), static_cast<T>(a.beta), static_cast<T>(a.gamma), a.partials, a.xcd_ways,
+        SLAB ? a.L[0] : 0, SLAB ? a.L[1] : 0, SLAB ? a.L[2] : 0, SLAB ? a.slab : 0);
+}
+
+// Bytes a sweep streams; above the 256 MB Infinity Cache nothing it reads
+// survives to the next sweep anyway.
+constexpr uint64_t kCacheBytes = 256ull << 20;
+
 template <typename T, int R, int WAVES, int VARIANT>
 hipError_t launch_v(const SweepArgs& a, hipStream_t s) {
     if constexpr (instantiable<T, R, WAVES>()) {
         // the slab order only where it changes the order (a lattice, slab <
         // Ly) and pays: up to R = 16 (beyond, its index arithmetic costs
         // more occupancy than the shorter z reuse distance saves)
-        if (R <= 16 && a.slab > 0 && a.L[0] > 0 && a.slab < a.L[1])
-            gather_sweep_kernel<T, R, WAVES, VARIANT, true><<<a.grid, 64 * WAVES, 0, s>>>(
-                static_cast<const T*>(a.val), a.col, a.nrows, static_cast<const T*>(a.V), static_cast<T*>(a.W),
-                static_cast<T>(a.alpha), static_cast<T>(a.beta), static_cast<T>(a.gamma), a.partials, a.xcd_ways,
-                a.L[0], a.L[1], a.L[2], a.slab);
-        else
-            gather_sweep_kernel<T, R, WAVES, VARIANT, false><<<a.grid, 64 * WAVES, 0, s>>>(
-                static_cast<const T*>(a.val), a.col, a.nrows, static_cast<const T*>(a.V), static_cast<T*>(a.W),
-                static_cast<T>(a.alpha), static_cast<T>(a.beta), static_cast<T>(a.gamma), a.partials, a.xcd_ways,
-                0, 0, 0, 0);
+        const bool slab = R <= 16 && a.slab > 0 && a.L[0] > 0 && a.slab < a.L[1];
+        // non-temporal matrix and W streams (batch::kStream) only when a
+        // sweep's data exceeds the last-level cache: on smaller problems
+        // they would throw away what the next sweep reads again
+        const uint64_t bytes = static_cast<uint64_t>(a.nrows) *
+                               (kWidth * (2 * sizeof(T) + 4) + 3ull * R * 2 * sizeof(T));
+        const bool nt = bytes > kCacheBytes;
+        if constexpr (kStream<R> != 0) {
+            if (slab && nt) launch_k<T, R, WAVES, VARIANT, true, kStream<R>>(a, s);
+            else if (slab) launch_k<T, R, WAVES, VARIANT, true, 0>(a, s);
+            else if (nt) launch_k<T, R, WAVES, VARIANT, false, kStream<R>>(a, s);
+            else launch_k<T, R, WAVES, VARIANT, false, 0>(a, s);
+        } else if constexpr (R <= 16) {
+            if (slab) launch_k<T, R, WAVES, VARIANT, true, 0>(a, s);
+            else launch_k<T, R, WAVES, VARIANT, false, 0>(a, s);
+        } else {
+            launch_k<T, R, WAVES, VARIANT, false, 0>(a, s);
+        }
         return hipGetLastError();
     } else {
         return hipErrorInvalidValue;
