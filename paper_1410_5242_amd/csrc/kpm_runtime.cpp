@@ -546,7 +546,7 @@ kpm_status kpm_moment_features(const double* mu, int32_t n_inst, int32_t R, int3
 kpm_status kpm_set_sweep_tuning(const kpm_sweep_tuning* t) {
     g_error.clear();
     if (!t) {
-        set_tuning(kpm_sweep_tuning{0, kXcds, 8, 16, 0, 2, 3, 1, 0, 0, 4});
+        set_tuning(kpm_sweep_tuning{0, kXcds, 8, 16, 0, 2, 3, 1, 1, 0, 4});
         return KPM_OK;
     }
     if (t->wg_per_cu < 0 || t->xcd_ways < 0 || t->chunk_tiles < 0 || t->pencil < 0 || t->dynamic < 0 ||

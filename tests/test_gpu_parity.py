@@ -250,7 +250,8 @@ def test_lattice_sweep_matches_oracle(L, periodic, dtype, vals):
 
 @pytest.mark.parametrize("L", [(5, 4, 4), (4, 9, 3), (1, 1, 7)])
 def test_lattice_sweep_falls_back_for_one_site_tail_tiles(L):
-    # a side with L mod 4 == 1 would leave tiles one site wide: the generic sweep runs
+    # a side with L mod 4 == 1 would leave tiles one site wide: the generic
+    # (staged-gather, by default) sweep runs
     K = kpm()
     M, R = 24, 32
     pot, Ho, a, b = oracle_problem(L, 1.0, 4, periodic=(0, 0, 1))
@@ -258,7 +259,7 @@ def test_lattice_sweep_falls_back_for_one_site_tail_tiles(L):
     try:
         K.set_sweep_tuning(lattice=2)
         H = K.build_hamiltonian(L, pot, periodic=(0, 0, 1))
-        assert K.sweep_kernel(H, R) == "aug_spmmv_kernel"
+        assert K.sweep_kernel(H, R) == "gather_sweep_kernel"
         H.close()
         mu, _ = gpu_moments(L, pot, v0, M, periodic=(0, 0, 1))
     finally:
