@@ -264,12 +264,15 @@ kpm_status kpm_get_sweep_tuning(kpm_sweep_tuning* tuning);
  * Errors: KPM_EINVAL. */
 kpm_status kpm_sweep_kernel(const kpm_hamiltonian* H, int32_t R, int32_t* kernel);
 
-/* Sweep-kernel timing for measurement tools.  While enabled (process-wide,
- * not thread-safe), every fused sweep launched by kpm_moments and
- * kpm_aug_spmmv is bracketed by a pair of HIP events on its own stream.
- * kpm_sweep_profile_read waits for the recorded events, returns the count,
- * total, minimum and maximum kernel time in milliseconds (any output may be
- * NULL) and clears the record.  Errors: KPM_EDEVICE. */
+/* Sweep-kernel timing for measurement tools.  kpm_sweep_profile_enable(n),
+ * n > 0 (process-wide, not thread-safe): every n-th fused sweep launched by
+ * kpm_moments and kpm_aug_spmmv from then on (the first, the (n+1)-th, ...)
+ * is bracketed by a pair of HIP events on its own stream; each pair costs a
+ * few microseconds of stream time, so sampling (n > 1) keeps a timed run
+ * close to an untimed one.  n = 0 turns it off.  kpm_sweep_profile_read
+ * waits for the recorded events, returns the count, total, minimum and
+ * maximum kernel time in milliseconds of the timed launches (any output may
+ * be NULL) and clears the record.  Errors: KPM_EINVAL (n < 0), KPM_EDEVICE. */
 kpm_status kpm_sweep_profile_enable(int32_t enable);
 kpm_status kpm_sweep_profile_read(int64_t* count, double* total_ms, double* min_ms, double* max_ms);
 

@@ -140,16 +140,19 @@ kpm_status ensure_flag(kpm_hamiltonian* H) {
     return KPM_OK;
 }
 
-// Event pairs around sweep launches (kpm_sweep_profile_*).
+// Event pairs around sweep launches (kpm_sweep_profile_*): every period-th
+// launch is timed (0: off).
 struct SweepProfile {
-    bool on = false;
+    int period = 0;
+    uint64_t seen = 0;
     std::vector<hipEvent_t> start, stop;
     size_t used = 0;
 };
 SweepProfile g_prof;
 
-hipError_t launch_sweep_profiled(int dtype, int R, int variant, const SweepArgs& a, hipStream_t s) {
-    if (!g_prof.on) return launch_sweep(dtype, R, variant, a, s);
+template <class Launch>
+hipError_t profiled(hipStream_t s, Launch&& launch) {
+    if (g_prof.period <= 0 || (g_prof.seen++ % static_cast<uint64_t>(g_prof.period)) != 0) return launch();
     if (g_prof.used == g_prof.start.size()) {
         hipEvent_t e0, e1;
         hipError_t e = hipEventCreate(&e0);
@@ -160,7 +163,7 @@ hipError_t launch_sweep_profiled(int dtype, int R, int variant, const SweepArgs&
     }
     hipError_t e = hipEventRecord(g_prof.start[g_prof.used], s);
     if (e != hipSuccess) return e;
-    if ((e = launch_sweep(dtype, R, variant, a, s)) != hipSuccess) return e;
+    if ((e = launch()) != hipSuccess) return e;
     if ((e = hipEventRecord(g_prof.stop[g_prof.used], s)) != hipSuccess) return e;
     ++g_prof.used;
     return hipSuccess;
@@ -173,23 +176,9 @@ hipError_t launch_any_sweep(kpm_hamiltonian* H, int R, int variant, const SweepA
         LatticeArgs la{H->val, a.V, a.W, a.alpha, a.beta, a.gamma, a.partials,
                        {H->L[0], H->L[1], H->L[2]}, {H->periodic[0], H->periodic[1], H->periodic[2]}, a.grid,
                        get_tuning().prefetch, get_tuning().stream, get_tuning().tile_order};
-        if (!g_prof.on) return launch_lattice(H->dtype, variant, la, s);
-        if (g_prof.used == g_prof.start.size()) {
-            hipEvent_t e0, e1;
-            hipError_t e = hipEventCreate(&e0);
-            if (e != hipSuccess) return e;
-            if ((e = hipEventCreate(&e1)) != hipSuccess) return e;
-            g_prof.start.push_back(e0);
-            g_prof.stop.push_back(e1);
-        }
-        hipError_t e = hipEventRecord(g_prof.start[g_prof.used], s);
-        if (e != hipSuccess) return e;
-        if ((e = launch_lattice(H->dtype, variant, la, s)) != hipSuccess) return e;
-        if ((e = hipEventRecord(g_prof.stop[g_prof.used], s)) != hipSuccess) return e;
-        ++g_prof.used;
-        return hipSuccess;
+        return profiled(s, [&] { return launch_lattice(H->dtype, variant, la, s); });
     }
-    return launch_sweep_profiled(H->dtype, R, variant, a, s);
+    return profiled(s, [&] { return launch_sweep(H->dtype, R, variant, a, s); });
 }
 
 // ---- batched solver: process-wide state, one set per device ----
@@ -575,7 +564,9 @@ kpm_status kpm_sweep_kernel(const kpm_hamiltonian* Hc, int32_t R, int32_t* kerne
 
 kpm_status kpm_sweep_profile_enable(int32_t enable) {
     g_error.clear();
-    g_prof.on = enable != 0;
+    if (enable < 0) return fail(KPM_EINVAL, "sweep profile period must be >= 0");
+    g_prof.period = enable;
+    g_prof.seen = 0;
     return KPM_OK;
 }
 

@@ -363,9 +363,11 @@ def sweep_kernel(H: Hamiltonian, R: int) -> str:
     return {0: "aug_spmmv_kernel", 1: "lattice_kernel", 2: "gather_sweep_kernel"}[k.value]
 
 
-def sweep_profile_enable(on: bool = True):
-    """kpm_sweep_profile_enable: bracket every sweep kernel with HIP events."""
-    _check(lib().kpm_sweep_profile_enable(1 if on else 0))
+def sweep_profile_enable(on=True):
+    """kpm_sweep_profile_enable: bracket every n-th sweep kernel with HIP events (True = every one,
+    an integer n > 0 = every n-th, False / 0 = off)."""
+    n = int(on) if not isinstance(on, bool) else (1 if on else 0)
+    _check(lib().kpm_sweep_profile_enable(n))
 
 
 def sweep_profile_read():

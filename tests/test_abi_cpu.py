@@ -63,6 +63,8 @@ def test_argument_validation_without_device(L):
     assert L.kpm_dos(fake, 1, 8, 7, 0.0, 1.0, 0.0, fake, 4, fake, None) == kpm.KPM_EINVAL   # kernel
     assert L.kpm_dos(fake, 1, 8, 2, 0.0, 1.0, 0.0, fake, 4, fake, None) == kpm.KPM_EINVAL   # Lorentz lambda
     assert L.kpm_hamiltonian_info(None, None, None, None, None, None, None, None, None) == kpm.KPM_EINVAL
+    assert L.kpm_sweep_profile_enable(-1) == kpm.KPM_EINVAL   # sampling period < 0
+    assert L.kpm_sweep_profile_enable(0) == kpm.KPM_OK
     L.kpm_destroy_hamiltonian(None)   # no-op
 
 

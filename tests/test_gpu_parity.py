@@ -510,3 +510,26 @@ def test_lattice_tile_orders_match_oracle(order, L):
     finally:
         K.reset_sweep_tuning()
     assert np.abs(mu - O.kpm_moments(Ho, a, b, v0, M)).max() <= TOL_C128
+
+
+@pytest.mark.parametrize("period", [1, 3])
+def test_sweep_profile_times_every_nth_launch(period):
+    # kpm_sweep_profile_enable(n): launches 1, n + 1, 2n + 1, ... are timed
+    K = kpm()
+    L, R, M = (8, 8, 8), 32, 20   # 10 sweeps
+    say("sweep profile period", period)
+    pot = inputs.potential(L, 1.0, 41)
+    H = K.build_hamiltonian(L, pot)
+    V0 = torch.from_numpy(inputs.phase_block(H.N, R, 42)).cuda()
+    try:
+        K.sweep_profile_read()
+        K.sweep_profile_enable(period)
+        K.moments(H, V0, M)
+        torch.cuda.synchronize()
+        K.sweep_profile_enable(False)
+        n, tot, lo, hi = K.sweep_profile_read()
+    finally:
+        K.sweep_profile_enable(False)
+        H.close()
+    assert n == (M // 2 + period - 1) // period
+    assert 0.0 < lo <= hi and tot >= n * lo * 0.999
