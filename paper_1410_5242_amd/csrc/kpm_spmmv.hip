@@ -9,16 +9,32 @@ namespace {
 
 
 // eta[sweep] from the partial sums of nslots consecutive sweeps, one
-// workgroup per sweep, each output summed over the workgroups in index order.
+// workgroup per sweep.  Each output sums the workgroup partials in kChunks
+// contiguous runs (in parallel, each in index order), then the runs in
+// order: the same fixed summation order on every call, with 1/kChunks of
+// the dependent-load chain of a single running sum.
+constexpr int kChunks = 8;
+constexpr int kMaxN3 = 3 * 64;
+
 __global__ void __launch_bounds__(256)
 reduce_partials_kernel(const double* __restrict__ part, int grid, int R, int sweep0,
                        double* __restrict__ eta) {
+    __shared__ double run[kChunks][kMaxN3];
     const int n3 = 3 * R;
     const double* p = part + static_cast<int64_t>(blockIdx.x) * grid * n3;
     const int sweep = sweep0 + blockIdx.x;
+    for (int j = threadIdx.x; j < kChunks * n3; j += blockDim.x) {
+        const int c = j / n3, i = j % n3;
+        const int g0 = grid * c / kChunks, g1 = grid * (c + 1) / kChunks;
+        double acc = 0.0;
+        for (int g = g0; g < g1; ++g) acc += p[static_cast<int64_t>(g) * n3 + i];
+        run[c][i] = acc;
+    }
+    __syncthreads();
     for (int i = threadIdx.x; i < n3; i += blockDim.x) {
         double acc = 0.0;
-        for (int g = 0; g < grid; ++g) acc += p[static_cast<int64_t>(g) * n3 + i];
+#pragma unroll
+        for (int c = 0; c < kChunks; ++c) acc += run[c][i];
         const int q = i / R, r = i % R;
         if (q == 0) {
             eta[(static_cast<int64_t>(2 * sweep) * R + r) * 2] = acc;
