@@ -82,7 +82,9 @@ struct Shape {
 // touched one block-plane earlier (a few lines of the lattice instead of a
 // whole plane).  A block-plane is a contiguous row range; passes cover it in
 // pieces of rpw rows, the last piece possibly shorter.  lines >= Ly (or 0)
-// is the natural row order, one plane at a time.
+// is the natural row order, one plane at a time.  This random-access form
+// defines the order (and is what the host check compares against); the
+// kernels walk it incrementally with SlabWalk below.
 struct Slabs {
     int64_t plane_rows = 0, line_rows = 0;
     int64_t pf = 0, pl = 0;          // passes per block-plane: full block, last block
@@ -131,41 +133,92 @@ struct Slabs {
     }
 };
 
-// Natural row order: pass p covers rows p * rpw .. (the last pass ragged).
-// Kernels built without the slab order use this one, which needs no
-// division (the slab order's index arithmetic costs registers even when
-// it is not taken).
-struct RowPasses {
-    int64_t nrows = 0, npass = 0;
+// Slab order walked incrementally by one wave: its passes are p0, p0 +
+// stride, p0 + 2 stride, ...; the pass index is kept as mixed-radix digits
+// (block, plane, piece) and the stride is added digit by digit with carries,
+// so a pass costs a few scalar operations.
+struct SlabWalk {
+    SlabGeom g;   // kpm::SlabGeom
+    uint32_t sb = 0, sz = 0, so = 0;   // stride as digits
+    uint32_t b = 0, z = 0, o = 0;      // current pass as digits (b >= nblk: past the end)
+
+    __host__ __device__ void digits(int64_t n, uint32_t& db, uint32_t& dz, uint32_t& d0) const {
+        if (n >= g.npass) {
+            db = g.nblk;
+            dz = d0 = 0;
+            return;
+        }
+        const uint32_t u = static_cast<uint32_t>(n);
+        db = g.per_blk.div(u);
+        const uint32_t r = u - db * (g.Lz * g.pf);
+        dz = g.per_piece.div(r);
+        d0 = r - dz * g.pf;
+    }
+    __host__ __device__ void init(const SlabGeom& geom, int64_t p0, int64_t stride) {
+        g = geom;
+        digits(p0, b, z, o);
+        digits(stride, sb, sz, so);
+    }
+    // first row and row count of the current pass (0 rows past the end)
+    __host__ __device__ void cur(int64_t& row0, int64_t& nr) const {
+        if (b >= g.nblk) {
+            row0 = g.nrows;
+            nr = 0;
+            return;
+        }
+        row0 = static_cast<int64_t>(z) * g.plane_rows + static_cast<int64_t>(b) * g.rows_full +
+               static_cast<int64_t>(o) * g.rpw;
+        const uint32_t left = g.rows_full - o * g.rpw;
+        nr = left < g.rpw ? left : g.rpw;
+    }
+    __host__ __device__ void advance() {
+        if (b >= g.nblk) return;
+        o += so;
+        uint32_t c = o >= g.pf ? 1u : 0u;
+        o -= c * g.pf;
+        z += sz + c;
+        c = z >= g.Lz ? 1u : 0u;
+        z -= c * g.Lz;
+        b += sb + c;
+    }
+};
+
+// Natural row order with the same interface: pass p covers rows p * rpw ..
+// nr is always rpw: rows past the end lie outside every buffer descriptor
+// (loads read 0, stores are dropped) and the kernels mask their scalar
+// products with row < N, so the pass size stays a compile-time constant.
+struct RowWalk {
+    int64_t p = 0, stride = 1, npass = 0, nrows = 0;
     int rpw = 1;
-    __host__ __device__ void init(int64_t n, int rpw_) {
+    __host__ __device__ void init(int64_t n, int rpw_, int64_t p0, int64_t stride_) {
         nrows = n;
         rpw = rpw_;
         npass = (n + rpw - 1) / rpw;
+        p = p0;
+        stride = stride_;
     }
-    // nr is always rpw: rows past the end lie outside every buffer
-    // descriptor (loads read 0, stores are dropped) and the kernels mask
-    // their scalar products with row < N, so the pass size stays a
-    // compile-time constant
-    __host__ __device__ void pass(int64_t p, int64_t& row0, int64_t& nr) const {
+    __host__ __device__ void cur(int64_t& row0, int64_t& nr) const {
         row0 = p < npass ? p * rpw : nrows;
         nr = rpw;
     }
+    __host__ __device__ void advance() { p += stride; }
 };
 
 // Pass order of a kernel: the slab order (SLAB) or the natural one.
 template <bool SLAB> struct PassOrder;
 template <> struct PassOrder<true> {
-    Slabs o;
-    __device__ void init(int64_t, int Lx, int Ly, int Lz, int lines, int rpw) { o.init(Lx, Ly, Lz, lines, rpw); }
-    __device__ int64_t npass() const { return o.npass; }
-    __device__ void pass(int64_t p, int64_t& row0, int64_t& nr) const { o.pass(p, row0, nr); }
+    SlabWalk w;
+    __device__ void init(int64_t, const SlabGeom& g, int, int64_t p0, int64_t stride) { w.init(g, p0, stride); }
+    __device__ int64_t npass() const { return w.g.npass; }
+    __device__ void cur(int64_t& row0, int64_t& nr) const { w.cur(row0, nr); }
+    __device__ void advance() { w.advance(); }
 };
 template <> struct PassOrder<false> {
-    RowPasses o;
-    __device__ void init(int64_t n, int, int, int, int, int rpw) { o.init(n, rpw); }
-    __device__ int64_t npass() const { return o.npass; }
-    __device__ void pass(int64_t p, int64_t& row0, int64_t& nr) const { o.pass(p, row0, nr); }
+    RowWalk w;
+    __device__ void init(int64_t n, const SlabGeom&, int rpw, int64_t p0, int64_t stride) { w.init(n, rpw, p0, stride); }
+    __device__ int64_t npass() const { return w.npass; }
+    __device__ void cur(int64_t& row0, int64_t& nr) const { w.cur(row0, nr); }
+    __device__ void advance() { w.advance(); }
 };
 
 template <typename T, int R, int WAVES>
@@ -299,9 +352,9 @@ batched_kernel(const BatchInst* __restrict__ insts, const int32_t* __restrict__ 
         if (idx >= n_inst) break;
         const BatchInst d = insts[order[idx]];
         const int64_t N = d.nrows;
-        PassOrder<SLAB> sl;
-        sl.init(N, d.L[0], d.L[1], d.L[2], slab, RPW);
-        const int64_t npass = sl.npass();
+        PassOrder<SLAB> sl0;   // this wave's passes wave, wave + WAVES, ... (every sweep)
+        sl0.init(N, d.geom, RPW, wave, WAVES);
+        const int64_t npass = sl0.npass();
         const uint64_t vbytes = static_cast<uint64_t>(N) * R * kCB;
         const __amdgpu_buffer_rsrc_t val_rs = rsrc(d.val, static_cast<uint64_t>(N) * kVW * 4);
         const __amdgpu_buffer_rsrc_t col_rs = rsrc(d.col, static_cast<uint64_t>(N) * kWidth * 4);
@@ -352,8 +405,9 @@ batched_kernel(const BatchInst* __restrict__ insts, const int32_t* __restrict__ 
             typename WV::type wv[S::kLoadsV];
             typename WC::type wc[S::kLoadsC];
             int buf = 0;
+            PassOrder<SLAB> sl = sl0;
             int64_t row0, nr;
-            sl.pass(wave, row0, nr);
+            sl.cur(row0, nr);
             if constexpr (S::kAhead) {
                 fetch(row0, wv, wc);
                 put(stage[wave][0], wv, wc);
@@ -390,7 +444,8 @@ batched_kernel(const BatchInst* __restrict__ insts, const int32_t* __restrict__ 
                 const Cv wo = LV::template load<kStream<R>>(wold_rs, off);
                 // matrix rows of this wave's next pass (zeros past the end)
                 int64_t row0n, nrn;
-                sl.pass(q + WAVES, row0n, nrn);
+                sl.advance();
+                sl.cur(row0n, nrn);
                 if constexpr (S::kAhead) fetch(row0n, wv, wc);
                 const int* sv = st + sub * kVW;
                 Cv acc;

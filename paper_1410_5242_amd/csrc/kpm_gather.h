@@ -59,7 +59,7 @@ template <typename T, int R, int WAVES, int VARIANT, bool SLAB, int AUX>
 __global__ void __launch_bounds__(64 * WAVES, (min_waves<T, R, WAVES>()))
 gather_sweep_kernel(const T* __restrict__ val, const int32_t* __restrict__ col, int64_t N,
                     const T* __restrict__ V, T* __restrict__ W, T alpha, T beta, T gamma,
-                    double* __restrict__ partials, int xcd_ways, int Lx, int Ly, int Lz, int lines) {
+                    double* __restrict__ partials, int xcd_ways, SlabGeom geom) {
     using S = Shape<T, R>;
     constexpr int CPL = S::CPL;
     using LV = Lanes<T, CPL>;
@@ -86,11 +86,12 @@ gather_sweep_kernel(const T* __restrict__ val, const int32_t* __restrict__ col, 
     const int xcd = blockIdx.x % X;
     const int per = ngrid / X;
     batch::PassOrder<SLAB> sl;
-    sl.init(N, Lx, Ly, Lz, lines, RPW);
+    sl.init(N, geom, RPW, 0, 1);
     const int64_t npass = sl.npass();
     const int64_t lo = npass * xcd / X, hi = npass * (xcd + 1) / X;
     const int64_t stride = static_cast<int64_t>(per) * WAVES;
     const int64_t q0 = lo + static_cast<int64_t>(blockIdx.x / X) * WAVES + wave;
+    sl.init(N, geom, RPW, q0, stride);   // this wave's passes q0, q0 + stride, ...
 
     const uint64_t vbytes = static_cast<uint64_t>(N) * R * kCB;
     const __amdgpu_buffer_rsrc_t val_rs = rsrc(val, static_cast<uint64_t>(N) * kVW * 4);
@@ -127,7 +128,7 @@ gather_sweep_kernel(const T* __restrict__ val, const int32_t* __restrict__ col, 
     typename WC::type wc[S::kLoadsC];
     int buf = 0;
     int64_t row0, nr;
-    sl.pass(q0, row0, nr);
+    sl.cur(row0, nr);
     if constexpr (S::kAhead) {
         fetch(row0, wv, wc);
         put(stage[wave][0], wv, wc);
@@ -162,7 +163,8 @@ gather_sweep_kernel(const T* __restrict__ val, const int32_t* __restrict__ col, 
         }
         const Cv wo = LV::template load<AUX>(wold_rs, off);
         int64_t row0n, nrn;
-        sl.pass(q + stride, row0n, nrn);
+        sl.advance();
+        sl.cur(row0n, nrn);
         if constexpr (S::kAhead) fetch(row0n, wv, wc);
         const int* sv = st + sub * kVW;
         Cv acc;
@@ -234,10 +236,10 @@ gather_sweep_kernel(const T* __restrict__ val, const int32_t* __restrict__ col, 
 
 template <typename T, int R, int WAVES, int VARIANT, bool SLAB, int AUX>
 void launch_k(const SweepArgs& a, hipStream_t s) {
+    const SlabGeom geom = SLAB ? SlabGeom::make(a.L[0], a.L[1], a.L[2], a.slab, Shape<T, R>::RPW) : SlabGeom{};
     gather_sweep_kernel<T, R, WAVES, VARIANT, SLAB, AUX><<<a.grid, 64 * WAVES, 0, s>>>(
         static_cast<const T*>(a.val), a.col, a.nrows, static_cast<const T*>(a.V), static_cast<T*>(a.W),
-        static_cast<T>(a.alpha), static_cast<T>(a.beta), static_cast<T>(a.gamma), a.partials, a.xcd_ways,
-        SLAB ? a.L[0] : 0, SLAB ? a.L[1] : 0, SLAB ? a.L[2] : 0, SLAB ? a.slab : 0);
+        static_cast<T>(a.alpha), static_cast<T>(a.beta), static_cast<T>(a.gamma), a.partials, a.xcd_ways, geom);
 }
 
 // Bytes a sweep streams; above the 256 MB Infinity Cache nothing it reads

@@ -101,6 +101,61 @@ int lattice_tiles(const kpm_hamiltonian* H);
 int lattice_grid(const kpm_hamiltonian* H);
 hipError_t launch_lattice(int dtype, int variant, const LatticeArgs& a, hipStream_t s);
 
+// Unsigned 32-bit division by a divisor fixed on the host: multiply-high by
+// a rounded-up reciprocal (the round-up method of Granlund and Montgomery),
+// exact for every 32-bit dividend.  The reciprocal is computed on the host,
+// so the kernels only multiply (scalar instructions); a division by a
+// run-time value would be expanded on the vector unit.
+struct FastDiv {
+    uint32_t d = 1, m = 0, s = 0;
+    void init(uint32_t d_) {   // host
+        d = d_ ? d_ : 1;
+        m = 0;
+        s = 0;
+        if (d == 1) return;
+        uint32_t l = 0;
+        while ((1ull << l) < d) ++l;                       // ceil(log2 d), d >= 2
+        m = static_cast<uint32_t>(((1ull << 32) * ((1ull << l) - d)) / d + 1);
+        s = l - 1;
+    }
+    __host__ __device__ uint32_t div(uint32_t n) const {
+        if (d == 1) return n;
+#if defined(__HIP_DEVICE_COMPILE__)
+        const uint32_t t = __umulhi(n, m);
+#else
+        const uint32_t t = static_cast<uint32_t>((static_cast<uint64_t>(n) * m) >> 32);
+#endif
+        return (t + ((n - t) >> 1)) >> s;
+    }
+};
+
+// Geometry of the slab order of one lattice, built on the host: blocks of
+// `lines` y-lines (the largest divisor of Ly not above the request, so all
+// blocks are whole), each walked plane by plane in pieces of rpw rows.
+struct SlabGeom {
+    uint32_t pf = 1, Lz = 1, nblk = 0, rpw = 1, rows_full = 0, plane_rows = 0;
+    FastDiv per_blk, per_piece;   // Lz * pf, pf
+    int64_t npass = 0, nrows = 0;
+
+    static SlabGeom make(int Lx, int Ly, int Lz, int lines, int rpw) {   // host
+        SlabGeom g;
+        if (lines <= 0 || lines > Ly) lines = Ly;
+        while (Ly % lines) --lines;
+        g.Lz = static_cast<uint32_t>(Lz);
+        g.rpw = static_cast<uint32_t>(rpw);
+        const uint32_t line_rows = 4u * static_cast<uint32_t>(Lx);
+        g.plane_rows = line_rows * static_cast<uint32_t>(Ly);
+        g.rows_full = line_rows * static_cast<uint32_t>(lines);
+        g.nblk = static_cast<uint32_t>(Ly / lines);
+        g.pf = (g.rows_full + g.rpw - 1) / g.rpw;
+        g.npass = static_cast<int64_t>(g.nblk) * g.Lz * g.pf;
+        g.nrows = static_cast<int64_t>(g.plane_rows) * g.Lz;
+        g.per_blk.init(g.Lz * g.pf);
+        g.per_piece.init(g.pf);
+        return g;
+    }
+};
+
 // One instance of the batched solver (device-side descriptor).
 struct BatchInst {
     const void* val;        // H: [N][kWidth] complex, diagonal in slot 0
@@ -115,7 +170,11 @@ struct BatchInst {
     double shift;           // b/a
     int32_t L[3];           // lattice sides (rows 4 (x + Lx (y + Ly z)) + o)
     int32_t pad;
+    SlabGeom geom;          // slab pass order of this instance (used when the slab tuning is on)
 };
+
+// Rows per pass of the batched solver's waves (the slab geometry needs it).
+int batched_rows_per_pass(int dtype, int R);
 
 struct BatchArgs {
     const BatchInst* inst;  // [n_inst]

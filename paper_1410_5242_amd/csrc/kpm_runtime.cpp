@@ -669,7 +669,11 @@ kpm_status kpm_moments_batched(const kpm_hamiltonian* const* H, const void* cons
         char* base = static_cast<char*>(b.vec) + voff[i];
         inst[i] = BatchInst{H[i]->val, H[i]->col, V0[i], base, base + blk, b.eta + eta_per * i,
                             mu + static_cast<size_t>(i) * R * M, H[i]->nrows, 1.0 / H[i]->a, H[i]->b / H[i]->a,
-                            {H[i]->L[0], H[i]->L[1], H[i]->L[2]}, 0};
+                            {H[i]->L[0], H[i]->L[1], H[i]->L[2]}, 0,
+                            g_batch_tuning.slab > 0
+                                ? SlabGeom::make(H[i]->L[0], H[i]->L[1], H[i]->L[2], g_batch_tuning.slab,
+                                                 batched_rows_per_pass(dtype, R))
+                                : SlabGeom{}};
     }
     // longest first (greedy longest-processing-time order), ties by index
     std::vector<int32_t> order(n_inst);

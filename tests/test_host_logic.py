@@ -1,8 +1,9 @@
 """Host-side logic of the HIP sources, compiled for the host only.
 
-The pass order of the staged-gather and batched sweeps (batch::Slabs) is
-__host__ __device__ code; tests/host/pass_order.cpp checks it exhaustively on
-small lattices.
+The pass orders of the staged-gather and batched sweeps (batch::Slabs, the
+incremental batch::SlabWalk the kernels use, and kpm::FastDiv) are
+__host__ __device__ code; tests/host/pass_order.cpp checks them exhaustively
+on small lattices.
 """
 import os
 import shutil
