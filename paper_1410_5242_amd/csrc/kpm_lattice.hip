@@ -36,10 +36,11 @@
 //     the scalar words are fetched from (or which lane is read), so the
 //     product loop has no data-dependent selects.
 //
-// Work distribution: tiles are numbered row-major over the tile grid and
-// split into 8 contiguous ranges; workgroup g takes range g % 8 (the die the
-// dispatcher deals it to) and strides over it, so that the tiles a die
-// holds in its L2 are spatial neighbours.
+// Work distribution: workgroup g works for die g % 8 (the die the
+// dispatcher deals it to) and strides over that die's tiles: by default a
+// 2-D block of the tile grid (most edge rows a tile gathers then belong to
+// tiles of the same die and its L2), else a run of tile rows or no die
+// mapping (tuning tile_order).
 #include "kpm_sweep.h"
 
 namespace kpm {
@@ -178,11 +179,6 @@ __device__ inline Nb xy_neighbour(int nx, int ny, int Lx, int Ly, int px, int py
         r.idx = nx + Lx * ny;
     }
     return r;
-}
-
-template <typename T>
-__device__ inline T wload(const T* p, bool nt) {
-    return nt ? __builtin_nontemporal_load(p) : *p;
 }
 
 // VALS: how the matrix rows reach the FMAs as wave-uniform operands.
