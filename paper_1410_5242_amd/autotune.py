@@ -324,13 +324,16 @@ def apply_batched(cache: TuningCache, Hs, R: int) -> bool:
 # --------------------------------------------------------------------------
 HEADLINE_L = (64, 64, 64)
 FAMILY = dict(n=512, sides=(12, 16, 20, 24), gamma_max=4.0, seed=0, R=8, M=512)
+TTD_INSTANCES, TTD_M = 1000, 256   # time-to-DOS family (tuned at a mid-range number of moments)
 
 
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description="Tune launch shapes on the benchmark workloads (64^3 TI lattice "
                                              "at every block width; the 512-instance family) and write the cache")
     ap.add_argument("--out", default=DEFAULT_CACHE)
-    ap.add_argument("--parts", default="sweep,batched", help="sweep, batched (comma separated)")
+    ap.add_argument("--parts", default="sweep,batched,ttd",
+                    help="sweep, batched, ttd (the time-to-DOS family: 1,000 learned-family instances, R = 16, "
+                         "complex64), comma separated")
     ap.add_argument("--widths", default="1,2,4,8,16,32,64")
     args = ap.parse_args(argv)
     import numpy as np
@@ -361,6 +364,17 @@ def main(argv=None) -> int:
         for H in Hs:
             H.close()
         del np
+    if "ttd" in parts:
+        from . import learned as LN
+        fam = LN.family(TTD_INSTANCES, LN.TEST_SEED + 7)
+        Hs = LN.build(fam, "c64")
+        V0s = LN.start_blocks(fam, Hs, LN.R_TRUTH, "c64")
+        torch.cuda.synchronize()
+        res = tune_batched(Hs, V0s, TTD_M, cache)
+        print(f"[autotune] {res.key}: {res.seconds:.4f} s with {res.best}", flush=True)
+        cache.save()
+        for H in Hs:
+            H.close()
     print(f"[autotune] wrote {args.out}", flush=True)
     return 0
 

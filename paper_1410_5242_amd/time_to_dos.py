@@ -25,6 +25,7 @@ import time
 import numpy as np
 import torch
 
+from . import autotune as AT
 from . import kpm as K
 from . import learned as LN
 
@@ -54,7 +55,11 @@ def run(n_inst: int = 1000, eps_list=(0.05, 0.02), per_instance_sample: int = 10
     p = K.dos_batched(mu_truth, a, b, E, masses=True)
     err_M = {M: float(LN.l1(K.dos_batched(mu_truth, a, b, E, M=M, masses=True), p).mean()) for M in M_CHOICES}
     net, _ = LN.load_weights(weights, max_batch=1024)
+    # batched launch shape from the committed tuning cache (tuned on this family); it then holds for
+    # every batched call below, the fallback reruns included
+    tuned = AT.apply_batched(AT.TuningCache(), H64, R)
     out = {"n_instances": n_inst, "R": R, "truth_M": LN.M_TRUTH, "build_s": round(build_s, 2),
+           "batched_tuning": dict(K.get_batch_tuning(), autotuned=tuned),
            "kpm_mean_l1_by_M": {str(k): round(v, 5) for k, v in err_M.items()},
            "per_instance_variants_timed_on": per_instance_sample, "targets": {}}
     rho = torch.empty((n_inst, LN.K_BINS), dtype=torch.float64, device="cuda")
@@ -112,6 +117,7 @@ def run(n_inst: int = 1000, eps_list=(0.05, 0.02), per_instance_sample: int = 10
         out["targets"][str(eps)] = res
         log(f"[time-to-dos] eps {eps}: M={M} " + " ".join(f"{k}={v['seconds']}s" for k, v in res.items()
                                                           if isinstance(v, dict)))
+    K.reset_batch_tuning()
     for H in H128 + H64:
         H.close()
     net.close()
