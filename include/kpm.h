@@ -200,13 +200,16 @@ kpm_status kpm_moment_features(const double* mu, int32_t n_inst, int32_t R, int3
  *                step ahead, handed over lane by lane; 1 scalar loads whose
  *                lines a vector load pulled into L2 a step ahead; 0 scalar
  *                loads when the row is computed; default 2
- *   lattice      1 (default): at R = 32, on lattices with at least 128
- *                4 x 4-site pencils, use the cache-blocked sweep that keeps a
- *                ring of z-planes of V in LDS (of the other fields only
- *                prefetch, stream, tile_order and wg_per_cu apply to it;
+ *   lattice      1 (default): at R = 32 and 64, on lattices with at least
+ *                128 4 x 4-site pencils, use the cache-blocked sweep that
+ *                keeps a ring of z-planes of V in LDS (of the other fields
+ *                only prefetch, stream, tile_order and wg_per_cu apply to it;
  *                wg_per_cu is capped at the 1 (complex128) or 2 (complex64)
- *                workgroups whose LDS fits on a CU, default 1); 2: use it
- *                whenever R = 32; 0: the generic gather sweep
+ *                workgroups whose LDS fits on a CU, default 1; at R = 64 it
+ *                sweeps the two 32-column halves of the block one after the
+ *                other, reading the matrix once per half, and always takes
+ *                prefetch 2); 2: use it whenever R is 32 or 64; 0: the
+ *                generic gather sweep
  *   stream       bit 0: old-W loads, bit 1: new-W stores carry the
  *                non-temporal hint (W is touched once per sweep, unlike the
  *                V rows, which are gathered 13 times), so that L2 keeps the

@@ -75,7 +75,8 @@ def sweep_candidates(R: int, lattice_ok: bool) -> list[dict]:
                     out.append(dict(base, gather=2, prefetch=0, wg_per_cu=wg, chunk_tiles=chunk, pencil=pencil,
                                     stream=stream))
     if lattice_ok:
-        for prefetch in (2, 1):
+        # wider blocks always take the record path (prefetch 2)
+        for prefetch in ((2, 1) if R == 32 else (2,)):
             for stream in (3, 0):
                 for order in (0, 1, 2):
                     for wg in (0, 2):

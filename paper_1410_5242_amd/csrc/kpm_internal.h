@@ -82,7 +82,7 @@ struct SweepArgs {
     int slab = 0;           // staged-gather sweep: y-lines per block of the pass order
 };
 
-// Cache-blocked sweep for the library's lattice Hamiltonians at R = 32.
+// Cache-blocked sweep for the library's lattice Hamiltonians at R = 32 k.
 struct LatticeArgs {
     const void* val;
     const void* V;
@@ -95,6 +95,7 @@ struct LatticeArgs {
     int prefetch;       // matrix rows through one vector load per site (a step ahead)
     int stream;         // non-temporal hint: bit 0 old-W loads, bit 1 new-W stores
     int order;          // tiles to dies: 0 2-D blocks, 1 runs of tile rows, 2 none
+    int R;              // block width, a multiple of 32
 };
 bool lattice_supported(const kpm_hamiltonian* H, int R);
 int lattice_tiles(const kpm_hamiltonian* H);

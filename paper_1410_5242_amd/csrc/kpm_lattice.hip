@@ -1,9 +1,11 @@
-// Cache-blocked fused sweep for lattice Hamiltonians at R = 32.
+// Cache-blocked fused sweep for lattice Hamiltonians at R = 32 (and 64).
 //
 // The generic sweep gathers all 13 neighbour rows of every output row from
 // global memory; at R = 32 that is 13 x 512 B per row through each CU's
 // texture path, whose address/data units then limit the sweep long before
-// HBM does.  This kernel exploits what the library knows about its own
+// HBM does.  Wider blocks are swept one 32-column slice at a time (a wave
+// holds one real of each of 32 columns; the LDS ring has room for one
+// slice of V at complex128), reading the matrix once per slice.  This kernel exploits what the library knows about its own
 // matrix: slot j of row (n, o) couples to a fixed lattice neighbour of site
 // n (slot order as written by the builder: diagonal, then for x, y, z the
 // neighbours n - e_j and n + e_j, each with the same orbital and with the
@@ -58,10 +60,13 @@ constexpr int kR = 32;           // block width handled here
 constexpr int kE = 2 * kR;       // reals per block row = lanes per wave
 constexpr int kThreadsL = 64 * kNW;
 
+// V and W rows hold R = 32 nsl columns; a wave works on one 32-column slice
+// of a row: voff = byte offset of this lane's value within the row (slice
+// and lane), soff = byte offset of the row.  The whole array is below 4 GiB,
+// so 32-bit offsets suffice.
 template <typename T>
-__device__ inline T gload(__amdgpu_buffer_rsrc_t rs, int lane, int64_t row) {
-    return sweep::buffer_load<T>(rs, static_cast<unsigned>(lane * sizeof(T)),
-                                 static_cast<unsigned>(row * kE * static_cast<int64_t>(sizeof(T))));
+__device__ inline T gload(__amdgpu_buffer_rsrc_t rs, unsigned voff, unsigned soff) {
+    return sweep::buffer_load<T>(rs, voff, soff);
 }
 
 typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
@@ -69,9 +74,7 @@ typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
 // Row `row` of W through a buffer descriptor (one lane offset VGPR shared by
 // every access); NT selects the non-temporal cache policy.
 template <typename T, bool NT>
-__device__ inline T wload(__amdgpu_buffer_rsrc_t rs, int lane, int64_t row) {
-    const unsigned voff = static_cast<unsigned>(lane * sizeof(T));
-    const unsigned soff = static_cast<unsigned>(row * kE * static_cast<int64_t>(sizeof(T)));
+__device__ inline T wload(__amdgpu_buffer_rsrc_t rs, unsigned voff, unsigned soff) {
     constexpr int aux = NT ? 2 : 0;
     if constexpr (sizeof(T) == 8)
         return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(rs, voff, soff, aux));
@@ -79,9 +82,7 @@ __device__ inline T wload(__amdgpu_buffer_rsrc_t rs, int lane, int64_t row) {
         return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(rs, voff, soff, aux));
 }
 template <typename T, bool NT>
-__device__ inline void wstore(T x, __amdgpu_buffer_rsrc_t rs, int lane, int64_t row) {
-    const unsigned voff = static_cast<unsigned>(lane * sizeof(T));
-    const unsigned soff = static_cast<unsigned>(row * kE * static_cast<int64_t>(sizeof(T)));
+__device__ inline void wstore(T x, __amdgpu_buffer_rsrc_t rs, unsigned voff, unsigned soff) {
     constexpr int aux = NT ? 2 : 0;
     if constexpr (sizeof(T) == 8)
         __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, x), rs, voff, soff, aux);
@@ -187,11 +188,12 @@ __device__ inline Nb xy_neighbour(int nx, int ny, int Lx, int Ly, int px, int py
 //   2  scalar loads, with the site's rows pulled into L2 by a vector load a
 //      step ahead (the scalar loads then wait on L2, not on HBM)
 
-template <typename T, int VARIANT, int VALS, int STREAM>
+// NSL: 32-column slices per block row (0: run-time value nsl, for R > 32)
+template <typename T, int VARIANT, int VALS, int STREAM, int NSL>
 __global__ void __launch_bounds__(kThreadsL)
 lattice_kernel(const T* __restrict__ val, const T* __restrict__ V, T* __restrict__ W,
                T alpha, T beta, T gamma, double* __restrict__ partials,
-               int Lx, int Ly, int Lz, int px, int py, int pz, int ntx, int ntiles, int order) {
+               int Lx, int Ly, int Lz, int px, int py, int pz, int ntx, int ntiles, int order, int nsl) {
     __shared__ T ring[4][kNW][4][kE];
     __shared__ T zrow[4][kE];          // rows of zeros: neighbours beyond an open side
     __shared__ double red[kNW][3][kR];
@@ -212,7 +214,14 @@ lattice_kernel(const T* __restrict__ val, const T* __restrict__ V, T* __restrict
     // size 0: loads return 0 and stores are dropped, so every wave issues
     // the same sequence of memory instructions each step and the compiler's
     // memory-counter waits stay exact.
-    const unsigned vbytes = static_cast<unsigned>(nrows * kE * static_cast<int64_t>(sizeof(T)));
+    const int nslice = NSL > 0 ? NSL : nsl;
+    const unsigned rowb = static_cast<unsigned>(nslice * kE * static_cast<int>(sizeof(T)));
+    const unsigned vbytes = static_cast<unsigned>(nrows * rowb);
+    // byte offset of a row of V or W
+    auto roff = [&](int64_t row) -> unsigned {
+        if constexpr (NSL == 1) return static_cast<unsigned>(row * kE * static_cast<int64_t>(sizeof(T)));
+        else return static_cast<unsigned>(row) * rowb;
+    };
     const unsigned mbytes = static_cast<unsigned>(nrows * 2 * kWidth * static_cast<int64_t>(sizeof(T)));
     auto rsrc = [](const void* p, unsigned bytes) {
         return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, static_cast<int>(bytes),
@@ -225,8 +234,6 @@ lattice_kernel(const T* __restrict__ val, const T* __restrict__ V, T* __restrict
     auto mrs = [&](bool on) { return rsrc(val, on ? mbytes : 0u); };
 
     if (wave < 4) zrow[wave][lane] = T(0);
-
-    double acc_e = 0.0, acc_or = 0.0, acc_oi = 0.0;
 
     const int ngrid = gridDim.x;
     const int X = (order != 2 && ngrid % kXcds == 0) ? kXcds : 1;
@@ -243,6 +250,12 @@ lattice_kernel(const T* __restrict__ val, const T* __restrict__ V, T* __restrict
 
     constexpr bool VEC_VALS = VALS == 1;
     unsigned sink = 0;   // keeps the L2 warm-up loads of VALS == 2
+
+    // Blocks wider than 32 columns: every workgroup sweeps its tiles once per
+    // 32-column slice (the matrix is read once per slice).
+    for (int sl = 0; sl < nslice; ++sl) {
+    const unsigned voff = static_cast<unsigned>((sl * kE + lane) * static_cast<int>(sizeof(T)));
+    double acc_e = 0.0, acc_or = 0.0, acc_oi = 0.0;
 
     for (int k = k_lo + slot; k < k_hi; k += per) {
         int tx = k % ntx, ty = k / ntx;
@@ -310,9 +323,9 @@ lattice_kernel(const T* __restrict__ val, const T* __restrict__ V, T* __restrict
             const __amdgpu_buffer_rsrc_t hx = vrs(on && hx_on);
             const __amdgpu_buffer_rsrc_t hy = vrs(on && hy_on);
 #pragma unroll
-            for (int o = 0; o < 4; ++o) r.h[0][o] = gload<T>(hx, lane, 4 * (hxs + plane_sites * z) + o);
+            for (int o = 0; o < 4; ++o) r.h[0][o] = gload<T>(hx, voff, roff(4 * (hxs + plane_sites * z) + o));
 #pragma unroll
-            for (int o = 0; o < 4; ++o) r.h[1][o] = gload<T>(hy, lane, 4 * (hys + plane_sites * z) + o);
+            for (int o = 0; o < 4; ++o) r.h[1][o] = gload<T>(hy, voff, roff(4 * (hys + plane_sites * z) + o));
             const int64_t base = 4 * (sxy + plane_sites * z);
             if constexpr (VALS == 1) r.hv = SiteRec<T>::load(mrs(on && active), rec_off, base / 4);
         };
@@ -321,13 +334,13 @@ lattice_kernel(const T* __restrict__ val, const T* __restrict__ V, T* __restrict
             const __amdgpu_buffer_rsrc_t wl = wrs(on && active && need_w);
             const int64_t base = 4 * (sxy + plane_sites * (on ? zp : 0));
 #pragma unroll
-            for (int o = 0; o < 4; ++o) r.w[o] = wload<T, (STREAM & 1) != 0>(wl, lane, base + o);
+            for (int o = 0; o < 4; ++o) r.w[o] = wload<T, (STREAM & 1) != 0>(wl, voff, roff(base + o));
         };
         auto load_plane = [&](bool on, int zp, T (&p)[4]) {
             const __amdgpu_buffer_rsrc_t rs = vrs(on && active);
             const int64_t base = 4 * (sxy + plane_sites * (on ? zp : 0));
 #pragma unroll
-            for (int o = 0; o < 4; ++o) p[o] = gload<T>(rs, lane, base + o);
+            for (int o = 0; o < 4; ++o) p[o] = gload<T>(rs, voff, roff(base + o));
         };
 
         // One z-step.  Register sets alternate between even and odd steps,
@@ -412,11 +425,11 @@ lattice_kernel(const T* __restrict__ val, const T* __restrict__ V, T* __restrict
                 }
                 const T hv = fma(sgn, swap_lanes(B), A);
                 if constexpr (VARIANT == KPM_PLAIN) {
-                    wstore<T, (STREAM & 2) != 0>(hv, wst, lane, row);
+                    wstore<T, (STREAM & 2) != 0>(hv, wst, voff, roff(row));
                 } else {
                     // cur.w holds zeros when no old W is read (need_w false)
                     const T w = fma(gamma, cur.w[o], fma(alpha, hv, beta * v[0]));
-                    wstore<T, (STREAM & 2) != 0>(w, wst, lane, row);
+                    wstore<T, (STREAM & 2) != 0>(w, wst, voff, roff(row));
                     if constexpr (VARIANT == KPM_FULL) {
                         const double vd = static_cast<double>(v[0]);
                         const double vsw = static_cast<double>(swap_lanes(v[0]));
@@ -464,8 +477,8 @@ lattice_kernel(const T* __restrict__ val, const T* __restrict__ V, T* __restrict
         }
         if (s < Lz) step(s, ra, rb);
     }
-    asm volatile("" ::"s"(sink));
 
+    // this slice's columns of the workgroup's [3][R] partial sums
     if constexpr (VARIANT == KPM_FULL) {
         const double e = acc_e + swap_pair(acc_e);
         const double o_r = acc_or + swap_pair(acc_or);
@@ -476,33 +489,43 @@ lattice_kernel(const T* __restrict__ val, const T* __restrict__ V, T* __restrict
             red[wave][2][lane >> 1] = o_i;
         }
         __syncthreads();
+        const int64_t R = static_cast<int64_t>(nslice) * kR;
         for (int i = threadIdx.x; i < 3 * kR; i += kThreadsL) {
             const int q = i / kR, r = i % kR;
             double sum = 0.0;
             for (int w = 0; w < kNW; ++w) sum += red[w][q][r];
-            partials[static_cast<int64_t>(blockIdx.x) * 3 * kR + i] = sum;
+            partials[static_cast<int64_t>(blockIdx.x) * 3 * R + q * R + sl * kR + r] = sum;
         }
+        __syncthreads();   // red is rewritten by the next slice
     }
+    }
+    asm volatile("" ::"s"(sink));
 }
 
 template <typename T, int STREAM>
 hipError_t launch_ts(int variant, const LatticeArgs& a, hipStream_t s) {
     const int ntx = (a.L[0] + kP - 1) / kP, nty = (a.L[1] + kP - 1) / kP;
     const int ntiles = ntx * nty;
-#define KPM_LAUNCH(VAR, VALS)                                                                    \
-    lattice_kernel<T, VAR, VALS, STREAM><<<a.grid, kThreadsL, 0, s>>>(                           \
+#define KPM_LAUNCH(VAR, VALS, NSL)                                                               \
+    lattice_kernel<T, VAR, VALS, STREAM, NSL><<<a.grid, kThreadsL, 0, s>>>(                      \
         static_cast<const T*>(a.val), static_cast<const T*>(a.V), static_cast<T*>(a.W),          \
         static_cast<T>(a.alpha), static_cast<T>(a.beta), static_cast<T>(a.gamma), a.partials,  \
-        a.L[0], a.L[1], a.L[2], a.periodic[0], a.periodic[1], a.periodic[2], ntx, ntiles, a.order)
+        a.L[0], a.L[1], a.L[2], a.periodic[0], a.periodic[1], a.periodic[2], ntx, ntiles, a.order, \
+        a.R / kR)
 // tuning `prefetch`: 2 (default) the site's matrix record a step ahead in
 // registers (VALS 1), 1 scalar loads after an L2 warm-up (VALS 2), 0 plain
-// scalar loads
+// scalar loads.  Blocks wider than 32 columns always take the record path.
 #define KPM_LAUNCH_V(VAR)                          \
-    switch (a.prefetch) {                          \
-    case 2: KPM_LAUNCH(VAR, 1); break;             \
-    case 1: KPM_LAUNCH(VAR, 2); break;             \
-    default: KPM_LAUNCH(VAR, 0); break;            \
+    if (a.R > kR) {                                \
+        KPM_LAUNCH(VAR, 1, 0);                     \
+    } else {                                       \
+        switch (a.prefetch) {                      \
+        case 2: KPM_LAUNCH(VAR, 1, 1); break;      \
+        case 1: KPM_LAUNCH(VAR, 2, 1); break;      \
+        default: KPM_LAUNCH(VAR, 0, 1); break;     \
+        }                                          \
     }
+    if (a.R <= 0 || a.R % kR != 0) return hipErrorInvalidValue;
     switch (variant) {
     case KPM_FULL: KPM_LAUNCH_V(KPM_FULL); break;
     case KPM_NODOT: KPM_LAUNCH_V(KPM_NODOT); break;
@@ -532,7 +555,7 @@ int lattice_tiles(const kpm_hamiltonian* H) {
 }
 
 bool lattice_supported(const kpm_hamiltonian* H, int R) {
-    if (R != lattice::kR) return false;
+    if (R <= 0 || R % lattice::kR != 0) return false;
     // every tile must be at least 2 sites wide in x and y (at most one
     // neighbour across each tile edge): no side with L mod 4 == 1
     if (H->L[0] % lattice::kP == 1 || H->L[1] % lattice::kP == 1) return false;

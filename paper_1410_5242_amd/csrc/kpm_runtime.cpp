@@ -175,7 +175,7 @@ hipError_t launch_any_sweep(kpm_hamiltonian* H, int R, int variant, const SweepA
     if (use_lattice(H, R)) {
         LatticeArgs la{H->val, a.V, a.W, a.alpha, a.beta, a.gamma, a.partials,
                        {H->L[0], H->L[1], H->L[2]}, {H->periodic[0], H->periodic[1], H->periodic[2]}, a.grid,
-                       get_tuning().prefetch, get_tuning().stream, get_tuning().tile_order};
+                       get_tuning().prefetch, get_tuning().stream, get_tuning().tile_order, R};
         return profiled(s, [&] { return launch_lattice(H->dtype, variant, la, s); });
     }
     return profiled(s, [&] { return launch_sweep(H->dtype, R, variant, a, s); });

@@ -248,6 +248,36 @@ def test_lattice_sweep_matches_oracle(L, periodic, dtype, vals):
         assert np.abs(got_eta - ref_eta).max() <= TOL_C128
 
 
+# blocks wider than 32 columns: the lattice sweep runs once per 32-column
+# slice; every slice writes its own columns of W and of the partial sums
+WIDE_GEOMETRIES = [LATTICE_GEOMETRIES[i] for i in (1, 3, 4, 6, 8, 9)]
+
+
+@pytest.mark.parametrize("L,periodic", WIDE_GEOMETRIES)
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_wide_lattice_sweep_matches_oracle(L, periodic, dtype):
+    K = kpm()
+    M, R = 32, 64
+    say("wide lattice", L, periodic, dtype, "R", R)
+    pot, Ho, a, b = oracle_problem(L, 1.5, 17, periodic=periodic)
+    v0 = inputs.phase_block(Ho.n, R, 18)
+    ref_eta = O.kpm_eta(Ho, a, b, v0, M)
+    ref = O.mu_from_eta(ref_eta)
+    try:
+        K.set_sweep_tuning(lattice=2)
+        H = K.build_hamiltonian(L, pot, periodic=periodic, dtype=dtype)
+        assert K.sweep_kernel(H, R) == "lattice_kernel"
+        H.close()
+        mu, eta = gpu_moments(L, pot, v0, M, dtype=dtype, periodic=periodic, eta=True)
+    finally:
+        K.reset_sweep_tuning()
+    tol = TOL_C128 if dtype == "c128" else TOL_C64
+    assert np.abs(mu - ref).max() <= tol
+    if dtype == "c128":
+        got_eta = eta[..., 0] + 1j * eta[..., 1]
+        assert np.abs(got_eta - ref_eta).max() <= TOL_C128
+
+
 @pytest.mark.parametrize("L", [(5, 4, 4), (4, 9, 3), (1, 1, 7)])
 def test_lattice_sweep_falls_back_for_one_site_tail_tiles(L):
     # a side with L mod 4 == 1 would leave tiles one site wide: the generic
@@ -267,9 +297,10 @@ def test_lattice_sweep_falls_back_for_one_site_tail_tiles(L):
     assert np.abs(mu - O.kpm_moments(Ho, a, b, v0, M)).max() <= TOL_C128
 
 
-def test_lattice_single_sweep_variants():
+@pytest.mark.parametrize("R", [32, 64])
+def test_lattice_single_sweep_variants(R):
     K = kpm()
-    L, R = (6, 6, 7), 32
+    L = (6, 6, 7)
     pot, Ho, a, b = oracle_problem(L, 1.0, 13, periodic=(1, 0, 1))
     Hd = Ho.dense()
     H = K.build_hamiltonian(L, pot, periodic=(1, 0, 1))
