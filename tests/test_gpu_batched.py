@@ -40,10 +40,13 @@ def device():
     kpm().reset_batch_tuning()
 
 
-# Uneven sizes: 108 .. 1008 rows, one open lattice, none a multiple of
-# every pass height.
+# Uneven sizes: 16 .. 1008 rows, open sides on every axis (sides of 1 and 2
+# are open: periodic sides must be at least 3), none a multiple of every
+# pass height.  The
+# solver derives every gather address from the lattice geometry.
 SHAPES = [((3, 3, 3), (1, 1, 1)), ((4, 4, 4), (1, 1, 1)), ((5, 4, 3), (1, 1, 1)),
-          ((6, 6, 7), (1, 1, 1)), ((3, 5, 4), (1, 0, 1)), ((4, 3, 6), (1, 1, 1))]
+          ((6, 6, 7), (1, 1, 1)), ((3, 5, 4), (1, 0, 1)), ((4, 3, 6), (1, 1, 1)),
+          ((2, 3, 5), (0, 1, 0)), ((1, 4, 3), (0, 1, 1)), ((4, 2, 1), (1, 0, 0))]
 
 
 def make_batch(shapes, R, dtype, seed0=10):
