@@ -236,6 +236,66 @@ def leg_variants(sweeps: int = 10):
     return out
 
 
+def leg_ladder(steps: int = 200, repeats: int = 3):
+    """The paper's optimisation ladder on the 64^3 complex128 lattice, per start vector and KPM
+    step (one moment pair): the naive algorithm (one SpMV and five BLAS-1 calls per step, one
+    vector at a time), the fused sweep at R = 1 (the vector-at-a-time "throughput mode"), and
+    the blocked fused sweep at R = 32.  Bytes per step and vector from the traffic model of
+    Table "kpm_analysis" (naive) and of the fused algorithms (index bytes only where the
+    kernel reads them)."""
+    import time
+    import torch
+    from paper_1410_5242_amd import autotune, inputs, kpm
+    L = (64, 64, 64)
+    H = kpm.build_hamiltonian(L, inputs.potential(L, 1.0, 0))
+    N, Sd, nnz = H.N, 16, 13 * H.N
+    M = 2 * steps
+    cache = autotune.TuningCache()
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        best = None
+        for _ in range(repeats):
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            best = dt if best is None else min(best, dt)
+        return best
+
+    out = {"workload": f"TI {L[0]}x{L[1]}x{L[2]} periodic, complex128, {steps} KPM steps per run, best of "
+                       f"{repeats} runs; times per start vector and step", "stages": []}
+    V1 = kpm.random_phase_block(N, 1, 1, "c128")
+    kpm.reset_sweep_tuning()
+    autotune.apply_sweep(cache, H, 1, L)
+    t_naive = timed(lambda: kpm.moments_naive(H, V1, M, check=False)) / steps
+    t_fused1 = timed(lambda: kpm.moments(H, V1, M, check=False)) / steps
+    kern1 = kpm.sweep_kernel(H, 1)
+    kpm.reset_sweep_tuning()
+    R = 32
+    autotune.apply_sweep(cache, H, R, L)
+    VR = kpm.random_phase_block(N, R, 1, "c128")
+    t_block = timed(lambda: kpm.moments(H, VR, M, check=False)) / steps / R
+    kernR = kpm.sweep_kernel(H, R)
+    kpm.reset_sweep_tuning()
+    Si1 = 0 if kern1 == "lattice_kernel" else 4
+    SiR = 0 if kernR == "lattice_kernel" else 4
+    stages = [
+        ("naive (SpMV + axpy, scal, axpy, nrm2, dot)", "R=1", t_naive, nnz * (Sd + 4) + 13 * N * Sd),
+        ("fused sweep, one vector at a time", f"R=1, {kern1}", t_fused1, nnz * (Sd + Si1) + 3 * N * Sd),
+        ("blocked fused sweep", f"R={R}, {kernR}", t_block, (nnz * (Sd + SiR) + 3 * R * N * Sd) / R),
+    ]
+    for name, shape, t, byts in stages:
+        out["stages"].append({"stage": name, "shape": shape, "us_per_vector_step": round(t * 1e6, 2),
+                              "model_bytes_per_vector_step": int(byts), "GBps": round(byts / t / 1e9, 1),
+                              "speedup_vs_naive": round(t_naive / t, 2)})
+    out["throughput_mode_penalty"] = round(t_fused1 / t_block, 2)
+    del V1, VR
+    H.close()
+    return out
+
+
 def leg_time_to_dos():
     from paper_1410_5242_amd import learned, time_to_dos
     if not os.path.exists(learned.WEIGHTS):
@@ -286,7 +346,7 @@ def main():
                     help="short run for hardware counters: a 1 GiB device copy (the calibration kernel "
                          "of known traffic) and --probe-sweeps fused sweeps of the workload")
     ap.add_argument("--probe-sweeps", type=int, default=8)
-    ap.add_argument("--legs", default="variants,precision,batched,time_to_dos",
+    ap.add_argument("--legs", default="variants,ladder,precision,batched,time_to_dos",
                     help="extra measurements after the headline step: any of variants, precision, batched, "
                          "time_to_dos (comma separated), or none")
     args = ap.parse_args()
@@ -415,8 +475,8 @@ def main():
     H.close()
     del V0
     legs = [x for x in args.legs.split(",") if x and x != "none"]
-    for name, fn in (("variants", leg_variants), ("precision", leg_precision), ("batched", leg_batched),
-                     ("time_to_dos", leg_time_to_dos)):
+    for name, fn in (("variants", leg_variants), ("ladder", leg_ladder), ("precision", leg_precision),
+                     ("batched", leg_batched), ("time_to_dos", leg_time_to_dos)):
         if name in legs:
             log(f"[bench] leg {name}")
             out[name] = fn()

@@ -130,6 +130,34 @@ kpm_status kpm_aug_spmmv(const kpm_hamiltonian* H, const void* V, void* W, int32
 kpm_status kpm_moments(const kpm_hamiltonian* H, const void* V0, int32_t R, int32_t M,
                        double* mu, double* eta_out, int32_t check, void* stream);
 
+/* The naive KPM-DOS algorithm (Alg. "kpm_naive"), for measuring what the
+ * fused and blocked sweeps save (Table "kpm_analysis": 13 N S_d vector bytes
+ * per step and vector against 3 R N S_d per blocked sweep).  The trace is an
+ * outer loop over the R start vectors; per vector the initialisation
+ * w = nu_1 = (H v - b v) / a, eta_0 = <v|v>, eta_1 = <w|v>, then for
+ * m = 1 .. M/2 - 1, with v and w swapping roles, one kernel per call:
+ *   u <- H v (SpMV: the plain sweep at R = 1),  u <- u - b v (axpy),
+ *   w <- -w (scal),  w <- w + (2/a) u (axpy),
+ *   eta_2m = <v|v> (nrm2),  eta_2m+1 = <w|v> (dot),
+ * and at the end the eta -> mu identity of kpm_moments.  Arguments, layout,
+ * check and errors as kpm_moments (mu: device [R][M] double); three [N]
+ * vectors and the scalar-product partials are cached on H.  The moments
+ * equal kpm_moments' to rounding. */
+kpm_status kpm_moments_naive(const kpm_hamiltonian* H, const void* V0, int32_t R, int32_t M,
+                             double* mu, int32_t check, void* stream);
+
+/* The BLAS level-1 kernels of the naive algorithm on device vectors of n
+ * complex elements of storage type dtype (KPM_C128 or KPM_C64), 16-byte
+ * aligned, enqueued on `stream`:
+ *   kpm_axpy: y <- y + alpha x;   kpm_scal: x <- alpha x;
+ *   kpm_dot:  out[0] + i out[1] = sum_i conj(x_i) y_i, accumulated in FP64
+ *             (out: device, 2 doubles; x == y gives the squared norm with
+ *             out[1] = 0).  The sum is reduced in a fixed order.
+ * Errors: KPM_EINVAL (dtype, n < 0, NULL or misaligned vector). */
+kpm_status kpm_axpy(int32_t dtype, int64_t n, double alpha, const void* x, void* y, void* stream);
+kpm_status kpm_scal(int32_t dtype, int64_t n, double alpha, void* x, void* stream);
+kpm_status kpm_dot(int32_t dtype, int64_t n, const void* x, const void* y, double* out, void* stream);
+
 /* Density of states per unit energy from moments (the reconstruction step
  * the paper leaves to the KPM literature):
  *   mubar_n = (1/R) sum_r mu[r][n]                 (stochastic trace)

@@ -30,6 +30,9 @@ struct Workspace {
     size_t etabytes = 0;
     int* flag = nullptr;                   // spectrum check flag (device)
     int* flag_host = nullptr;              // pinned mirror
+    void* naive[3] = {nullptr, nullptr, nullptr};   // v, w, u of the naive algorithm ([N] each)
+    size_t naive_bytes = 0;
+    double* dot_part = nullptr;            // [naive_dot_partials()][2] scalar-product partials
 };
 
 }  // namespace kpm
@@ -223,6 +226,14 @@ hipError_t launch_dos(const double* mu, int R, int M, int kernel, double kparam,
 hipError_t launch_dos_batched(const double* mu, int n_inst, int R, int ld, int M, int kernel, double kparam,
                               const double* a, const double* b, const double* E, int K, int masses,
                               double* rho, hipStream_t s);
+// BLAS level-1 kernels of the naive algorithm (n complex elements of the
+// given storage type; scalar products in FP64, out = sum conj(x_i) y_i
+// through part[naive_dot_partials()][2]); column r of an [n][R] block.
+int naive_dot_partials();
+hipError_t launch_axpy(int dtype, int64_t n, double alpha, const void* x, void* y, hipStream_t s);
+hipError_t launch_scal(int dtype, int64_t n, double alpha, void* x, hipStream_t s);
+hipError_t launch_dot(int dtype, int64_t n, const void* x, const void* y, double* part, double* out, hipStream_t s);
+hipError_t launch_column(int dtype, int64_t n, int R, int r, const void* V, void* v, hipStream_t s);
 hipError_t launch_phase_block(void* V, int64_t N, int R, int dtype, uint64_t seed, hipStream_t s);
 hipError_t launch_features(const double* mu, int n_inst, int R, int ld, int n_mom, const float* extra,
                            float* x, hipStream_t s);

@@ -87,6 +87,12 @@ bool use_lattice(const kpm_hamiltonian* H, int R) {
     return t == 2 || lattice_tiles(H) >= 128;
 }
 
+// The per-die tile counters are read only by the scalar-operand sweep with
+// dynamic tile mapping; the other sweeps need no cleared queue.
+bool sweep_uses_queue(const kpm_hamiltonian* H, int R) {
+    return !use_lattice(H, R) && !use_gather(H->dtype, R, H->nrows) && get_tuning().dynamic != 0;
+}
+
 int launch_grid(const kpm_hamiltonian* H, int R) {
     return use_lattice(H, R) ? lattice_grid(H) : sweep_grid(H->dtype, R, H->nrows);
 }
@@ -380,6 +386,9 @@ void kpm_destroy_hamiltonian(kpm_hamiltonian* H) {
     if (H->ws.eta) (void)hipFree(H->ws.eta);
     if (H->ws.flag) (void)hipFree(H->ws.flag);
     if (H->ws.flag_host) (void)hipHostFree(H->ws.flag_host);
+    for (int i = 0; i < 3; ++i)
+        if (H->ws.naive[i]) (void)hipFree(H->ws.naive[i]);
+    if (H->ws.dot_part) (void)hipFree(H->ws.dot_part);
     delete H;
 }
 
@@ -407,7 +416,7 @@ kpm_status kpm_aug_spmmv(const kpm_hamiltonian* Hc, const void* V, void* W, int3
         if (st != KPM_OK) return st;
     }
     if ((st = ensure_queue(H)) != KPM_OK) return st;
-    KPM_HIP(launch_zero_ints(H->ws.queue, kXcds, s), "zero kernel");
+    if (sweep_uses_queue(H, R)) KPM_HIP(launch_zero_ints(H->ws.queue, kXcds, s), "zero kernel");
     SweepArgs a{H->val, H->col, H->nrows, V, W, H->sched, alpha, beta, gamma,
                 dots ? H->ws.partials : nullptr, launch_grid(H, R)};
     a.queue = H->ws.queue;
@@ -478,6 +487,127 @@ kpm_status kpm_moments(const kpm_hamiltonian* Hc, const void* V0, int32_t R, int
         if (*H->ws.flag_host)
             return fail(KPM_ESPECTRUM, "moments left [-mu_0, mu_0]: the scaled spectrum is not inside [-1, 1]");
     }
+    return KPM_OK;
+}
+
+kpm_status kpm_moments_naive(const kpm_hamiltonian* Hc, const void* V0, int32_t R, int32_t M, double* mu,
+                             int32_t check, void* stream) {
+    g_error.clear();
+    if (!Hc || !V0 || !mu) return fail(KPM_EINVAL, "H, V0 or mu is NULL");
+    if (!r_supported(R)) return fail(KPM_ENOTSUP, "R must be one of 1, 2, 4, 8, 16, 32, 64");
+    if (M < 2 || (M % 2) != 0) return fail(KPM_EINVAL, "M must be even and >= 2");
+    auto* H = const_cast<kpm_hamiltonian*>(Hc);
+    kpm_status st = check_device(H);
+    if (st != KPM_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t N = H->nrows;
+    const size_t vb = static_cast<size_t>(N) * 2 * real_size(H->dtype);
+    for (int i = 0; i < 3; ++i) {
+        size_t have = H->ws.naive_bytes;
+        if ((st = grow(&H->ws.naive[i], &have, vb, "hipMalloc(naive vector)")) != KPM_OK) return st;
+    }
+    H->ws.naive_bytes = vb;
+    if (!H->ws.dot_part)
+        KPM_HIP(hipMalloc(&H->ws.dot_part, static_cast<size_t>(naive_dot_partials()) * 2 * sizeof(double)),
+                "hipMalloc(dot partials)");
+    if ((st = grow(&H->ws.eta, &H->ws.etabytes, static_cast<size_t>(M) * R * 2 * sizeof(double), "hipMalloc(eta)")) !=
+        KPM_OK)
+        return st;
+    double* eta = H->ws.eta;   // [M][R][2]
+    const int dt = H->dtype;
+    const double inv_a = 1.0 / H->a, b = H->b;
+    // one SpMV: u <- H v (the plain sweep at R = 1, which applies H unscaled)
+    auto spmv = [&](const void* v, void* u) -> hipError_t {
+        SweepArgs a{H->val, H->col, N, v, u, H->sched, 1.0, 0.0, 0.0, nullptr, launch_grid(H, 1)};
+        a.queue = H->ws.queue;
+        for (int j = 0; j < 3; ++j) a.L[j] = H->L[j];
+        if (sweep_uses_queue(H, 1)) {
+            const hipError_t e = launch_zero_ints(H->ws.queue, kXcds, s);
+            if (e != hipSuccess) return e;
+        }
+        return launch_any_sweep(H, 1, KPM_PLAIN, a, s);
+    };
+    auto eta_at = [&](int n, int r) { return eta + (static_cast<int64_t>(n) * R + r) * 2; };
+    if ((st = ensure_queue(H)) != KPM_OK) return st;
+    if ((st = ensure_schedule(H)) != KPM_OK) return st;
+    // the stochastic trace as an outer loop over the R start vectors
+    for (int r = 0; r < R; ++r) {
+        void* v = H->ws.naive[0];
+        void* w = H->ws.naive[1];
+        void* u = H->ws.naive[2];
+        KPM_HIP(launch_column(dt, N, R, r, V0, v, s), "column kernel");
+        // initialisation: w = nu_1 = (H v - b v) / a; eta_0 = <v|v>, eta_1 = <w|v>
+        KPM_HIP(spmv(v, w), "spmv");
+        KPM_HIP(launch_axpy(dt, N, -b, v, w, s), "axpy kernel");
+        KPM_HIP(launch_scal(dt, N, inv_a, w, s), "scal kernel");
+        KPM_HIP(launch_dot(dt, N, v, v, H->ws.dot_part, eta_at(0, r), s), "nrm2 kernel");
+        KPM_HIP(launch_dot(dt, N, w, v, H->ws.dot_part, eta_at(1, r), s), "dot kernel");
+        for (int m = 1; m < M / 2; ++m) {
+            std::swap(v, w);   // v = nu_m, w = nu_{m-1}
+            KPM_HIP(spmv(v, u), "spmv");
+            KPM_HIP(launch_axpy(dt, N, -b, v, u, s), "axpy kernel");
+            KPM_HIP(launch_scal(dt, N, -1.0, w, s), "scal kernel");
+            KPM_HIP(launch_axpy(dt, N, 2.0 * inv_a, u, w, s), "axpy kernel");
+            KPM_HIP(launch_dot(dt, N, v, v, H->ws.dot_part, eta_at(2 * m, r), s), "nrm2 kernel");
+            KPM_HIP(launch_dot(dt, N, w, v, H->ws.dot_part, eta_at(2 * m + 1, r), s), "dot kernel");
+        }
+    }
+    KPM_HIP(launch_eta_to_mu(eta, R, M, mu, s), "eta_to_mu kernel");
+    if (check) {
+        if ((st = ensure_flag(H)) != KPM_OK) return st;
+        KPM_HIP(launch_check_moments(mu, R, M, H->ws.flag, s), "check kernel");
+        KPM_HIP(hipMemcpyAsync(H->ws.flag_host, H->ws.flag, sizeof(int), hipMemcpyDeviceToHost, s), "copy flag");
+        KPM_HIP(hipStreamSynchronize(s), "synchronise");
+        if (*H->ws.flag_host)
+            return fail(KPM_ESPECTRUM, "moments left [-mu_0, mu_0]: the scaled spectrum is not inside [-1, 1]");
+    }
+    return KPM_OK;
+}
+
+namespace {
+// scalar-product partials of kpm_dot, one buffer per device
+std::vector<double*> g_dot_part;
+
+kpm_status blas1_args(int32_t dtype, int64_t n, std::initializer_list<const void*> ptrs) {
+    if (dtype != KPM_C128 && dtype != KPM_C64) return fail(KPM_EINVAL, "unknown dtype");
+    if (n < 0) return fail(KPM_EINVAL, "n must be >= 0");
+    for (const void* p : ptrs) {
+        if (!p && n > 0) return fail(KPM_EINVAL, "NULL vector");
+        if (reinterpret_cast<uintptr_t>(p) % 16 != 0) return fail(KPM_EINVAL, "vectors must be 16-byte aligned");
+    }
+    return KPM_OK;
+}
+}  // namespace
+
+kpm_status kpm_axpy(int32_t dtype, int64_t n, double alpha, const void* x, void* y, void* stream) {
+    g_error.clear();
+    kpm_status st = blas1_args(dtype, n, {x, y});
+    if (st != KPM_OK || n == 0) return st;
+    KPM_HIP(launch_axpy(dtype, n, alpha, x, y, static_cast<hipStream_t>(stream)), "axpy kernel");
+    return KPM_OK;
+}
+
+kpm_status kpm_scal(int32_t dtype, int64_t n, double alpha, void* x, void* stream) {
+    g_error.clear();
+    kpm_status st = blas1_args(dtype, n, {x});
+    if (st != KPM_OK || n == 0) return st;
+    KPM_HIP(launch_scal(dtype, n, alpha, x, static_cast<hipStream_t>(stream)), "scal kernel");
+    return KPM_OK;
+}
+
+kpm_status kpm_dot(int32_t dtype, int64_t n, const void* x, const void* y, double* out, void* stream) {
+    g_error.clear();
+    kpm_status st = blas1_args(dtype, n, {x, y});
+    if (st != KPM_OK) return st;
+    if (!out) return fail(KPM_EINVAL, "out is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int dev = 0;
+    KPM_HIP(hipGetDevice(&dev), "hipGetDevice");
+    if (static_cast<int>(g_dot_part.size()) <= dev) g_dot_part.resize(dev + 1, nullptr);
+    if (!g_dot_part[dev])
+        KPM_HIP(hipMalloc(&g_dot_part[dev], static_cast<size_t>(naive_dot_partials()) * 2 * sizeof(double)),
+                "hipMalloc(dot partials)");
+    KPM_HIP(launch_dot(dtype, n, x, y, g_dot_part[dev], out, s), "dot kernel");
     return KPM_OK;
 }
 

@@ -71,6 +71,7 @@ EXPORTS = ("kpm_build_hamiltonian", "kpm_hamiltonian_info", "kpm_export_csr",
            "kpm_mlp_param_count", "kpm_mlp_set_params", "kpm_mlp_get_params", "kpm_mlp_get_grads",
            "kpm_mlp_forward", "kpm_mlp_backward", "kpm_mlp_adam_step", "kpm_mlp_train_step",
            "kpm_mlp_gemm_bf16", "kpm_dos_batched", "kpm_moment_features", "kpm_random_phase_block",
+           "kpm_moments_naive", "kpm_axpy", "kpm_scal", "kpm_dot",
            "kpm_last_error", "kpm_version")
 
 
@@ -97,6 +98,14 @@ def lib():
     L.kpm_aug_spmmv.argtypes = [vp, vp, vp, i32, dbl, dbl, dbl, i32, vp, vp]
     L.kpm_moments.restype = ctypes.c_int
     L.kpm_moments.argtypes = [vp, vp, i32, i32, vp, vp, i32, vp]
+    L.kpm_moments_naive.restype = ctypes.c_int
+    L.kpm_moments_naive.argtypes = [vp, vp, i32, i32, vp, i32, vp]
+    L.kpm_axpy.restype = ctypes.c_int
+    L.kpm_axpy.argtypes = [i32, i64, dbl, vp, vp, vp]
+    L.kpm_scal.restype = ctypes.c_int
+    L.kpm_scal.argtypes = [i32, i64, dbl, vp, vp]
+    L.kpm_dot.restype = ctypes.c_int
+    L.kpm_dot.argtypes = [i32, i64, vp, vp, vp, vp]
     L.kpm_dos.restype = ctypes.c_int
     L.kpm_dos.argtypes = [vp, i32, i32, i32, dbl, dbl, dbl, vp, i32, vp, vp]
     L.kpm_set_sweep_tuning.restype = ctypes.c_int
@@ -250,6 +259,55 @@ def moments(H: Hamiltonian, V0: torch.Tensor, M: int, mu: torch.Tensor | None = 
     _check(lib().kpm_moments(H.handle, _dptr(V0), R, int(M), _dptr(mu),
                              _dptr(eta) if eta is not None else None, 1 if check else 0, _stream(stream)))
     return mu
+
+
+def moments_naive(H: Hamiltonian, V0: torch.Tensor, M: int, mu: torch.Tensor | None = None,
+                  check: bool = True, stream=None) -> torch.Tensor:
+    """kpm_moments_naive: mu[R][M] by the naive algorithm (one SpMV and five BLAS-1 calls per step)."""
+    if V0.dim() != 2 or V0.shape[0] != H.N:
+        raise ValueError("V0 must be [N][R]")
+    if V0.dtype != H.torch_dtype:
+        raise ValueError(f"V0 must be {H.torch_dtype}")
+    R = V0.shape[1]
+    if mu is None:
+        mu = torch.empty((R, M), dtype=torch.float64, device=V0.device)
+    _check(lib().kpm_moments_naive(H.handle, _dptr(V0), R, int(M), _dptr(mu), 1 if check else 0, _stream(stream)))
+    return mu
+
+
+_BLAS1_DTYPES = {torch.complex128: 0, torch.complex64: 1}
+
+
+def _blas1_vec(x: torch.Tensor) -> int:
+    if x.dtype not in _BLAS1_DTYPES or not x.is_contiguous() or not x.is_cuda:
+        raise ValueError("BLAS-1 vectors must be contiguous complex128 or complex64 device tensors")
+    return _BLAS1_DTYPES[x.dtype]
+
+
+def axpy(alpha: float, x: torch.Tensor, y: torch.Tensor, stream=None) -> torch.Tensor:
+    """kpm_axpy: y <- y + alpha x (in place)."""
+    dt = _blas1_vec(x)
+    if _blas1_vec(y) != dt or x.numel() != y.numel():
+        raise ValueError("x and y must have the same dtype and length")
+    _check(lib().kpm_axpy(dt, x.numel(), float(alpha), _dptr(x), _dptr(y), _stream(stream)))
+    return y
+
+
+def scal(alpha: float, x: torch.Tensor, stream=None) -> torch.Tensor:
+    """kpm_scal: x <- alpha x (in place)."""
+    _check(lib().kpm_scal(_blas1_vec(x), x.numel(), float(alpha), _dptr(x), _stream(stream)))
+    return x
+
+
+def dot(x: torch.Tensor, y: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """kpm_dot: sum_i conj(x_i) y_i in FP64 as a device tensor [re, im]."""
+    dt = _blas1_vec(x)
+    if _blas1_vec(y) != dt or x.numel() != y.numel():
+        raise ValueError("x and y must have the same dtype and length")
+    if out is None:
+        out = torch.empty(2, dtype=torch.float64, device=x.device)
+    _check(lib().kpm_dot(dt, x.numel(), _dptr(x), _dptr(y), _dptr(out), _stream(stream)))
+    return out
 
 
 def moments_batched(Hs, V0s, M: int, mu: torch.Tensor | None = None, check: bool = True,

@@ -63,6 +63,13 @@ def test_argument_validation_without_device(L):
     assert L.kpm_dos(fake, 1, 8, 7, 0.0, 1.0, 0.0, fake, 4, fake, None) == kpm.KPM_EINVAL   # kernel
     assert L.kpm_dos(fake, 1, 8, 2, 0.0, 1.0, 0.0, fake, 4, fake, None) == kpm.KPM_EINVAL   # Lorentz lambda
     assert L.kpm_hamiltonian_info(None, None, None, None, None, None, None, None, None) == kpm.KPM_EINVAL
+    assert L.kpm_moments_naive(None, fake, 1, 8, fake, 0, None) == kpm.KPM_EINVAL
+    assert L.kpm_axpy(7, 4, 1.0, fake, fake, None) == kpm.KPM_EINVAL                  # dtype
+    assert L.kpm_axpy(0, -1, 1.0, fake, fake, None) == kpm.KPM_EINVAL                 # n < 0
+    assert L.kpm_axpy(0, 4, 1.0, ctypes.c_void_p(0x1008), fake, None) == kpm.KPM_EINVAL  # misaligned
+    assert L.kpm_scal(1, 4, 1.0, None, None) == kpm.KPM_EINVAL                        # NULL vector
+    assert L.kpm_dot(0, 4, fake, fake, None, None) == kpm.KPM_EINVAL                  # NULL out
+    assert L.kpm_axpy(0, 0, 1.0, None, None, None) == kpm.KPM_OK                      # empty: no-op
     assert L.kpm_sweep_profile_enable(-1) == kpm.KPM_EINVAL   # sampling period < 0
     assert L.kpm_sweep_profile_enable(0) == kpm.KPM_OK
     L.kpm_destroy_hamiltonian(None)   # no-op
