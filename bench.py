@@ -296,6 +296,41 @@ def leg_ladder(steps: int = 200, repeats: int = 3):
     return out
 
 
+def leg_spectral(M: int = 1000, K: int = 1024):
+    """Local DOS of 16 sites and A(k, E) at 16 momenta on the 64^3 complex128 lattice (gamma = 1):
+    the fused blocked sweep on deterministic start vectors (4 orbitals x 16 = R = 64 per run),
+    then the batched Jackson reconstruction."""
+    import math
+    import time
+    import torch
+    from paper_1410_5242_amd import autotune, inputs, kpm, spectral
+    L = (64, 64, 64)
+    H = kpm.build_hamiltonian(L, inputs.potential(L, 1.0, 0))
+    kpm.reset_sweep_tuning()
+    tuned = autotune.apply_sweep(autotune.TuningCache(), H, 64, L)
+    E = torch.linspace(H.b - 0.999 * H.a, H.b + 0.999 * H.a, K, dtype=torch.float64, device="cuda")
+    sites = [x + 64 * (y + 64 * 32) for x, y in ((4 * i, 3 * i) for i in range(16))]
+    ks = [(math.pi * i / 15, 0.0, 0.0) for i in range(16)]   # Gamma -> X
+    out = {"workload": f"TI 64x64x64 periodic, gamma=1, complex128, M={M}, {K} energies; 16 sites / 16 momenta, "
+                       "4 orbitals each (R = 64 per run)", "kernel": kpm.sweep_kernel(H, 64), "autotuned": tuned}
+    Sd, N = 16, H.N
+    bps = 13 * N * Sd + 3 * 64 * N * Sd
+    for name, fn in (("local_dos", lambda: spectral.local_dos(H, L, sites, M, E)),
+                     ("spectral_function", lambda: spectral.spectral_function(H, L, ks, M, E))):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, rho = fn()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        integ = float((rho.sum(dim=1) * (E[1] - E[0])).mean().item())
+        out[name] = {"seconds": round(dt, 4), "GBps": round(bps * (M // 2) / dt / 1e9, 1),
+                     "mean_integral": round(integ, 4)}
+    kpm.reset_sweep_tuning()
+    H.close()
+    return out
+
+
 def leg_time_to_dos():
     from paper_1410_5242_amd import learned, time_to_dos
     if not os.path.exists(learned.WEIGHTS):
@@ -346,7 +381,7 @@ def main():
                     help="short run for hardware counters: a 1 GiB device copy (the calibration kernel "
                          "of known traffic) and --probe-sweeps fused sweeps of the workload")
     ap.add_argument("--probe-sweeps", type=int, default=8)
-    ap.add_argument("--legs", default="variants,ladder,precision,batched,time_to_dos",
+    ap.add_argument("--legs", default="variants,ladder,precision,batched,spectral,time_to_dos",
                     help="extra measurements after the headline step: any of variants, precision, batched, "
                          "time_to_dos (comma separated), or none")
     args = ap.parse_args()
@@ -476,7 +511,7 @@ def main():
     del V0
     legs = [x for x in args.legs.split(",") if x and x != "none"]
     for name, fn in (("variants", leg_variants), ("ladder", leg_ladder), ("precision", leg_precision),
-                     ("batched", leg_batched), ("time_to_dos", leg_time_to_dos)):
+                     ("batched", leg_batched), ("spectral", leg_spectral), ("time_to_dos", leg_time_to_dos)):
         if name in legs:
             log(f"[bench] leg {name}")
             out[name] = fn()

@@ -183,6 +183,23 @@ kpm_status kpm_dos(const double* mu, int32_t R, int32_t M, int32_t kernel, doubl
  * column has unit norm up to rounding.  Errors: KPM_EINVAL. */
 kpm_status kpm_random_phase_block(void* V, int64_t N, int32_t R, int32_t dtype, uint64_t seed, void* stream);
 
+/* Deterministic start blocks for local and momentum-resolved spectra (the
+ * local DOS and the spectral function A(k, E) of Fig. "topi_demo"; the paper
+ * shows them without formulas, these follow the standard KPM reading: the
+ * moments of one start vector |phi> are <phi|T_n(Htilde)|phi>, with no
+ * trace average).  V: device [N][R] in dtype, 0 < R <= 64, written in full.
+ * kpm_site_block: column r is the unit vector of row rows[r] (host [R],
+ *   0 <= rows[r] < N); row 4 n + o is orbital o of site n.
+ * kpm_plane_wave_block: column r is the plane wave of momentum k[r] (host
+ *   [R][3], radians per lattice spacing) on orbital orbital[r] (host [R],
+ *   0..3) of the Lx x Ly x Lz lattice L (host [3], N = 4 Lx Ly Lz):
+ *   V[4 n + o][r] = delta(o, orbital[r]) exp(i k[r] . (x, y, z)_n) / sqrt(Lx Ly Lz),
+ *   site n = x + Lx (y + Ly z); the phase is computed in FP64.
+ * Errors: KPM_EINVAL (NULL, dtype, R, a row, orbital or momentum out of range). */
+kpm_status kpm_site_block(void* V, int64_t N, int32_t R, const int64_t* rows, int32_t dtype, void* stream);
+kpm_status kpm_plane_wave_block(void* V, const int32_t* L, int32_t R, const double* k, const int32_t* orbital,
+                                int32_t dtype, void* stream);
+
 /* kpm_dos for n_inst instances in one launch, from a prefix of their
  * moments: instance i uses mu[i][r][n] = mu[(i R + r) ld + n] for n < M
  * (ld >= M; a prefix of an M'-moment run equals an M-moment run with the

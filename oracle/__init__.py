@@ -276,6 +276,28 @@ def dense_moments(Hd: np.ndarray, a: float, b: float, v0: np.ndarray, M: int) ->
     return (Tn @ w).T
 
 
+def site_block(N: int, rows) -> np.ndarray:
+    """Start block for local quantities: column r is the unit vector of row rows[r]."""
+    rows = [int(r) for r in rows]
+    v = np.zeros((N, len(rows)), dtype=np.complex128)
+    for r, i in enumerate(rows):
+        v[i, r] = 1.0
+    return v
+
+
+def plane_wave_block(L, momenta, orbitals) -> np.ndarray:
+    """Start block for momentum-resolved quantities: column r is the plane wave
+    sum_n exp(i k_r . (x, y, z)_n) |n, orbital_r> / sqrt(sites), site n = x + Lx (y + Ly z)."""
+    Lx, Ly, Lz = (int(v) for v in L)
+    n = np.arange(Lx * Ly * Lz)
+    x, y, z = n % Lx, (n // Lx) % Ly, n // (Lx * Ly)
+    v = np.zeros((4 * n.size, len(orbitals)), dtype=np.complex128)
+    for r, (k, o) in enumerate(zip(momenta, orbitals)):
+        ph = k[0] * x + k[1] * y + k[2] * z
+        v[4 * n + int(o), r] = np.exp(1j * ph) / math.sqrt(n.size)
+    return v
+
+
 def clean_ti_spectrum(L: int, t: float = 1.0) -> np.ndarray:
     """Eigenvalues of the clean (V = 0) periodic L^3 lattice from the Bloch form.
 

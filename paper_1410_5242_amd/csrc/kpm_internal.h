@@ -234,6 +234,12 @@ hipError_t launch_axpy(int dtype, int64_t n, double alpha, const void* x, void* 
 hipError_t launch_scal(int dtype, int64_t n, double alpha, void* x, hipStream_t s);
 hipError_t launch_dot(int dtype, int64_t n, const void* x, const void* y, double* part, double* out, hipStream_t s);
 hipError_t launch_column(int dtype, int64_t n, int R, int r, const void* V, void* v, hipStream_t s);
+// Deterministic start blocks (at most kMaxStartColumns columns): unit
+// vectors of given rows; plane waves of given momenta on given orbitals.
+constexpr int kMaxStartColumns = 64;
+hipError_t launch_site_block(void* V, int64_t N, int R, const int64_t* rows, int dtype, hipStream_t s);
+hipError_t launch_plane_wave_block(void* V, const int L[3], int R, const double* k, const int32_t* orb, int dtype,
+                                   hipStream_t s);
 hipError_t launch_phase_block(void* V, int64_t N, int R, int dtype, uint64_t seed, hipStream_t s);
 hipError_t launch_features(const double* mu, int n_inst, int R, int ld, int n_mom, const float* extra,
                            float* x, hipStream_t s);

@@ -611,6 +611,36 @@ kpm_status kpm_dot(int32_t dtype, int64_t n, const void* x, const void* y, doubl
     return KPM_OK;
 }
 
+kpm_status kpm_site_block(void* V, int64_t N, int32_t R, const int64_t* rows, int32_t dtype, void* stream) {
+    g_error.clear();
+    if (!V || !rows) return fail(KPM_EINVAL, "V or rows is NULL");
+    if (dtype != KPM_C128 && dtype != KPM_C64) return fail(KPM_EINVAL, "unknown dtype");
+    if (N <= 0 || R <= 0 || R > kMaxStartColumns) return fail(KPM_EINVAL, "need N > 0 and 0 < R <= 64");
+    for (int r = 0; r < R; ++r)
+        if (rows[r] < 0 || rows[r] >= N) return fail(KPM_EINVAL, "row outside [0, N)");
+    KPM_HIP(launch_site_block(V, N, R, rows, dtype, static_cast<hipStream_t>(stream)), "site block kernel");
+    return KPM_OK;
+}
+
+kpm_status kpm_plane_wave_block(void* V, const int32_t* L, int32_t R, const double* k, const int32_t* orbital,
+                                int32_t dtype, void* stream) {
+    g_error.clear();
+    if (!V || !L || !k || !orbital) return fail(KPM_EINVAL, "V, L, k or orbital is NULL");
+    if (dtype != KPM_C128 && dtype != KPM_C64) return fail(KPM_EINVAL, "unknown dtype");
+    if (R <= 0 || R > kMaxStartColumns) return fail(KPM_EINVAL, "need 0 < R <= 64");
+    if (L[0] <= 0 || L[1] <= 0 || L[2] <= 0) return fail(KPM_EINVAL, "lattice side <= 0");
+    if (static_cast<int64_t>(L[0]) * L[1] * L[2] > (INT32_MAX / 4)) return fail(KPM_EINVAL, "lattice too large");
+    for (int r = 0; r < R; ++r) {
+        if (orbital[r] < 0 || orbital[r] > 3) return fail(KPM_EINVAL, "orbital outside [0, 4)");
+        for (int j = 0; j < 3; ++j)
+            if (!std::isfinite(k[3 * r + j])) return fail(KPM_EINVAL, "momentum not finite");
+    }
+    const int Li[3] = {L[0], L[1], L[2]};
+    KPM_HIP(launch_plane_wave_block(V, Li, R, k, orbital, dtype, static_cast<hipStream_t>(stream)),
+            "plane wave kernel");
+    return KPM_OK;
+}
+
 kpm_status kpm_dos(const double* mu, int32_t R, int32_t M, int32_t kernel, double kparam, double a, double b,
                    const double* E, int32_t K, double* rho, void* stream) {
     g_error.clear();

@@ -71,7 +71,7 @@ EXPORTS = ("kpm_build_hamiltonian", "kpm_hamiltonian_info", "kpm_export_csr",
            "kpm_mlp_param_count", "kpm_mlp_set_params", "kpm_mlp_get_params", "kpm_mlp_get_grads",
            "kpm_mlp_forward", "kpm_mlp_backward", "kpm_mlp_adam_step", "kpm_mlp_train_step",
            "kpm_mlp_gemm_bf16", "kpm_dos_batched", "kpm_moment_features", "kpm_random_phase_block",
-           "kpm_moments_naive", "kpm_axpy", "kpm_scal", "kpm_dot",
+           "kpm_moments_naive", "kpm_axpy", "kpm_scal", "kpm_dot", "kpm_site_block", "kpm_plane_wave_block",
            "kpm_last_error", "kpm_version")
 
 
@@ -149,6 +149,10 @@ def lib():
     L.kpm_dos_batched.argtypes = [vp, i32, i32, i32, i32, i32, dbl, vp, vp, vp, i32, i32, vp, vp]
     L.kpm_moment_features.restype = ctypes.c_int
     L.kpm_moment_features.argtypes = [vp, i32, i32, i32, i32, vp, vp, vp]
+    L.kpm_site_block.restype = ctypes.c_int
+    L.kpm_site_block.argtypes = [vp, i64, i32, vp, i32, vp]
+    L.kpm_plane_wave_block.restype = ctypes.c_int
+    L.kpm_plane_wave_block.argtypes = [vp, vp, i32, vp, vp, i32, vp]
     L.kpm_random_phase_block.restype = ctypes.c_int
     L.kpm_random_phase_block.argtypes = [vp, i64, i32, i32, ctypes.c_uint64, vp]
     L.kpm_last_error.restype = ctypes.c_char_p
@@ -366,6 +370,37 @@ def random_phase_block(N: int, R: int, seed: int, dtype: str = "c128", out: torc
         out = torch.empty((N, R), dtype=_TORCH_DTYPE[dt], device="cuda")
     _check(lib().kpm_random_phase_block(_dptr(out), int(N), int(R), dt, int(seed) & 0xFFFFFFFFFFFFFFFF,
                                         _stream(stream)))
+    return out
+
+
+def site_block(N: int, rows, dtype: str = "c128", out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """kpm_site_block: [N][R] block whose column r is the unit vector of row rows[r]."""
+    import numpy as np
+    r = np.ascontiguousarray(rows, dtype=np.int64)
+    dt = _DTYPES[dtype]
+    if out is None:
+        out = torch.empty((N, r.size), dtype=_TORCH_DTYPE[dt], device="cuda")
+    _check(lib().kpm_site_block(_dptr(out), int(N), int(r.size), r.ctypes.data_as(ctypes.c_void_p), dt,
+                                _stream(stream)))
+    return out
+
+
+def plane_wave_block(L, k, orbitals, dtype: str = "c128", out: torch.Tensor | None = None,
+                     stream=None) -> torch.Tensor:
+    """kpm_plane_wave_block: [N][R] block of plane waves (momenta k [R][3], orbitals [R])."""
+    import numpy as np
+    Ls = np.ascontiguousarray(L, dtype=np.int32)
+    kk = np.ascontiguousarray(k, dtype=np.float64).reshape(-1, 3)
+    oo = np.ascontiguousarray(orbitals, dtype=np.int32)
+    if kk.shape[0] != oo.size:
+        raise ValueError("one orbital per momentum")
+    dt = _DTYPES[dtype]
+    N = 4 * int(Ls[0]) * int(Ls[1]) * int(Ls[2])
+    if out is None:
+        out = torch.empty((N, oo.size), dtype=_TORCH_DTYPE[dt], device="cuda")
+    _check(lib().kpm_plane_wave_block(_dptr(out), Ls.ctypes.data_as(ctypes.c_void_p), int(oo.size),
+                                      kk.ctypes.data_as(ctypes.c_void_p), oo.ctypes.data_as(ctypes.c_void_p), dt,
+                                      _stream(stream)))
     return out
 
 

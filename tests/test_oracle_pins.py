@@ -206,6 +206,58 @@ def test_identity_block_gives_exact_trace():
 
 
 # --------------------------------------------------------------------------
+# Local and momentum-resolved moments (deterministic start vectors)
+# --------------------------------------------------------------------------
+def _bloch(k, t=1.0):
+    """4 x 4 Bloch matrix of the clean lattice from eq. "Ham": a plane wave
+    exp(i k . r) u is mapped to exp(i k . r) H(k) u with
+    H(k) = 2 Gamma^1 + sum_j [T_j exp(-i k_j) + T_j^dagger exp(i k_j)],
+    T_j = -t (Gamma^1 - i Gamma^{j+1}) / 2."""
+    G = _gammas()
+    Hk = 2.0 * G[1]
+    for j in range(3):
+        T = -0.5 * t * (G[1] - 1j * G[j + 2])
+        Hk = Hk + T * np.exp(-1j * k[j]) + T.conj().T * np.exp(1j * k[j])
+    return Hk
+
+
+def test_plane_wave_moments_match_bloch_closed_form():
+    # on the clean periodic lattice a plane wave of a lattice momentum stays in
+    # the 4-dimensional Bloch subspace: mu_n = [T_n((H(k) - b) / a)]_oo
+    L = (4, 6, 5)
+    H = O.ti_hamiltonian(L, np.zeros(4 * 6 * 5))
+    a, b = O.scaling(*O.gershgorin(H))
+    ks = [(0.0, 0.0, 0.0), (2 * math.pi / 4, 0.0, 0.0), (math.pi, 2 * math.pi / 6 * 2, 2 * math.pi / 5),
+          (2 * math.pi * 3 / 4, 2 * math.pi * 5 / 6, 2 * math.pi * 4 / 5)]
+    kk = [k for k in ks for _ in range(4)]
+    oo = [o for _ in ks for o in range(4)]
+    M = 64
+    mu = O.kpm_moments(H, a, b, O.plane_wave_block(L, kk, oo), M)
+    n = np.arange(M)
+    for i, k in enumerate(ks):
+        lam, U = np.linalg.eigh((_bloch(k) - b * np.eye(4)) / a)
+        Tn = np.cos(np.outer(n, np.arccos(np.clip(lam, -1, 1))))   # [n][band]
+        for o in range(4):
+            ref = Tn @ (np.abs(U[o, :]) ** 2)
+            assert np.abs(mu[4 * i + o] - ref).max() <= 1e-12, (k, o)
+
+
+def test_site_moments_match_eigendecomposition():
+    # local moments <e_i|T_n(Htilde)|e_i> = sum_k |U_ik|^2 T_n(lambda_k)
+    L = (3, 4, 3)
+    pot = inputs.potential(L, 2.0, 5)
+    H = O.ti_hamiltonian(L, pot, periodic=(1, 1, 0))
+    a, b = O.scaling(*O.gershgorin(H))
+    rows = [0, 5, 17, H.n - 1]
+    M = 48
+    mu = O.kpm_moments(H, a, b, O.site_block(H.n, rows), M)
+    lam, U = np.linalg.eigh((H.dense() - b * np.eye(H.n)) / a)
+    Tn = np.cos(np.outer(np.arange(M), np.arccos(np.clip(lam, -1, 1))))
+    for r, i in enumerate(rows):
+        assert np.abs(mu[r] - Tn @ (np.abs(U[i, :]) ** 2)).max() <= 1e-12
+
+
+# --------------------------------------------------------------------------
 # Reconstruction: damping kernels and density of states
 # --------------------------------------------------------------------------
 def test_jackson_kernel_properties():
