@@ -331,6 +331,51 @@ def leg_spectral(M: int = 1000, K: int = 1024):
     return out
 
 
+def leg_slab(M: int = 2000, R: int = 32):
+    """The paper's own geometry: slabs of 100 x 100 x 40 (its performance-model domain) and
+    200 x 100 x 40 sites (its single-device domain), periodic in x and y, open in z, with a
+    superlattice of quantum dots in the top layers; complex128, R = 32, M = 2000, Jackson DOS."""
+    import torch
+    from paper_1410_5242_amd import autotune, inputs, kpm
+    out = {"workload": f"TI slabs periodic in x, y, open in z; quantum dots (period 25, radius 6, 4 layers, "
+                       f"V = 1) + disorder gamma = 0.2; complex128, R = {R}, M = {M}", "points": []}
+    for L in ((100, 100, 40), (200, 100, 40)):
+        pot = inputs.quantum_dot_potential(L)
+        H = kpm.build_hamiltonian(L, pot, periodic=(1, 1, 0))
+        kpm.reset_sweep_tuning()
+        tuned = autotune.apply_sweep(autotune.TuningCache(), H, R, L)
+        V0 = kpm.random_phase_block(H.N, R, 1, "c128")
+        kpm.moments(H, V0, 8)
+        torch.cuda.synchronize()
+        kpm.sweep_profile_read()
+        kpm.sweep_profile_enable(PROFILE_PERIOD)
+        t0 = time.perf_counter()
+        mu = kpm.moments(H, V0, M)
+        E = torch.linspace(H.b - 0.999 * H.a, H.b + 0.999 * H.a, 4096, dtype=torch.float64, device="cuda")
+        rho = kpm.dos(mu, H.a, H.b, E)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        kpm.sweep_profile_enable(False)
+        n, tot, lo, hi = kpm.sweep_profile_read()
+        kernel = kpm.sweep_kernel(H, R)
+        Si = 0 if kernel == "lattice_kernel" else 4
+        N = H.N
+        nnz = 13 * N - 2 * 2 * 4 * L[0] * L[1]   # the two surfaces lack their outward z neighbour
+        stored = 13 * N * (16 + Si) + 3 * R * 16 * N
+        model = nnz * (16 + 4) + 3 * R * 16 * N
+        avg = tot / max(n, 1) * 1e-3
+        out["points"].append({"L": list(L), "N": N, "kernel": kernel, "autotuned": tuned,
+                              "seconds": round(dt, 4), "sweep_avg_us": round(avg * 1e6, 1),
+                              "GBps_stored": round(stored / avg / 1e9, 1),
+                              "GBps_paper_model": round(model / avg / 1e9, 1),
+                              "gflops": round(sweep_flops(N, R) / avg / 1e9, 1),
+                              "dos_integral": round(float(rho.sum().item() * (E[1] - E[0]).item()), 4)})
+        kpm.reset_sweep_tuning()
+        H.close()
+        del V0, mu
+    return out
+
+
 def leg_time_to_dos():
     from paper_1410_5242_amd import learned, time_to_dos
     if not os.path.exists(learned.WEIGHTS):
@@ -381,7 +426,7 @@ def main():
                     help="short run for hardware counters: a 1 GiB device copy (the calibration kernel "
                          "of known traffic) and --probe-sweeps fused sweeps of the workload")
     ap.add_argument("--probe-sweeps", type=int, default=8)
-    ap.add_argument("--legs", default="variants,ladder,precision,batched,spectral,time_to_dos",
+    ap.add_argument("--legs", default="variants,ladder,precision,batched,spectral,slab,time_to_dos",
                     help="extra measurements after the headline step: any of variants, precision, batched, "
                          "time_to_dos (comma separated), or none")
     args = ap.parse_args()
@@ -511,7 +556,8 @@ def main():
     del V0
     legs = [x for x in args.legs.split(",") if x and x != "none"]
     for name, fn in (("variants", leg_variants), ("ladder", leg_ladder), ("precision", leg_precision),
-                     ("batched", leg_batched), ("spectral", leg_spectral), ("time_to_dos", leg_time_to_dos)):
+                     ("batched", leg_batched), ("spectral", leg_spectral), ("slab", leg_slab),
+                     ("time_to_dos", leg_time_to_dos)):
         if name in legs:
             log(f"[bench] leg {name}")
             out[name] = fn()

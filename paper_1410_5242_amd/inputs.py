@@ -23,6 +23,24 @@ def potential(L, gamma: float, seed: int) -> np.ndarray:
     return rng.uniform(-0.5 * gamma, 0.5 * gamma, size=Lx * Ly * Lz)
 
 
+def quantum_dot_potential(L, period: int = 25, radius: float = 6.0, v_dot: float = 1.0, depth: int = 4,
+                          gamma: float = 0.2, seed: int = 0) -> np.ndarray:
+    """Potential of a quantum-dot superlattice on a slab (x fastest), float64.
+
+    Cylindrical dots of radius `radius` (sites) on a square superlattice of
+    period `period` in the x-y plane, centred in each cell, reaching `depth`
+    layers down from the top surface z = Lz - 1, raise the potential by v_dot;
+    on top of that the uniform disorder U[-gamma/2, gamma/2] of `potential`.
+    """
+    Lx, Ly, Lz = (int(v) for v in L)
+    n = np.arange(Lx * Ly * Lz)
+    x, y, z = n % Lx, (n // Lx) % Ly, n // (Lx * Ly)
+    dx = (x % period) - 0.5 * (period - 1)
+    dy = (y % period) - 0.5 * (period - 1)
+    dot = (dx * dx + dy * dy <= radius * radius) & (z >= Lz - depth)
+    return potential(L, gamma, seed) + v_dot * dot.astype(np.float64)
+
+
 def phase_block(N: int, R: int, seed: int, dtype=np.complex128) -> np.ndarray:
     """[N][R] block of random-phase unit vectors v_ir = exp(2 pi i u_ir) / sqrt(N).
 

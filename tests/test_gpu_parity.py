@@ -278,6 +278,30 @@ def test_wide_lattice_sweep_matches_oracle(L, periodic, dtype):
         assert np.abs(got_eta - ref_eta).max() <= TOL_C128
 
 
+@pytest.mark.parametrize("lattice", [0, 2])
+def test_quantum_dot_slab_matches_oracle(lattice):
+    # the paper's geometry in small: periodic in x and y, open in z, a
+    # superlattice of quantum dots in the top layers (rows of the two
+    # surfaces carry padding slots)
+    K = kpm()
+    L, per, M, R = (12, 8, 6), (1, 1, 0), 40, 32
+    say("quantum-dot slab, lattice", lattice)
+    pot = inputs.quantum_dot_potential(L, period=6, radius=2.0, v_dot=1.5, depth=2, gamma=0.5, seed=3)
+    Ho = O.ti_hamiltonian(L, pot, periodic=per)
+    a, b = O.scaling(*O.gershgorin(Ho))
+    v0 = inputs.phase_block(Ho.n, R, 4)
+    ref = O.kpm_moments(Ho, a, b, v0, M)
+    try:
+        K.set_sweep_tuning(lattice=lattice)
+        H = K.build_hamiltonian(L, pot, periodic=per)
+        assert K.sweep_kernel(H, R) == ("lattice_kernel" if lattice else "gather_sweep_kernel")
+        H.close()
+        mu, _ = gpu_moments(L, pot, v0, M, periodic=per)
+    finally:
+        K.reset_sweep_tuning()
+    assert np.abs(mu - ref).max() <= TOL_C128
+
+
 @pytest.mark.parametrize("L", [(5, 4, 4), (4, 9, 3), (1, 1, 7)])
 def test_lattice_sweep_falls_back_for_one_site_tail_tiles(L):
     # a side with L mod 4 == 1 would leave tiles one site wide: the generic
