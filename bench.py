@@ -376,6 +376,30 @@ def leg_slab(M: int = 2000, R: int = 32):
     return out
 
 
+def leg_bounds():
+    """Spectral bounds on the 64^3 complex128 lattice (gamma = 1): Gershgorin discs (fused into
+    the build) against the extreme Ritz values of 25, 50 and 100 Lanczos steps on the device.
+    A tighter half-width a gives proportionally finer energy resolution per moment."""
+    import time
+    import torch
+    from paper_1410_5242_amd import inputs, kpm
+    L = (64, 64, 64)
+    H = kpm.build_hamiltonian(L, inputs.potential(L, 1.0, 0))
+    a_g = (H.emax - H.emin) / 2
+    out = {"workload": "TI 64x64x64 periodic, gamma=1, complex128",
+           "gershgorin": {"emin": round(H.emin, 6), "emax": round(H.emax, 6)}, "lanczos": []}
+    kpm.lanczos_bounds(H, 4, 1)
+    for steps in (25, 50, 100):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lo, hi = kpm.lanczos_bounds(H, steps, 1)
+        dt = time.perf_counter() - t0
+        out["lanczos"].append({"steps": steps, "emin": round(lo, 6), "emax": round(hi, 6),
+                               "seconds": round(dt, 4), "halfwidth_ratio_vs_gershgorin": round(((hi - lo) / 2) / a_g, 4)})
+    H.close()
+    return out
+
+
 def leg_time_to_dos():
     from paper_1410_5242_amd import learned, time_to_dos
     if not os.path.exists(learned.WEIGHTS):
@@ -426,7 +450,7 @@ def main():
                     help="short run for hardware counters: a 1 GiB device copy (the calibration kernel "
                          "of known traffic) and --probe-sweeps fused sweeps of the workload")
     ap.add_argument("--probe-sweeps", type=int, default=8)
-    ap.add_argument("--legs", default="variants,ladder,precision,batched,spectral,slab,time_to_dos",
+    ap.add_argument("--legs", default="variants,ladder,precision,batched,spectral,slab,bounds,time_to_dos",
                     help="extra measurements after the headline step: any of variants, precision, batched, "
                          "time_to_dos (comma separated), or none")
     args = ap.parse_args()
@@ -556,7 +580,7 @@ def main():
     del V0
     legs = [x for x in args.legs.split(",") if x and x != "none"]
     for name, fn in (("variants", leg_variants), ("ladder", leg_ladder), ("precision", leg_precision),
-                     ("batched", leg_batched), ("spectral", leg_spectral), ("slab", leg_slab),
+                     ("batched", leg_batched), ("spectral", leg_spectral), ("slab", leg_slab), ("bounds", leg_bounds),
                      ("time_to_dos", leg_time_to_dos)):
         if name in legs:
             log(f"[bench] leg {name}")

@@ -183,6 +183,26 @@ kpm_status kpm_dos(const double* mu, int32_t R, int32_t M, int32_t kernel, doubl
  * column has unit norm up to rounding.  Errors: KPM_EINVAL. */
 kpm_status kpm_random_phase_block(void* V, int64_t N, int32_t R, int32_t dtype, uint64_t seed, void* stream);
 
+/* Spectral bounds from `steps` Lanczos steps (section "Problem Description":
+ * a, b from Gershgorin's theorem or a few Lanczos sweeps).  Starting from
+ * the random-phase unit vector of kpm_random_phase_block(seed, R = 1), the
+ * recurrence w = H q_j - alpha_j q_j - beta_{j-1} q_{j-1}, alpha_j =
+ * Re <q_j|H q_j>, beta_j = |w|, q_{j+1} = w / beta_j runs on the device
+ * (one SpMV and four vector kernels per step, no reorthogonalisation); the
+ * smallest and largest eigenvalues of the resulting tridiagonal matrix (the
+ * extreme Ritz values, by bisection on Sturm counts) are written to *emin and
+ * *emax (host).  Ritz values lie inside the spectrum, so these are not
+ * rigorous bounds: enlarge them (kpm_set_scaling) and keep the moment check
+ * of kpm_moments, which reports a scaling that does not contain the spectrum.
+ * 2 <= steps <= 1024.  Uses H's cached [N] vectors; synchronises `stream`.
+ * Errors: KPM_EINVAL, KPM_ENOMEM, KPM_EDEVICE. */
+kpm_status kpm_lanczos_bounds(const kpm_hamiltonian* H, int32_t steps, uint64_t seed, double* emin, double* emax,
+                              void* stream);
+
+/* Replace the scaling of H: the sweeps apply Htilde = (H - b) / a from now on
+ * (a > 0 finite, b finite).  Errors: KPM_EINVAL. */
+kpm_status kpm_set_scaling(kpm_hamiltonian* H, double a, double b);
+
 /* Deterministic start blocks for local and momentum-resolved spectra (the
  * local DOS and the spectral function A(k, E) of Fig. "topi_demo"; the paper
  * shows them without formulas, these follow the standard KPM reading: the

@@ -276,6 +276,36 @@ def dense_moments(Hd: np.ndarray, a: float, b: float, v0: np.ndarray, M: int) ->
     return (Tn @ w).T
 
 
+def lanczos(H: CSR, v0: np.ndarray, steps: int):
+    """Lanczos recurrence (section "Problem Description", bounds from a few Lanczos
+    sweeps) from the start vector v0, without reorthogonalisation:
+    w = H q_j - alpha_j q_j - beta_{j-1} q_{j-1}, alpha_j = Re <q_j|H q_j>,
+    beta_j = |w|, q_{j+1} = w / beta_j.  Returns (alpha [steps], beta [steps])."""
+    Hd = H.dense()
+    q = np.asarray(v0, dtype=np.complex128).reshape(-1)
+    q = q / np.linalg.norm(q)
+    qp = np.zeros_like(q)
+    alpha, beta = np.zeros(steps), np.zeros(steps)
+    b_prev = 0.0
+    for j in range(steps):
+        w = Hd @ q
+        alpha[j] = np.vdot(q, w).real
+        w = w - alpha[j] * q - b_prev * qp
+        beta[j] = np.linalg.norm(w)
+        qp, q = q, (w / beta[j] if beta[j] > 0 else np.zeros_like(w))
+        b_prev = beta[j]
+    return alpha, beta
+
+
+def tridiagonal_extremes(alpha: np.ndarray, beta: np.ndarray):
+    """Smallest and largest eigenvalue of the tridiagonal matrix with diagonal
+    alpha and off-diagonal beta[:-1] (the extreme Ritz values)."""
+    k = len(alpha)
+    T = np.diag(alpha) + np.diag(beta[:k - 1], 1) + np.diag(beta[:k - 1], -1)
+    lam = np.linalg.eigvalsh(T)
+    return lam[0], lam[-1]
+
+
 def site_block(N: int, rows) -> np.ndarray:
     """Start block for local quantities: column r is the unit vector of row rows[r]."""
     rows = [int(r) for r in rows]

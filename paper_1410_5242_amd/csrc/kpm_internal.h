@@ -33,6 +33,8 @@ struct Workspace {
     void* naive[3] = {nullptr, nullptr, nullptr};   // v, w, u of the naive algorithm ([N] each)
     size_t naive_bytes = 0;
     double* dot_part = nullptr;            // [naive_dot_partials()][2] scalar-product partials
+    double* lanczos = nullptr;             // alpha, beta and scalars of the Lanczos bounds
+    size_t lanczos_bytes = 0;
 };
 
 }  // namespace kpm
@@ -234,6 +236,16 @@ hipError_t launch_axpy(int dtype, int64_t n, double alpha, const void* x, void* 
 hipError_t launch_scal(int dtype, int64_t n, double alpha, void* x, hipStream_t s);
 hipError_t launch_dot(int dtype, int64_t n, const void* x, const void* y, double* part, double* out, hipStream_t s);
 hipError_t launch_column(int dtype, int64_t n, int R, int r, const void* V, void* v, hipStream_t s);
+// Lanczos bounds: the recurrence's vector steps with alpha, beta read from
+// device memory, and the extreme eigenvalues of the tridiagonal matrix.
+int lanczos_max_steps();
+hipError_t launch_lanczos_update(int dtype, int64_t n, const double* ab, const void* q, const void* qp, void* w,
+                                 hipStream_t s);
+hipError_t launch_lanczos_normalise(int dtype, int64_t n, const double* nrm, const void* w, void* q, double* beta_out,
+                                    hipStream_t s);
+hipError_t launch_lanczos_pack(const double* dot, const double* beta_prev, double* ab, hipStream_t s);
+hipError_t launch_tridiag_extremes(const double* ab, const double* beta, int k, double* out, hipStream_t s);
+
 // Deterministic start blocks (at most kMaxStartColumns columns): unit
 // vectors of given rows; plane waves of given momenta on given orbitals.
 constexpr int kMaxStartColumns = 64;

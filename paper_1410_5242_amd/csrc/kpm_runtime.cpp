@@ -389,6 +389,7 @@ void kpm_destroy_hamiltonian(kpm_hamiltonian* H) {
     for (int i = 0; i < 3; ++i)
         if (H->ws.naive[i]) (void)hipFree(H->ws.naive[i]);
     if (H->ws.dot_part) (void)hipFree(H->ws.dot_part);
+    if (H->ws.lanczos) (void)hipFree(H->ws.lanczos);
     delete H;
 }
 
@@ -561,6 +562,77 @@ kpm_status kpm_moments_naive(const kpm_hamiltonian* Hc, const void* V0, int32_t 
         if (*H->ws.flag_host)
             return fail(KPM_ESPECTRUM, "moments left [-mu_0, mu_0]: the scaled spectrum is not inside [-1, 1]");
     }
+    return KPM_OK;
+}
+
+kpm_status kpm_lanczos_bounds(const kpm_hamiltonian* Hc, int32_t steps, uint64_t seed, double* emin, double* emax,
+                              void* stream) {
+    g_error.clear();
+    if (!Hc || !emin || !emax) return fail(KPM_EINVAL, "H, emin or emax is NULL");
+    if (steps < 2 || steps > lanczos_max_steps()) return fail(KPM_EINVAL, "steps must be in [2, 1024]");
+    auto* H = const_cast<kpm_hamiltonian*>(Hc);
+    kpm_status st = check_device(H);
+    if (st != KPM_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t N = H->nrows;
+    const int dt = H->dtype;
+    const size_t vb = static_cast<size_t>(N) * 2 * real_size(dt);
+    for (int i = 0; i < 3; ++i) {
+        size_t have = H->ws.naive_bytes;
+        if ((st = grow(&H->ws.naive[i], &have, vb, "hipMalloc(Lanczos vector)")) != KPM_OK) return st;
+    }
+    H->ws.naive_bytes = vb;
+    if (!H->ws.dot_part)
+        KPM_HIP(hipMalloc(&H->ws.dot_part, static_cast<size_t>(naive_dot_partials()) * 2 * sizeof(double)),
+                "hipMalloc(dot partials)");
+    // [steps][2] (alpha_j, beta_{j-1}), [steps] beta_j, <q|Hq>, |w|^2, the two extremes
+    const size_t nd = 3 * static_cast<size_t>(steps) + 6;
+    if ((st = grow(&H->ws.lanczos, &H->ws.lanczos_bytes, nd * sizeof(double), "hipMalloc(Lanczos scalars)")) != KPM_OK)
+        return st;
+    if ((st = ensure_queue(H)) != KPM_OK) return st;
+    if ((st = ensure_schedule(H)) != KPM_OK) return st;
+    double* ab = H->ws.lanczos;
+    double* beta = ab + 2 * steps;
+    double* dq = beta + steps;
+    double* nrm = dq + 2;
+    double* ext = nrm + 2;
+    void* qp = H->ws.naive[0];
+    void* q = H->ws.naive[1];
+    void* w = H->ws.naive[2];
+    // q_0 = 0 (its coefficient is 0 in the first step, but 0 * garbage need not be 0)
+    const int64_t words = static_cast<int64_t>(vb / sizeof(int));
+    if (words > INT32_MAX) return fail(KPM_ENOTSUP, "Lanczos vector too large");
+    KPM_HIP(launch_zero_ints(static_cast<int*>(qp), static_cast<int>(words), s), "zero kernel");
+    // q_1: a random-phase unit vector
+    KPM_HIP(launch_phase_block(q, N, 1, dt, seed, s), "phase block kernel");
+    for (int j = 0; j < steps; ++j) {
+        SweepArgs a{H->val, H->col, N, q, w, H->sched, 1.0, 0.0, 0.0, nullptr, launch_grid(H, 1)};
+        a.queue = H->ws.queue;
+        for (int i = 0; i < 3; ++i) a.L[i] = H->L[i];
+        if (sweep_uses_queue(H, 1)) KPM_HIP(launch_zero_ints(H->ws.queue, kXcds, s), "zero kernel");
+        KPM_HIP(launch_any_sweep(H, 1, KPM_PLAIN, a, s), "spmv");                       // w = H q
+        KPM_HIP(launch_dot(dt, N, q, w, H->ws.dot_part, dq, s), "dot kernel");           // alpha_j
+        KPM_HIP(launch_lanczos_pack(dq, j > 0 ? beta + j - 1 : nullptr, ab + 2 * j, s), "pack kernel");
+        KPM_HIP(launch_lanczos_update(dt, N, ab + 2 * j, q, qp, w, s), "update kernel"); // w -= alpha q + beta qp
+        KPM_HIP(launch_dot(dt, N, w, w, H->ws.dot_part, nrm, s), "nrm2 kernel");         // beta_j^2
+        KPM_HIP(launch_lanczos_normalise(dt, N, nrm, w, qp, beta + j, s), "normalise kernel");
+        std::swap(qp, q);   // q_{j-1} <- q_j, q_j <- q_{j+1}
+    }
+    KPM_HIP(launch_tridiag_extremes(ab, beta, steps, ext, s), "tridiagonal kernel");
+    double host[2];
+    KPM_HIP(hipMemcpyAsync(host, ext, sizeof(host), hipMemcpyDeviceToHost, s), "copy extremes");
+    KPM_HIP(hipStreamSynchronize(s), "synchronise");
+    *emin = host[0];
+    *emax = host[1];
+    return KPM_OK;
+}
+
+kpm_status kpm_set_scaling(kpm_hamiltonian* H, double a, double b) {
+    g_error.clear();
+    if (!H) return fail(KPM_EINVAL, "H is NULL");
+    if (!(a > 0.0) || !std::isfinite(a) || !std::isfinite(b)) return fail(KPM_EINVAL, "need finite a > 0 and finite b");
+    H->a = a;
+    H->b = b;
     return KPM_OK;
 }
 

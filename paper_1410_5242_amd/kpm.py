@@ -72,6 +72,7 @@ EXPORTS = ("kpm_build_hamiltonian", "kpm_hamiltonian_info", "kpm_export_csr",
            "kpm_mlp_forward", "kpm_mlp_backward", "kpm_mlp_adam_step", "kpm_mlp_train_step",
            "kpm_mlp_gemm_bf16", "kpm_dos_batched", "kpm_moment_features", "kpm_random_phase_block",
            "kpm_moments_naive", "kpm_axpy", "kpm_scal", "kpm_dot", "kpm_site_block", "kpm_plane_wave_block",
+           "kpm_lanczos_bounds", "kpm_set_scaling",
            "kpm_last_error", "kpm_version")
 
 
@@ -149,6 +150,10 @@ def lib():
     L.kpm_dos_batched.argtypes = [vp, i32, i32, i32, i32, i32, dbl, vp, vp, vp, i32, i32, vp, vp]
     L.kpm_moment_features.restype = ctypes.c_int
     L.kpm_moment_features.argtypes = [vp, i32, i32, i32, i32, vp, vp, vp]
+    L.kpm_lanczos_bounds.restype = ctypes.c_int
+    L.kpm_lanczos_bounds.argtypes = [vp, i32, ctypes.c_uint64, ctypes.POINTER(dbl), ctypes.POINTER(dbl), vp]
+    L.kpm_set_scaling.restype = ctypes.c_int
+    L.kpm_set_scaling.argtypes = [vp, dbl, dbl]
     L.kpm_site_block.restype = ctypes.c_int
     L.kpm_site_block.argtypes = [vp, i64, i32, vp, i32, vp]
     L.kpm_plane_wave_block.restype = ctypes.c_int
@@ -371,6 +376,20 @@ def random_phase_block(N: int, R: int, seed: int, dtype: str = "c128", out: torc
     _check(lib().kpm_random_phase_block(_dptr(out), int(N), int(R), dt, int(seed) & 0xFFFFFFFFFFFFFFFF,
                                         _stream(stream)))
     return out
+
+
+def lanczos_bounds(H: Hamiltonian, steps: int = 50, seed: int = 0, stream=None):
+    """kpm_lanczos_bounds: (emin, emax), the extreme Ritz values after `steps` Lanczos steps."""
+    lo, hi = ctypes.c_double(), ctypes.c_double()
+    _check(lib().kpm_lanczos_bounds(H.handle, int(steps), int(seed) & 0xFFFFFFFFFFFFFFFF, ctypes.byref(lo),
+                                    ctypes.byref(hi), _stream(stream)))
+    return lo.value, hi.value
+
+
+def set_scaling(H: Hamiltonian, a: float, b: float):
+    """kpm_set_scaling: the sweeps apply (H - b) / a from now on."""
+    _check(lib().kpm_set_scaling(H.handle, float(a), float(b)))
+    H.a, H.b = float(a), float(b)
 
 
 def site_block(N: int, rows, dtype: str = "c128", out: torch.Tensor | None = None, stream=None) -> torch.Tensor:

@@ -70,6 +70,11 @@ def test_argument_validation_without_device(L):
     assert L.kpm_scal(1, 4, 1.0, None, None) == kpm.KPM_EINVAL                        # NULL vector
     assert L.kpm_dot(0, 4, fake, fake, None, None) == kpm.KPM_EINVAL                  # NULL out
     assert L.kpm_axpy(0, 0, 1.0, None, None, None) == kpm.KPM_OK                      # empty: no-op
+    lo, hi = ctypes.c_double(), ctypes.c_double()
+    assert L.kpm_lanczos_bounds(None, 10, 0, ctypes.byref(lo), ctypes.byref(hi), None) == kpm.KPM_EINVAL
+    assert L.kpm_set_scaling(None, 1.0, 0.0) == kpm.KPM_EINVAL
+    assert L.kpm_site_block(None, 4, 1, fake, 0, None) == kpm.KPM_EINVAL
+    assert L.kpm_plane_wave_block(fake, None, 1, fake, fake, 0, None) == kpm.KPM_EINVAL
     assert L.kpm_sweep_profile_enable(-1) == kpm.KPM_EINVAL   # sampling period < 0
     assert L.kpm_sweep_profile_enable(0) == kpm.KPM_OK
     L.kpm_destroy_hamiltonian(None)   # no-op

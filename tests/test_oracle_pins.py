@@ -257,6 +257,21 @@ def test_site_moments_match_eigendecomposition():
         assert np.abs(mu[r] - Tn @ (np.abs(U[i, :]) ** 2)).max() <= 1e-12
 
 
+def test_lanczos_extremes_converge_inside_the_spectrum():
+    # Ritz values lie inside [lambda_min, lambda_max] and the extreme ones
+    # converge to the extreme eigenvalues (dense eigvalsh; clean lattice: +-5)
+    for L, pot in (((3, 4, 3), inputs.potential((3, 4, 3), 2.0, 1)), ((4, 4, 4), np.zeros(64))):
+        H = O.ti_hamiltonian(L, pot, periodic=(1, 1, 1))
+        lam = np.linalg.eigvalsh(H.dense())
+        v0 = inputs.phase_block(H.n, 1, 7)[:, 0]
+        lo10, hi10 = O.tridiagonal_extremes(*O.lanczos(H, v0, 10))
+        lo, hi = O.tridiagonal_extremes(*O.lanczos(H, v0, 80))
+        assert lam[0] - 1e-10 <= lo <= lo10 and hi10 <= hi <= lam[-1] + 1e-10
+        assert abs(lo - lam[0]) <= 1e-8 and abs(hi - lam[-1]) <= 1e-8
+        if not pot.any():
+            assert abs(hi - 5.0) <= 1e-8 and abs(lo + 5.0) <= 1e-8
+
+
 # --------------------------------------------------------------------------
 # Reconstruction: damping kernels and density of states
 # --------------------------------------------------------------------------
