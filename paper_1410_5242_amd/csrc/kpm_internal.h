@@ -239,11 +239,10 @@ hipError_t launch_column(int dtype, int64_t n, int R, int r, const void* V, void
 // Lanczos bounds: the recurrence's vector steps with alpha, beta read from
 // device memory, and the extreme eigenvalues of the tridiagonal matrix.
 int lanczos_max_steps();
-hipError_t launch_lanczos_update(int dtype, int64_t n, const double* ab, const void* q, const void* qp, void* w,
-                                 hipStream_t s);
+hipError_t launch_lanczos_update(int dtype, int64_t n, const double* dot, const double* beta_prev, double* ab,
+                                 const void* q, const void* qp, void* w, hipStream_t s);
 hipError_t launch_lanczos_normalise(int dtype, int64_t n, const double* nrm, const void* w, void* q, double* beta_out,
                                     hipStream_t s);
-hipError_t launch_lanczos_pack(const double* dot, const double* beta_prev, double* ab, hipStream_t s);
 hipError_t launch_tridiag_extremes(const double* ab, const double* beta, int k, double* out, hipStream_t s);
 
 // Deterministic start blocks (at most kMaxStartColumns columns): unit

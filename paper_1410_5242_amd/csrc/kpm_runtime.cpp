@@ -612,8 +612,8 @@ kpm_status kpm_lanczos_bounds(const kpm_hamiltonian* Hc, int32_t steps, uint64_t
         if (sweep_uses_queue(H, 1)) KPM_HIP(launch_zero_ints(H->ws.queue, kXcds, s), "zero kernel");
         KPM_HIP(launch_any_sweep(H, 1, KPM_PLAIN, a, s), "spmv");                       // w = H q
         KPM_HIP(launch_dot(dt, N, q, w, H->ws.dot_part, dq, s), "dot kernel");           // alpha_j
-        KPM_HIP(launch_lanczos_pack(dq, j > 0 ? beta + j - 1 : nullptr, ab + 2 * j, s), "pack kernel");
-        KPM_HIP(launch_lanczos_update(dt, N, ab + 2 * j, q, qp, w, s), "update kernel"); // w -= alpha q + beta qp
+        KPM_HIP(launch_lanczos_update(dt, N, dq, j > 0 ? beta + j - 1 : nullptr, ab + 2 * j, q, qp, w, s),
+                "update kernel");                                                         // w -= alpha q + beta qp
         KPM_HIP(launch_dot(dt, N, w, w, H->ws.dot_part, nrm, s), "nrm2 kernel");         // beta_j^2
         KPM_HIP(launch_lanczos_normalise(dt, N, nrm, w, qp, beta + j, s), "normalise kernel");
         std::swap(qp, q);   // q_{j-1} <- q_j, q_j <- q_{j+1}
