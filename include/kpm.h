@@ -153,7 +153,7 @@ kpm_status kpm_moments_naive(const kpm_hamiltonian* H, const void* V0, int32_t R
  *   kpm_dot:  out[0] + i out[1] = sum_i conj(x_i) y_i, accumulated in FP64
  *             (out: device, 2 doubles; x == y gives the squared norm with
  *             out[1] = 0).  The sum is reduced in a fixed order through a
- *             16 KiB partials buffer per device, allocated on the first call
+ *             32 KiB partials buffer per device, allocated on the first call
  *             and held until the process ends; calls that overlap on one
  *             device (other streams, other threads) share it and race.
  * Errors: KPM_EINVAL (dtype, n < 0, NULL or misaligned vector). */
