@@ -18,7 +18,7 @@ from . import kpm as K
 GROUP = 16   # sites or momenta per blocked run (4 orbitals each: R <= 64)
 
 
-def _widths(n: int) -> int:
+def _group_size(n: int) -> int:
     """Smallest group size >= n among 1, 2, 4, 8, 16 (R = 4 x that is a supported block width)."""
     g = 1
     while g < n:
@@ -50,7 +50,7 @@ def local_dos(H: K.Hamiltonian, L, sites, M: int, E: torch.Tensor, kernel: str =
     blocks = []
     for i in range(0, len(sites), GROUP):
         chunk = sites[i:i + GROUP]
-        g = _widths(len(chunk))
+        g = _group_size(len(chunk))
         padded = chunk + [chunk[-1]] * (g - len(chunk))
         rows = [4 * s + o for s in padded for o in range(4)]
         blocks.append((K.site_block(H.N, rows, _dtype_name(H)), len(chunk)))
@@ -66,7 +66,7 @@ def spectral_function(H: K.Hamiltonian, L, momenta, M: int, E: torch.Tensor, ker
     blocks = []
     for i in range(0, len(ks), GROUP):
         chunk = ks[i:i + GROUP]
-        g = _widths(len(chunk))
+        g = _group_size(len(chunk))
         padded = chunk + [chunk[-1]] * (g - len(chunk))
         kk = [k for k in padded for _ in range(4)]
         orbs = [o for _ in padded for o in range(4)]
