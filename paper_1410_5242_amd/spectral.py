@@ -47,6 +47,9 @@ def local_dos(H: K.Hamiltonian, L, sites, M: int, E: torch.Tensor, kernel: str =
     Returns (mu [n][4][M], rho [n][K]); rho is the orbital average (integral 1).
     """
     sites = [int(s) for s in sites]
+    nsites = int(L[0]) * int(L[1]) * int(L[2])
+    if 4 * nsites != H.N or any(not 0 <= s < nsites for s in sites):
+        raise ValueError("L must be H's lattice and every site inside it")
     blocks = []
     for i in range(0, len(sites), GROUP):
         chunk = sites[i:i + GROUP]
