@@ -326,15 +326,16 @@ def apply_batched(cache: TuningCache, Hs, R: int) -> bool:
 HEADLINE_L = (64, 64, 64)
 FAMILY = dict(n=512, sides=(12, 16, 20, 24), gamma_max=4.0, seed=0, R=8, M=512)
 TTD_INSTANCES, TTD_M = 1000, 256   # time-to-DOS family (tuned at a mid-range number of moments)
+SLABS = ((100, 100, 40), (200, 100, 40))   # the paper's slab domains (quantum dots, open z), R = 32
 
 
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description="Tune launch shapes on the benchmark workloads (64^3 TI lattice "
                                              "at every block width; the 512-instance family) and write the cache")
     ap.add_argument("--out", default=DEFAULT_CACHE)
-    ap.add_argument("--parts", default="sweep,batched,ttd",
+    ap.add_argument("--parts", default="sweep,batched,ttd,slab",
                     help="sweep, batched, ttd (the time-to-DOS family: 1,000 learned-family instances, R = 16, "
-                         "complex64), comma separated")
+                         "complex64), slab (the quantum-dot slabs at R = 32, lattice-sweep shapes), comma separated")
     ap.add_argument("--widths", default="1,2,4,8,16,32,64")
     args = ap.parse_args(argv)
     import numpy as np
@@ -375,6 +376,16 @@ def main(argv=None) -> int:
         print(f"[autotune] {res.key}: {res.seconds:.4f} s with {res.best}", flush=True)
         cache.save()
         for H in Hs:
+            H.close()
+    if "slab" in parts:
+        for L in SLABS:
+            H = K.build_hamiltonian(L, inputs.quantum_dot_potential(L), periodic=(1, 1, 0), dtype="c128")
+            K.reset_sweep_tuning()
+            default = K.get_sweep_tuning()
+            cands = [default] + [c for c in sweep_candidates(32, True) if c["lattice"] == 2]
+            res = tune_sweep(H, 32, cache, L=L, candidates=cands)
+            print(f"[autotune] {res.key}: {res.seconds * 1e6:.1f} us/sweep with {res.best}", flush=True)
+            cache.save()
             H.close()
     print(f"[autotune] wrote {args.out}", flush=True)
     return 0
