@@ -110,7 +110,7 @@ def leg_precision(log_fn=None):
     against complex128 on the same seed (moments error, DOS L1 error, speed)."""
     import numpy as np
     import torch
-    from paper_1410_5242_amd import inputs, kpm
+    from paper_1410_5242_amd import autotune, inputs, kpm
     L, gamma, R, M, K = (128, 128, 64), 2.0, 32, 2000, 4096
     pot = inputs.potential(L, gamma, 0)
     res = {"workload": f"TI {L[0]}x{L[1]}x{L[2]} periodic, gamma={gamma}, R={R}, M={M}, same potential and start "
@@ -119,6 +119,8 @@ def leg_precision(log_fn=None):
     a = b = None
     for dt in ("c128", "c64"):
         H = kpm.build_hamiltonian(L, pot, dtype=dt)
+        kpm.reset_sweep_tuning()
+        tuned = autotune.apply_sweep(autotune.TuningCache(), H, R, L)
         a, b = H.a, H.b
         V0 = kpm.random_phase_block(H.N, R, 0, dt)
         E = torch.from_numpy(H.b + H.a * (-1.0 + (2.0 * np.arange(K) + 1.0) / K)).cuda()
@@ -135,7 +137,8 @@ def leg_precision(log_fn=None):
         Sd = 16 if dt == "c128" else 8
         bps = sweep_bytes(H.N, 13 * H.N, R, Sd, 0 if kpm.sweep_kernel(H, R) == "lattice_kernel" else 4)
         res[dt] = {"seconds": round(times[dt], 4), "GBps": round(bps * (M // 2) / times[dt] / 1e9, 1),
-                   "sweep_kernel": kpm.sweep_kernel(H, R)}
+                   "sweep_kernel": kpm.sweep_kernel(H, R), "autotuned": tuned}
+        kpm.reset_sweep_tuning()
         H.close()
         del V0
     dE = 2.0 * a / K

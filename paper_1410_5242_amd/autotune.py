@@ -327,15 +327,17 @@ HEADLINE_L = (64, 64, 64)
 FAMILY = dict(n=512, sides=(12, 16, 20, 24), gamma_max=4.0, seed=0, R=8, M=512)
 TTD_INSTANCES, TTD_M = 1000, 256   # time-to-DOS family (tuned at a mid-range number of moments)
 SLABS = ((100, 100, 40), (200, 100, 40))   # the paper's slab domains (quantum dots, open z), R = 32
+PRECISION_L, PRECISION_GAMMA = (128, 128, 64), 2.0   # the precision comparison, both dtypes, R = 32
 
 
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description="Tune launch shapes on the benchmark workloads (64^3 TI lattice "
                                              "at every block width; the 512-instance family) and write the cache")
     ap.add_argument("--out", default=DEFAULT_CACHE)
-    ap.add_argument("--parts", default="sweep,batched,ttd,slab",
+    ap.add_argument("--parts", default="sweep,batched,ttd,slab,precision",
                     help="sweep, batched, ttd (the time-to-DOS family: 1,000 learned-family instances, R = 16, "
-                         "complex64), slab (the quantum-dot slabs at R = 32, lattice-sweep shapes), comma separated")
+                         "complex64), slab (the quantum-dot slabs at R = 32, lattice-sweep shapes), precision "
+                         "(128 x 128 x 64 in both dtypes at R = 32, lattice-sweep shapes), comma separated")
     ap.add_argument("--widths", default="1,2,4,8,16,32,64")
     args = ap.parse_args(argv)
     import numpy as np
@@ -380,6 +382,18 @@ def main(argv=None) -> int:
     if "slab" in parts:
         for L in SLABS:
             H = K.build_hamiltonian(L, inputs.quantum_dot_potential(L), periodic=(1, 1, 0), dtype="c128")
+            K.reset_sweep_tuning()
+            default = K.get_sweep_tuning()
+            cands = [default] + [c for c in sweep_candidates(32, True) if c["lattice"] == 2]
+            res = tune_sweep(H, 32, cache, L=L, candidates=cands)
+            print(f"[autotune] {res.key}: {res.seconds * 1e6:.1f} us/sweep with {res.best}", flush=True)
+            cache.save()
+            H.close()
+    if "precision" in parts:
+        L = PRECISION_L
+        pot = inputs.potential(L, PRECISION_GAMMA, 0)
+        for dt in ("c128", "c64"):
+            H = K.build_hamiltonian(L, pot, dtype=dt)
             K.reset_sweep_tuning()
             default = K.get_sweep_tuning()
             cands = [default] + [c for c in sweep_candidates(32, True) if c["lattice"] == 2]
