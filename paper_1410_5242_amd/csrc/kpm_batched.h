@@ -367,6 +367,9 @@ batched_kernel(const BatchInst* __restrict__ insts, const int32_t* __restrict__ 
             for (unsigned i = threadIdx.x; i < n16; i += 64 * WAVES)
                 Words<4>::store(Words<4>::load(src, 16 * i), dst, 16 * i);
         }
+        // every wave gathers rows of nu_0 that other waves copied: the whole
+        // block must be stored before the first sweep reads it
+        __syncthreads();
 
         // matrix rows of the pass starting at row r0 (values, then column
         // indices); lanes past the end of a part fetch words that are never read

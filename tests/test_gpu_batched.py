@@ -158,6 +158,26 @@ def test_batched_same_handle_repeated_and_many_instances():
         assert np.abs(mu[i] - refs[p]).max() <= TOL_C128
 
 
+def test_batched_first_sweep_sees_the_copied_start_block():
+    # each workgroup copies nu_0 into its work block before the first sweep,
+    # and every wave then gathers rows another wave copied; the work blocks
+    # still hold a previous batch of another layout
+    K = kpm()
+    say("batched start-block copy")
+    try:
+        K.set_batch_tuning(waves=16, wg_per_cu=1, dynamic=1)
+        run(make_batch(SHAPES, 4, "c64", seed0=30), 32)
+        batch = make_batch(SHAPES, 8, "c64", seed0=40)
+        refs = [O.kpm_moments(x["Ho"], x["a"], x["b"], x["v0"], 40) for x in batch]
+        for _ in range(3):
+            mu = run(batch, 40)
+            for i, ref in enumerate(refs):
+                assert np.abs(mu[i] - ref).max() <= TOL_C64, i
+            run(make_batch(SHAPES[:3], 16, "c64", seed0=50), 32)
+    finally:
+        K.reset_batch_tuning()
+
+
 def test_batched_graph_replay():
     # replays interleaved with eager work; each replay must equal the eager
     # result, and a replay must see new contents of the same start blocks
