@@ -300,10 +300,15 @@ kpm_status kpm_moment_features(const double* mu, int32_t n_inst, int32_t R, int3
  *                vector block and the matrix to stay below 4 GiB (otherwise
  *                the scalar-operand sweep runs).
  *   tile_order   lattice sweep: how pencils are dealt to the 8 dies: 0
- *                (default) each die a 2-D block of tiles (so that most edge
- *                rows a tile gathers belong to tiles of its own die, in its
- *                own L2), 1 each die a contiguous run of tile rows, 2 no die
- *                mapping.  Only the work distribution changes.
+ *                each die a 2-D block of tiles (so that most edge rows a
+ *                tile gathers belong to tiles of its own die, in its own
+ *                L2), 1 each die a contiguous run of tile rows, 2 no die
+ *                mapping (pencils dealt round-robin to all workgroups), 3
+ *                (default) 2 when there are more pencils than workgroups,
+ *                else 0 (measured: 2 is 1-12 % faster on 128 x 128 x 64 and
+ *                on 100 x 100 x 40 and 200 x 100 x 40 slabs; at one pencil
+ *                per workgroup, as on 64^3, 0 is as fast or faster).  Only the
+ *                work distribution changes.
  *   slab         staged-gather sweep at R <= 16: the passes walk the lattice
  *                in blocks of this many y-lines, each block plane by plane,
  *                so that the rows gathered for z neighbours were touched a

@@ -179,9 +179,13 @@ hipError_t profiled(hipStream_t s, Launch&& launch) {
 // generic gather kernel otherwise.
 hipError_t launch_any_sweep(kpm_hamiltonian* H, int R, int variant, const SweepArgs& a, hipStream_t s) {
     if (use_lattice(H, R)) {
+        // tile order 3 (auto): round-robin when the workgroups take several
+        // pencils each, the per-die 2-D blocks otherwise
+        int order = get_tuning().tile_order;
+        if (order == 3) order = lattice_tiles(H) > a.grid ? 2 : 0;
         LatticeArgs la{H->val, a.V, a.W, a.alpha, a.beta, a.gamma, a.partials,
                        {H->L[0], H->L[1], H->L[2]}, {H->periodic[0], H->periodic[1], H->periodic[2]}, a.grid,
-                       get_tuning().prefetch, get_tuning().stream, get_tuning().tile_order, R};
+                       get_tuning().prefetch, get_tuning().stream, order, R};
         return profiled(s, [&] { return launch_lattice(H->dtype, variant, la, s); });
     }
     return profiled(s, [&] { return launch_sweep(H->dtype, R, variant, a, s); });
@@ -772,7 +776,7 @@ kpm_status kpm_set_sweep_tuning(const kpm_sweep_tuning* t) {
     }
     if (t->wg_per_cu < 0 || t->xcd_ways < 0 || t->chunk_tiles < 0 || t->pencil < 0 || t->dynamic < 0 ||
         t->prefetch < 0 || t->prefetch > 2 || t->stream < 0 || t->stream > 3 || t->lattice < 0 || t->lattice > 2 ||
-        t->gather < 0 || t->gather > 2 || t->tile_order < 0 || t->tile_order > 2 || t->slab < 0)
+        t->gather < 0 || t->gather > 2 || t->tile_order < 0 || t->tile_order > 3 || t->slab < 0)
         return fail(KPM_EINVAL, "tuning fields must be >= 0");
     if (t->wg_per_cu > 64 || t->xcd_ways > 64 || t->chunk_tiles > (1 << 20))
         return fail(KPM_EINVAL, "tuning field out of range");

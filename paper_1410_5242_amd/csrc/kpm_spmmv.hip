@@ -77,7 +77,7 @@ check_moments_kernel(const double* __restrict__ mu, int R, int M, int* __restric
 }  // namespace
 
 namespace {
-kpm_sweep_tuning g_tuning = {0, kXcds, 8, 16, 0, 2, 3, 1, 1, 0, 4};
+kpm_sweep_tuning g_tuning = {0, kXcds, 8, 16, 0, 2, 3, 1, 1, 3, 4};
 }
 
 kpm_sweep_tuning get_tuning() { return g_tuning; }

@@ -449,7 +449,7 @@ def moment_features(mu: torch.Tensor, n_mom: int, extra: torch.Tensor | None = N
 
 def set_sweep_tuning(wg_per_cu: int = 0, xcd_ways: int = 8, chunk_tiles: int = 8, pencil: int = 16,
                      dynamic: int = 0, prefetch: int = 2, stream: int = 3, lattice: int = 1, gather: int = 1,
-                     tile_order: int = 0, slab: int = 4):
+                     tile_order: int = 3, slab: int = 4):
     """kpm_set_sweep_tuning: launch shape and site order of the sweep kernel (process-wide)."""
     _check(lib().kpm_set_sweep_tuning(ctypes.byref(SweepTuning(wg_per_cu, xcd_ways, chunk_tiles, pencil,
                                                                dynamic, prefetch, stream, lattice, gather,

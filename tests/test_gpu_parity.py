@@ -550,7 +550,7 @@ def test_gather_slab_order_matches_oracle(slab, R):
     assert np.abs(mu - ref).max() <= TOL_C128
 
 
-@pytest.mark.parametrize("order", [0, 1, 2])
+@pytest.mark.parametrize("order", [0, 1, 2, 3])
 @pytest.mark.parametrize("L", [(8, 16, 5), (16, 16, 3)])
 def test_lattice_tile_orders_match_oracle(order, L):
     # 2-D tile blocks per die, runs of tile rows, or no die mapping: same moments
