@@ -76,3 +76,18 @@ def test_lanczos_bounds_converge_and_rescale():
     with pytest.raises(K.KPMError):
         K.lanczos_bounds(H, 1, 0)
     H.close()
+
+
+def test_lanczos_edge_cases():
+    # two steps (a 2 x 2 tridiagonal matrix) and an open lattice in complex64
+    K = kpm()
+    L, per = (5, 4, 3), (0, 1, 0)
+    pot = inputs.potential(L, 1.0, 4)
+    Ho = O.ti_hamiltonian(L, pot, periodic=per)
+    for dtype, steps, tol in (("c128", 2, 1e-12), ("c64", 40, 1e-4)):
+        H = K.build_hamiltonian(L, pot, periodic=per, dtype=dtype)
+        lo, hi = K.lanczos_bounds(H, steps, 5)
+        H.close()
+        rlo, rhi = O.tridiagonal_extremes(*O.lanczos(Ho, O.phase_block_counter(Ho.n, 1, 5)[:, 0], steps))
+        assert abs(lo - rlo) <= tol * 8 and abs(hi - rhi) <= tol * 8
+        assert lo < hi

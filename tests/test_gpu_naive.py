@@ -102,3 +102,25 @@ def test_naive_moments_match_oracle(L, periodic, R, M, dtype):
     H.close()
     assert np.abs(mu - ref).max() <= (TOL_C128 if dtype == "c128" else TOL_C64)
     assert np.abs(mu - fused).max() <= (1e-13 if dtype == "c128" else 1e-5)
+
+
+def test_naive_edge_cases():
+    # minimal M (the initialisation only), the widest block, empty BLAS-1 calls
+    K = kpm()
+    L = (3, 4, 3)
+    pot = inputs.potential(L, 1.0, 2)
+    Ho = O.ti_hamiltonian(L, pot, periodic=(1, 1, 0))
+    a, b = O.scaling(*O.gershgorin(Ho))
+    H = K.build_hamiltonian(L, pot, periodic=(1, 1, 0))
+    for R, M in ((1, 2), (64, 6)):
+        v0 = inputs.phase_block(Ho.n, R, R)
+        mu = K.moments_naive(H, torch.from_numpy(v0).cuda(), M).cpu().numpy()
+        assert np.abs(mu - O.kpm_moments(Ho, a, b, v0, M)).max() <= TOL_C128
+    H.close()
+    e = torch.empty(0, dtype=torch.complex128, device="cuda")
+    K.axpy(2.0, e, e)
+    K.scal(2.0, e)
+    assert np.array_equal(K.dot(e, e).cpu().numpy(), [0.0, 0.0])
+    with pytest.raises(K.KPMError):
+        K.moments_naive(K.build_hamiltonian(L, pot, periodic=(1, 1, 0)), torch.from_numpy(
+            inputs.phase_block(Ho.n, 3, 0)).cuda(), 8)   # R = 3 is not a supported block width

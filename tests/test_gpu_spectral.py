@@ -114,3 +114,17 @@ def test_clean_spectral_function_matches_bloch_bands():
         for o in range(4):
             assert np.abs(mu[i, o] - Tn @ (np.abs(U[o]) ** 2)).max() <= TOL_C128, (k, o)
     H.close()
+
+
+def test_start_blocks_with_64_columns():
+    K = kpm()
+    L = (4, 4, 2)
+    N = 4 * 32
+    rows = list(range(0, 128, 2))
+    assert np.array_equal(K.site_block(N, rows).cpu().numpy(), O.site_block(N, rows))
+    ks = [(0.1 * i, -0.05 * i, 0.2) for i in range(64)]
+    orbs = [i % 4 for i in range(64)]
+    got = K.plane_wave_block(L, ks, orbs).cpu().numpy()
+    assert np.abs(got - O.plane_wave_block(L, ks, orbs)).max() <= 1e-15
+    with pytest.raises(K.KPMError):
+        K.site_block(N, list(range(65)))
