@@ -188,12 +188,14 @@ __device__ inline Nb xy_neighbour(int nx, int ny, int Lx, int Ly, int px, int py
 //   2  scalar loads, with the site's rows pulled into L2 by a vector load a
 //      step ahead (the scalar loads then wait on L2, not on HBM)
 
-// NSL: 32-column slices per block row (0: run-time value nsl, for R > 32)
-template <typename T, int VARIANT, int VALS, int STREAM, int NSL>
+// NSL: 32-column slices per block row (0: run-time value nsl, for R > 32).
+// SPLIT: pencils are cut into npc z-pieces (run-time npc); otherwise a work
+// item is a whole pencil.
+template <typename T, int VARIANT, int VALS, int STREAM, int NSL, bool SPLIT>
 __global__ void __launch_bounds__(kThreadsL)
 lattice_kernel(const T* __restrict__ val, const T* __restrict__ V, T* __restrict__ W,
                T alpha, T beta, T gamma, double* __restrict__ partials,
-               int Lx, int Ly, int Lz, int px, int py, int pz, int ntx, int ntiles, int order, int nsl) {
+               int Lx, int Ly, int Lz, int px, int py, int pz, int ntx, int ntiles, int order, int nsl, int npc) {
     __shared__ T ring[4][kNW][4][kE];
     __shared__ T zrow[4][kE];          // rows of zeros: neighbours beyond an open side
     __shared__ double red[kNW][3][kR];
@@ -240,13 +242,17 @@ lattice_kernel(const T* __restrict__ val, const T* __restrict__ V, T* __restrict
     const int xcd = blockIdx.x % X;
     const int slot = blockIdx.x / X;
     const int per = ngrid / X;
-    const int k_lo = static_cast<int>(static_cast<int64_t>(ntiles) * xcd / X);
-    const int k_hi = static_cast<int>(static_cast<int64_t>(ntiles) * (xcd + 1) / X);
+    // work items: npc consecutive z-pieces of every pencil (npc = 1: whole
+    // pencils)
+    const int npieces = SPLIT ? npc : 1;
+    const int nitems = ntiles * npieces;
+    const int k_lo = static_cast<int>(static_cast<int64_t>(nitems) * xcd / X);
+    const int k_hi = static_cast<int>(static_cast<int64_t>(nitems) * (xcd + 1) / X);
     const int nty = ntiles / ntx;
     // order 0: each die takes a 2-D block of (ntx/2) x (nty/4) tiles, so that
     // most tiles whose edge rows it gathers are its own; order 1: each die
     // takes a contiguous run of tile rows; order 2: no die mapping
-    const bool blocks = order == 0 && X == kXcds && ntx % 2 == 0 && nty % 4 == 0;
+    const bool blocks = order == 0 && X == kXcds && ntx % 2 == 0 && nty % 4 == 0 && !SPLIT;
 
     constexpr bool VEC_VALS = VALS == 1;
     unsigned sink = 0;   // keeps the L2 warm-up loads of VALS == 2
@@ -258,7 +264,11 @@ lattice_kernel(const T* __restrict__ val, const T* __restrict__ V, T* __restrict
     double acc_e = 0.0, acc_or = 0.0, acc_oi = 0.0;
 
     for (int k = k_lo + slot; k < k_hi; k += per) {
-        int tx = k % ntx, ty = k / ntx;
+        const int tile = SPLIT ? k / npieces : k;
+        const int piece = SPLIT ? k - tile * npieces : 0;
+        const int z0 = SPLIT ? piece * Lz / npieces : 0;               // planes [z0, z1) of this item
+        const int z1 = SPLIT ? (piece + 1) * Lz / npieces : Lz;
+        int tx = tile % ntx, ty = tile / ntx;
         if (blocks) {
             const int bw = ntx / 2, bh = nty / 4, i = k - k_lo;
             tx = (xcd % 2) * bw + i % bw;
@@ -352,7 +362,7 @@ lattice_kernel(const T* __restrict__ val, const T* __restrict__ V, T* __restrict
         // Loads are issued warm-up first, then the plane, then the rest, so
         // the waits at the end of the step leave the later loads in flight.
         auto step = [&](int s, StepRegs<T>& cur, StepRegs<T>& nxt) {
-            const bool on1 = s + 1 < Lz;                       // step s + 1 exists
+            const bool on1 = s + 1 < z1;                       // step s + 1 exists
             const int zn2 = on1 ? plane_of(s + 2) : -1;        // plane used by step s + 1
             T p[4];
             if constexpr (VALS == 2)
@@ -450,32 +460,32 @@ lattice_kernel(const T* __restrict__ val, const T* __restrict__ V, T* __restrict
             __syncthreads();
         };
 
-        // prologue: planes -1, 0, 1 into ring slots 3, 0, 1 (zeros where a
-        // plane does not exist); halo, old W and matrix rows of step 0
+        // prologue: planes z0 - 1, z0, z0 + 1 into their ring slots (zeros
+        // where a plane does not exist); halo, old W and matrix rows of step z0
         {
             T q[3][4];
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
-                const int zp = plane_of(i - 1);
+                const int zp = plane_of(z0 + i - 1);
                 load_plane(zp >= 0, zp, q[i]);
             }
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
 #pragma unroll
-                for (int o = 0; o < 4; ++o) ring[(i + 3) & 3][wave][o][lane] = q[i][o];
+                for (int o = 0; o < 4; ++o) ring[(z0 + i + 3) & 3][wave][o][lane] = q[i][o];
             }
         }
         StepRegs<T> ra, rb;
-        load_step(true, 0, ra);
-        load_wold(true, 0, ra);
+        load_step(true, z0, ra);
+        load_wold(true, z0, ra);
         __syncthreads();
 
-        int s = 0;
-        for (; s + 1 < Lz; s += 2) {
+        int s = z0;
+        for (; s + 1 < z1; s += 2) {
             step(s, ra, rb);
             step(s + 1, rb, ra);
         }
-        if (s < Lz) step(s, ra, rb);
+        if (s < z1) step(s, ra, rb);
     }
 
     // this slice's columns of the workgroup's [3][R] partial sums
@@ -502,22 +512,39 @@ lattice_kernel(const T* __restrict__ val, const T* __restrict__ V, T* __restrict
     asm volatile("" ::"s"(sink));
 }
 
+// z-pieces per pencil: 2 when more pencils than workgroups leave the last
+// round of pencils partly empty and halving the pencils shortens the longest
+// workgroup's work (rounds x (planes + 2 steps of pipeline fill)), else 1
+int pieces(int ntiles, int grid, int Lz) {
+    if (grid <= 0 || ntiles <= grid || Lz < 8) return 1;
+    auto cost = [&](int p) {
+        const int64_t rounds = (static_cast<int64_t>(ntiles) * p + grid - 1) / grid;
+        return rounds * (Lz / p + 2);
+    };
+    return cost(2) < cost(1) ? 2 : 1;
+}
+
 template <typename T, int STREAM>
 hipError_t launch_ts(int variant, const LatticeArgs& a, hipStream_t s) {
     const int ntx = (a.L[0] + kP - 1) / kP, nty = (a.L[1] + kP - 1) / kP;
     const int ntiles = ntx * nty;
-#define KPM_LAUNCH(VAR, VALS, NSL)                                                               \
-    lattice_kernel<T, VAR, VALS, STREAM, NSL><<<a.grid, kThreadsL, 0, s>>>(                      \
+    // pencils are split only at R = 32 on the record path (prefetch 2)
+    const int npc = (a.R == kR && a.prefetch == 2) ? pieces(ntiles, a.grid, a.L[2]) : 1;
+#define KPM_LAUNCH(VAR, VALS, NSL) KPM_LAUNCH_S(VAR, VALS, NSL, false)
+#define KPM_LAUNCH_S(VAR, VALS, NSL, SPLIT)                                                      \
+    lattice_kernel<T, VAR, VALS, STREAM, NSL, SPLIT><<<a.grid, kThreadsL, 0, s>>>(               \
         static_cast<const T*>(a.val), static_cast<const T*>(a.V), static_cast<T*>(a.W),          \
         static_cast<T>(a.alpha), static_cast<T>(a.beta), static_cast<T>(a.gamma), a.partials,  \
         a.L[0], a.L[1], a.L[2], a.periodic[0], a.periodic[1], a.periodic[2], ntx, ntiles, a.order, \
-        a.R / kR)
+        a.R / kR, npc)
 // tuning `prefetch`: 2 (default) the site's matrix record a step ahead in
 // registers (VALS 1), 1 scalar loads after an L2 warm-up (VALS 2), 0 plain
 // scalar loads.  Blocks wider than 32 columns always take the record path.
 #define KPM_LAUNCH_V(VAR)                          \
     if (a.R > kR) {                                \
         KPM_LAUNCH(VAR, 1, 0);                     \
+    } else if (npc > 1) {                          \
+        KPM_LAUNCH_S(VAR, 1, 1, true);             \
     } else {                                       \
         switch (a.prefetch) {                      \
         case 2: KPM_LAUNCH(VAR, 1, 1); break;      \
@@ -533,6 +560,7 @@ hipError_t launch_ts(int variant, const LatticeArgs& a, hipStream_t s) {
     default: return hipErrorInvalidValue;
     }
 #undef KPM_LAUNCH_V
+#undef KPM_LAUNCH_S
 #undef KPM_LAUNCH
     return hipGetLastError();
 }

@@ -302,6 +302,40 @@ def test_quantum_dot_slab_matches_oracle(lattice):
     assert np.abs(mu - ref).max() <= TOL_C128
 
 
+@pytest.mark.parametrize("pz", [1, 0])
+def test_lattice_pencils_split_in_z_match_oracle(pz):
+    # 17 x 16 = 272 pencils of 9 planes on 256 workgroups: the launch cuts
+    # every pencil into two z-pieces (planes 0-3 and 4-8), each with its own
+    # prologue; periodic and open z
+    K = kpm()
+    L, per, M, R = (68, 64, 9), (1, 1, pz), 16, 32
+    say("split pencils, pz", pz)
+    pot = inputs.potential(L, 1.0, 6)
+    Ho = O.ti_hamiltonian(L, pot, periodic=per)
+    a, b = O.scaling(*O.gershgorin(Ho))
+    v0 = inputs.phase_block(Ho.n, R, 7)
+    ref = O.kpm_moments(Ho, a, b, v0, M)
+    try:
+        K.set_sweep_tuning(lattice=2, wg_per_cu=1)
+        H = K.build_hamiltonian(L, pot, periodic=per)
+        assert K.sweep_kernel(H, R) == "lattice_kernel"
+        H.close()
+        mu, _ = gpu_moments(L, pot, v0, M, periodic=per)
+        # the same sweep without the split (prefetch 1 never splits pencils)
+        K.set_sweep_tuning(lattice=2, wg_per_cu=1, prefetch=1)
+        whole, _ = gpu_moments(L, pot, v0, M, periodic=per)
+    finally:
+        K.reset_sweep_tuning()
+    # both GPU runs reduce in tree order: they agree to rounding
+    assert np.abs(mu - whole).max() <= 1e-13
+    # against the oracle: its scalar products are running sums of N nearly
+    # equal terms, whose rounding error is bounded by (N - 1) u sum |x_i|
+    # (recursive summation); an even moment combines three such sums
+    tol = max(TOL_C128, 3.0 * Ho.n * 2.0 ** -53)
+    assert np.abs(mu - ref).max() <= tol
+    assert np.abs(mu[:, 1::2] - ref[:, 1::2]).max() <= TOL_C128
+
+
 @pytest.mark.parametrize("L", [(5, 4, 4), (4, 9, 3), (1, 1, 7)])
 def test_lattice_sweep_falls_back_for_one_site_tail_tiles(L):
     # a side with L mod 4 == 1 would leave tiles one site wide: the generic
