@@ -62,7 +62,13 @@ typedef struct {
     int32_t L[3];            /* lattice sides Lx, Ly, Lz (>= 1) */
     int32_t periodic[3];     /* nonzero: periodic along that axis (side must be >= 3) */
     double t;                /* hopping amplitude */
-    const double* potential; /* host [Lx*Ly*Lz] onsite V_n, site n = x + Lx*(y + Ly*z); required */
+    double gamma;            /* disorder strength when potential is NULL (>= 0) */
+    uint64_t seed;           /* generator seed when potential is NULL */
+    const double* potential; /* host [Lx*Ly*Lz] onsite V_n, site n = x + Lx*(y + Ly*z), or NULL:
+                                V_n = gamma (u_n - 1/2), u_n = (top 53 bits of SplitMix64 output) / 2^53
+                                at counter n, state key + (n + 1) * 0x9E3779B97F4A7C15,
+                                key = mix(seed + 2 * 0x9E3779B97F4A7C15) (the second output of
+                                SplitMix64 seeded with `seed`; kpm_random_phase_block uses the first) */
     int32_t dtype;           /* kpm_dtype */
     double margin;           /* half-width factor applied to the Gershgorin interval (e.g. 1.01) */
     int32_t fixed_scale;     /* nonzero: use a, b below instead of the Gershgorin bound */
@@ -81,8 +87,11 @@ typedef struct kpm_hamiltonian kpm_hamiltonian; /* opaque, library-owned */
  * Description": a and b from Gershgorin's circle theorem) gives
  * b = (E_max + E_min)/2 and a = margin (E_max - E_min)/2, unless
  * desc->fixed_scale.  Synchronises `stream` (the bounds are read back).
- * Errors: KPM_EINVAL (null desc/potential/out, side <= 0, non-finite
- * potential or t, margin < 1, a <= 0), KPM_ENOTSUP (a periodic side < 3),
+ * The storage is row-major with 13 slots per row: the lattice rows all have
+ * the same length, so the SELL-C-sigma format of the paper's section
+ * "Testbed and Implementation" reduces to chunk height 1 without sorting.
+ * Errors: KPM_EINVAL (null desc/out, side <= 0, non-finite potential, t or
+ * gamma, gamma < 0, margin < 1, a <= 0), KPM_ENOTSUP (a periodic side < 3),
  * KPM_ENOMEM, KPM_EDEVICE.  *out is NULL on error. */
 kpm_status kpm_build_hamiltonian(const kpm_lattice_desc* desc, void* stream,
                                  kpm_hamiltonian** out);
@@ -114,21 +123,39 @@ kpm_status kpm_aug_spmmv(const kpm_hamiltonian* H, const void* V, void* W, int32
                          double alpha, double beta, double gamma, int32_t variant,
                          double* eta, void* stream);
 
+/* Options of kpm_moments.  A NULL opts pointer means all fields zero.
+ * (struct kpm_sweep_tuning is defined with kpm_set_sweep_tuning below.) */
+struct kpm_sweep_tuning;
+typedef struct {
+    int32_t check;       /* nonzero: synchronise `stream` and return KPM_ESPECTRUM when a moment is
+                            non-finite or |mu_n| > mu_0 (1 + 1e-6) */
+    int32_t use_graph;   /* nonzero: the launch sequence (copy of V0, the M/2 sweeps, the reductions
+                            and eta -> mu) is captured once in a HIP graph and replayed by later calls
+                            on the same stream with the same H, V0, R, M, mu, eta_out, variant,
+                            scaling and tuning (any change captures again) */
+    int32_t variant;     /* KPM_FULL (moments), or KPM_NODOT: the same M/2 sweeps of the recurrence
+                            without the scalar products, for timing; mu is then not written */
+    int32_t mu_on_host;  /* nonzero: mu is host memory (the call synchronises `stream`) */
+    const struct kpm_sweep_tuning* tuning;   /* launch shape for this call only (NULL: the process-wide
+                                         kpm_set_sweep_tuning setting, read once at entry) */
+    double* eta_out;     /* optional device [M][R] complex double: the raw products eta_n */
+} kpm_run_opts;
+
 /* Chebyshev moments for R start vectors (eq. "eq:kpm_iter", scalar products
  * eta_{2m} = <nu_m|nu_m>, eta_{2m+1} = <nu_{m+1}|nu_m>, blocked algorithm):
  * M/2 fused sweeps on the device give eta_0 .. eta_{M-1}, then
  *   mu_0 = eta_0, mu_1 = Re eta_1, mu_{2m} = 2 eta_{2m} - mu_0,
  *   mu_{2m+1} = 2 Re eta_{2m+1} - mu_1      (per start vector r).
- * V0: device [N][R] block in H's dtype (read-only).  mu: device [R][M]
- * double.  eta_out: optional device [M][R] complex double (raw products).
- * M even and >= 2, R in {1, 2, 4, 8, 16, 32, 64}.
- * If `check` is nonzero the call synchronises `stream` and returns
- * KPM_ESPECTRUM when a moment is non-finite or |mu_n| > mu_0 (1 + 1e-6)
- * (|<v|T_n(Htilde)|v>| <= <v|v> holds whenever the spectrum of Htilde lies in
- * [-1, 1]).  Workspaces (two blocks and the partial sums) are cached on H.
+ * V0: device [N][R] block in H's dtype (read-only).  mu: [R][M] double,
+ * device (or host with opts->mu_on_host).  M even and >= 2, R in {1, 2, 4,
+ * 8, 16, 32, 64}.  (|<v|T_n(Htilde)|v>| <= <v|v> holds whenever the
+ * spectrum of Htilde lies in [-1, 1], which the check tests.)
+ * Workspaces (two blocks, the partial sums, the graph) are cached on H per
+ * stream: calls on one stream reuse them in order, calls on different
+ * streams (also from different threads) use separate sets and may overlap.
  * Errors: KPM_EINVAL, KPM_ENOTSUP, KPM_ENOMEM, KPM_ESPECTRUM, KPM_EDEVICE. */
-kpm_status kpm_moments(const kpm_hamiltonian* H, const void* V0, int32_t R, int32_t M,
-                       double* mu, double* eta_out, int32_t check, void* stream);
+kpm_status kpm_moments(const kpm_hamiltonian* H, const void* V0, int32_t R, int32_t M, double* mu,
+                       const kpm_run_opts* opts, void* stream);
 
 /* The naive KPM-DOS algorithm (Alg. "kpm_naive"), for measuring what the
  * fused and blocked sweeps save (Table "kpm_analysis": 13 N S_d vector bytes
@@ -153,9 +180,10 @@ kpm_status kpm_moments_naive(const kpm_hamiltonian* H, const void* V0, int32_t R
  *   kpm_dot:  out[0] + i out[1] = sum_i conj(x_i) y_i, accumulated in FP64
  *             (out: device, 2 doubles; x == y gives the squared norm with
  *             out[1] = 0).  The sum is reduced in a fixed order through a
- *             32 KiB partials buffer per device, allocated on the first call
- *             and held until the process ends; calls that overlap on one
- *             device (other streams, other threads) share it and race.
+ *             32 KiB partials buffer per (device, stream), allocated on the
+ *             first call on that stream and held until the process ends:
+ *             calls on one stream reuse it in order, calls on different
+ *             streams (or threads using different streams) do not share it.
  * Errors: KPM_EINVAL (dtype, n < 0, NULL or misaligned vector). */
 kpm_status kpm_axpy(int32_t dtype, int64_t n, double alpha, const void* x, void* y, void* stream);
 kpm_status kpm_scal(int32_t dtype, int64_t n, double alpha, void* x, void* stream);
@@ -187,7 +215,7 @@ kpm_status kpm_dos(const double* mu, int32_t R, int32_t M, int32_t kernel, doubl
 kpm_status kpm_random_phase_block(void* V, int64_t N, int32_t R, int32_t dtype, uint64_t seed, void* stream);
 
 /* Spectral bounds from `steps` Lanczos steps (section "Problem Description":
- * a, b from Gershgorin's theorem or a few Lanczos sweeps).  Starting from
+ * a, b from Gershgorin's theorem or from Lanczos iterations).  Starting from
  * the random-phase unit vector of kpm_random_phase_block(seed, R = 1), the
  * recurrence w = H q_j - alpha_j q_j - beta_{j-1} q_{j-1}, alpha_j =
  * Re <q_j|H q_j>, beta_j = |w|, q_{j+1} = w / beta_j runs on the device
@@ -243,8 +271,11 @@ kpm_status kpm_dos_batched(const double* mu, int32_t n_inst, int32_t R, int32_t 
 kpm_status kpm_moment_features(const double* mu, int32_t n_inst, int32_t R, int32_t ld, int32_t n_mom,
                                const float* extra, float* x, void* stream);
 
-/* Launch shape of the fused sweep kernel (process-wide, not thread-safe;
- * results do not depend on it beyond the order of floating-point sums):
+/* Launch shape of the fused sweep kernel (process-wide, guarded by a lock:
+ * every call reads it once at entry, so a change from another thread takes
+ * effect from the next call on; kpm_run_opts.tuning overrides it for one
+ * kpm_moments call).  Results do not depend on it beyond the order of
+ * floating-point sums:
  *   wg_per_cu    workgroups per compute unit in the persistent grid; 0
  *                selects 8 for the scalar-operand sweep (4-wave workgroups,
  *                32 resident waves per CU) and 16 waves per CU for the
@@ -318,7 +349,7 @@ kpm_status kpm_moment_features(const double* mu, int32_t n_inst, int32_t R, int3
  *                default 4
  * kpm_set_sweep_tuning(NULL) restores the defaults.  Errors: KPM_EINVAL
  * (negative field). */
-typedef struct {
+typedef struct kpm_sweep_tuning {
     int32_t wg_per_cu;
     int32_t xcd_ways;
     int32_t chunk_tiles;
@@ -340,15 +371,31 @@ kpm_status kpm_get_sweep_tuning(kpm_sweep_tuning* tuning);
  * Errors: KPM_EINVAL. */
 kpm_status kpm_sweep_kernel(const kpm_hamiltonian* H, int32_t R, int32_t* kernel);
 
+/* The launch a sweep of H at block width R gets under `tuning` (NULL: the
+ * process-wide setting): kernel as kpm_sweep_kernel; grid = workgroups;
+ * tile_order = the lattice sweep's pencil-to-die mapping after resolving
+ * the automatic choice (0 2-D blocks per die, 1 runs of tile rows, 2
+ * round-robin; -1 for the other kernels); pieces = z-pieces per pencil
+ * (1 = whole pencils; -1 for the other kernels); halves = 32-column passes
+ * of the lattice sweep over the block (-1 for the other kernels).
+ * Errors: KPM_EINVAL. */
+typedef struct {
+    int32_t kernel, grid, tile_order, pieces, halves;
+} kpm_sweep_plan_info;
+kpm_status kpm_sweep_plan(const kpm_hamiltonian* H, int32_t R, const struct kpm_sweep_tuning* tuning,
+                          kpm_sweep_plan_info* out);
+
 /* Sweep-kernel timing for measurement tools.  kpm_sweep_profile_enable(n),
- * n > 0 (process-wide, not thread-safe): every n-th fused sweep launched by
+ * n > 0 (process-wide, guarded by a lock): every n-th fused sweep launched by
  * kpm_moments and kpm_aug_spmmv from then on (the first, the (n+1)-th, ...)
  * is bracketed by a pair of HIP events on its own stream; each pair costs a
  * few microseconds of stream time, so sampling (n > 1) keeps a timed run
  * close to an untimed one.  n = 0 turns it off.  kpm_sweep_profile_read
  * waits for the recorded events, returns the count, total, minimum and
  * maximum kernel time in milliseconds of the timed launches (any output may
- * be NULL) and clears the record.  Errors: KPM_EINVAL (n < 0), KPM_EDEVICE. */
+ * be NULL) and clears the record.  Sweeps captured into a HIP graph
+ * (kpm_run_opts.use_graph) are not timed.  Errors: KPM_EINVAL (n < 0),
+ * KPM_EDEVICE. */
 kpm_status kpm_sweep_profile_enable(int32_t enable);
 kpm_status kpm_sweep_profile_read(int64_t* count, double* total_ms, double* min_ms, double* max_ms);
 
@@ -377,14 +424,16 @@ kpm_status kpm_sweep_profile_read(int64_t* count, double* total_ms, double* min_
  * same handles, start blocks, mu, R, M and tuning, replays it instead of
  * re-uploading the instance table.
  * Workspaces (two blocks per instance, the per-sweep products, the instance
- * table) are library-owned, one set per device, shared by all calls: the
- * call is not thread-safe, and calls on different streams must not overlap.
+ * table, the graph) are library-owned, one set per (device, stream): calls
+ * on one stream reuse them in order, calls on different streams (also from
+ * different threads) use separate sets and may overlap.
  * Errors: KPM_EINVAL, KPM_ENOTSUP, KPM_ENOMEM, KPM_ESPECTRUM, KPM_EDEVICE. */
 enum { KPM_BATCH_CHECK = 1, KPM_BATCH_GRAPH = 2 };
 kpm_status kpm_moments_batched(const kpm_hamiltonian* const* H, const void* const* V0, int32_t n_inst,
                                int32_t R, int32_t M, double* mu, int32_t flags, void* stream);
 
-/* Launch shape of the batched solver (process-wide, not thread-safe):
+/* Launch shape of the batched solver (process-wide, guarded by a lock and
+ * read once per call):
  *   waves      waves per workgroup (4, 8 or 16, capped by what the
  *              workgroup's LDS and registers allow: 16 in complex64, 8 in
  *              complex128, fewer for R <= 2); 0 = 8 (or the cap if lower).
@@ -457,6 +506,20 @@ kpm_status kpm_mlp_train_step(kpm_mlp* net, const float* x, const float* p, cons
  * trans_b), all device; not both transposed. */
 kpm_status kpm_mlp_gemm_bf16(const uint16_t* A, const uint16_t* B, int32_t M, int32_t N, int32_t K, int32_t trans_a,
                              int32_t trans_b, float* C, void* stream);
+
+/* Attainable-bandwidth reference for the roofline (the paper bounds every
+ * kernel by a measured copy bandwidth b, Table "tab:architectures" and eq.
+ * "eq:roofline_mem"): STREAM-style kernels over `bytes` (a multiple of 16)
+ * of 16-byte-aligned device arrays,
+ *   KPM_STREAM_COPY:   c = a              (traffic 2 x bytes)
+ *   KPM_STREAM_TRIAD:  c = a + scalar b   (FP64 elements; traffic 3 x bytes)
+ * with wg_per_cu workgroups of 256 threads per compute unit (1 .. 32), each
+ * thread keeping four 16-byte loads in flight, and non-temporal stores when
+ * `nontemporal` is nonzero.  c must not overlap a or b; b is unused by copy.
+ * Errors: KPM_EINVAL. */
+enum { KPM_STREAM_COPY = 0, KPM_STREAM_TRIAD = 1 };
+kpm_status kpm_stream(int32_t kind, void* c, const void* a, const void* b, double scalar, int64_t bytes,
+                      int32_t wg_per_cu, int32_t nontemporal, void* stream);
 
 /* Thread-local message for the last failing call on this thread ("" if none). */
 const char* kpm_last_error(void);

@@ -6,10 +6,10 @@ with the GPU library (``paper_1410_5242_amd``) and never imports it.
 
 The heavy loops (Hamiltonian construction, Chebyshev recurrence, scalar
 products) live in ``kpm_oracle.c`` (plain C, double complex, CRS).  This
-module wraps them with ctypes and adds the small steps that the paper calls
-"computationally inexpensive": the moment doubling identity, the damping
-kernels and the density-of-states reconstruction, plus the dense brute-force
-and closed-form references used to pin the oracle.
+module wraps them with ctypes and adds the cheap steps that turn moments into
+a spectrum (section "Problem Description"): the moment doubling identity, the
+damping kernels and the density-of-states reconstruction, plus the dense
+brute-force and closed-form references used to pin the oracle.
 """
 from __future__ import annotations
 
@@ -48,6 +48,10 @@ def lib():
         L.oracle_splitmix64_next.argtypes = [p]
         L.oracle_phase_block.restype = None
         L.oracle_phase_block.argtypes = [ctypes.c_int64, ctypes.c_int, ctypes.c_uint64, p]
+        L.oracle_potential_counter.restype = None
+        L.oracle_potential_counter.argtypes = [ctypes.c_int64, ctypes.c_double, ctypes.c_uint64, p]
+        L.oracle_block_dot.restype = None
+        L.oracle_block_dot.argtypes = [ctypes.c_int64, ctypes.c_int, p, p, p]
         _LIB = L
     return _LIB
 
@@ -64,6 +68,30 @@ def phase_block_counter(N: int, R: int, seed: int) -> np.ndarray:
     out = np.zeros(2 * N * R, dtype=np.float64)
     lib().oracle_phase_block(int(N), int(R), int(seed) & 0xFFFFFFFFFFFFFFFF, _ptr(out))
     return out.view(np.complex128).reshape(N, R)
+
+
+def potential_counter(L, gamma: float, seed: int) -> np.ndarray:
+    """Site potentials V_n = gamma (u_n - 1/2) from the counter generator (x fastest), for
+    Hamiltonians built without a caller potential (see kpm_oracle.c)."""
+    n = int(L[0]) * int(L[1]) * int(L[2])
+    out = np.zeros(n, dtype=np.float64)
+    lib().oracle_potential_counter(n, float(gamma), int(seed) & 0xFFFFFFFFFFFFFFFF, _ptr(out))
+    return out
+
+
+def block_dot(x: np.ndarray, y: np.ndarray) -> np.ndarray:
+    """Column scalar products <x_r|y_r> = sum_i conj(x_ir) y_ir of two [N][R] blocks, by the
+    pairwise summation the moment recurrence uses (complex [R])."""
+    x = np.ascontiguousarray(x, dtype=np.complex128)
+    y = np.ascontiguousarray(y, dtype=np.complex128)
+    if x.ndim == 1:
+        x, y = x[:, None], y[:, None]
+    if x.shape != y.shape:
+        raise ValueError("blocks differ in shape")
+    N, R = x.shape
+    out = np.zeros(R, dtype=np.complex128)
+    lib().oracle_block_dot(N, R, _ptr(x.view(np.float64)), _ptr(y.view(np.float64)), _ptr(out.view(np.float64)))
+    return out
 
 
 def lib_threads() -> int:
@@ -277,8 +305,8 @@ def dense_moments(Hd: np.ndarray, a: float, b: float, v0: np.ndarray, M: int) ->
 
 
 def lanczos(H: CSR, v0: np.ndarray, steps: int):
-    """Lanczos recurrence (section "Problem Description", bounds from a few Lanczos
-    sweeps) from the start vector v0, without reorthogonalisation:
+    """Lanczos recurrence (section "Problem Description": the scaling may come from
+    Lanczos iterations) from the start vector v0, without reorthogonalisation:
     w = H q_j - alpha_j q_j - beta_{j-1} q_{j-1}, alpha_j = Re <q_j|H q_j>,
     beta_j = |w|, q_{j+1} = w / beta_j.  Returns (alpha [steps], beta [steps])."""
     Hd = H.dense()

@@ -19,7 +19,7 @@ SOURCES = ["kpm_runtime.cpp", "kpm_build.hip", "kpm_spmmv.hip", "kpm_dos.hip",
            "kpm_sweep_c128_large.hip", "kpm_sweep_c128_small.hip",
            "kpm_sweep_c64_large.hip", "kpm_sweep_c64_small.hip", "kpm_lattice.hip",
            "kpm_batched_c64.hip", "kpm_batched_c128.hip", "kpm_mlp.hip", "kpm_start.hip", "kpm_gather_c64.hip", "kpm_gather_c128.hip",
-           "kpm_naive.hip", "kpm_lanczos.hip"]
+           "kpm_naive.hip", "kpm_lanczos.hip", "kpm_stream.hip"]
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -50,16 +50,6 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
     return LIB
-
-
-def asm(src: str = "kpm_sweep_c128_large.hip", out: str | None = None) -> str:
-    """Write the gfx950 assembly of one source (for inspection)."""
-    out = out or os.path.join(OBJ, os.path.splitext(src)[0] + ".s")
-    os.makedirs(OBJ, exist_ok=True)
-    cmd = [HIPCC, *FLAGS, "-x", "hip", "--cuda-device-only", "-S",
-           os.path.join(CSRC, src), "-o", out]
-    subprocess.run(cmd, check=True)
-    return out
 
 
 if __name__ == "__main__":

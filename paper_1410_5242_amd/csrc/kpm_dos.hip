@@ -1,6 +1,6 @@
-// Density-of-states reconstruction from Chebyshev moments: the "second,
-// computationally inexpensive step" that the paper leaves to the KPM
-// literature (section "Problem Description").
+// Density-of-states reconstruction from Chebyshev moments: the cheap
+// follow-up to the moment computation, whose formulas the paper takes from
+// the KPM literature (section "Problem Description").
 //
 //   mubar_n = (1/R) sum_r mu[r][n]            (stochastic trace over R vectors)
 //   c_n     = g_n mubar_n                      (damping kernel)

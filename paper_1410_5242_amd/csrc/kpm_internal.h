@@ -4,7 +4,10 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <map>
+#include <mutex>
 #include <string>
+#include <vector>
 
 #include "../../include/kpm.h"
 
@@ -19,6 +22,9 @@ constexpr int kWidth = 13;
 // to round-robin on gfx950.
 constexpr int kXcds = 8;
 
+// Buffers of the calls on one stream.  Calls enqueued on one stream run in
+// order, so they may reuse these; calls on different streams get different
+// sets (see kpm_hamiltonian::ws).
 struct Workspace {
     void* vbuf[2] = {nullptr, nullptr};   // two [N][R] blocks
     size_t vbytes = 0;
@@ -28,6 +34,8 @@ struct Workspace {
     size_t pbytes = 0;
     double* eta = nullptr;                 // [M][R][2]
     size_t etabytes = 0;
+    double* mu = nullptr;                  // [R][M] device moments for callers with host mu
+    size_t mubytes = 0;
     int* flag = nullptr;                   // spectrum check flag (device)
     int* flag_host = nullptr;              // pinned mirror
     void* naive[3] = {nullptr, nullptr, nullptr};   // v, w, u of the naive algorithm ([N] each)
@@ -35,6 +43,12 @@ struct Workspace {
     double* dot_part = nullptr;            // [naive_dot_partials()][2] scalar-product partials
     double* lanczos = nullptr;             // alpha, beta and scalars of the Lanczos bounds
     size_t lanczos_bytes = 0;
+    // HIP graph of the kpm_moments launch sequence (captured on a private
+    // stream, replayed on this workspace's stream) and what it was made for
+    hipStream_t capture = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<unsigned char> graph_key;
 };
 
 }  // namespace kpm
@@ -47,12 +61,15 @@ struct kpm_hamiltonian {
     int32_t* col = nullptr;         // [N][width]
     int L[3] = {0, 0, 0};           // lattice sides
     int periodic[3] = {0, 0, 0};
-    int32_t* sched = nullptr;       // device [N/4]: sites in processing order (nullptr = natural)
-    int sched_pencil = -1;          // pencil side the schedule was made for
     double a = 1.0, b = 0.0;        // Htilde = (H - b)/a
     double emin = 0.0, emax = 0.0;  // Gershgorin interval
     int device = 0;
-    kpm::Workspace ws;
+    // Guards the two maps below; buffers are only ever added to them (and
+    // released by kpm_destroy_hamiltonian), so a pointer taken under the lock
+    // stays valid while another thread adds entries.
+    std::mutex lock;
+    std::map<hipStream_t, kpm::Workspace*> ws;   // per caller stream
+    std::map<int, int32_t*> sched;              // device [N/4] site schedule per pencil side
 };
 
 namespace kpm {
@@ -105,6 +122,8 @@ struct LatticeArgs {
 bool lattice_supported(const kpm_hamiltonian* H, int R);
 int lattice_tiles(const kpm_hamiltonian* H);
 int lattice_grid(const kpm_hamiltonian* H);
+// z-pieces per pencil the lattice sweep cuts its pencils into at this grid
+int lattice_pieces(const kpm_hamiltonian* H, int R, int grid, int prefetch);
 hipError_t launch_lattice(int dtype, int variant, const LatticeArgs& a, hipStream_t s);
 
 // Unsigned 32-bit division by a divisor fixed on the host: multiply-high by
@@ -199,8 +218,27 @@ hipError_t launch_batched(int dtype, int R, const BatchArgs& a, hipStream_t s);
 int batched_max_waves(int dtype, int R);
 int device_cus();
 
+// Sweep tuning.  get_tuning() returns the running call's snapshot (see
+// TuningScope) or, outside a call, the process-wide setting; set_tuning
+// replaces the process-wide setting (mutex-protected, so calls that run
+// meanwhile on other threads keep the snapshot they started with).
+kpm_sweep_tuning default_tuning();
 kpm_sweep_tuning get_tuning();
 void set_tuning(const kpm_sweep_tuning& t);
+// For the lifetime of the object, get_tuning() on this thread returns
+// *override, or the process-wide setting as it was at construction.
+class TuningScope {
+public:
+    explicit TuningScope(const kpm_sweep_tuning* override);
+    ~TuningScope();
+    TuningScope(const TuningScope&) = delete;
+    TuningScope& operator=(const TuningScope&) = delete;
+private:
+    kpm_sweep_tuning snap_;
+    const kpm_sweep_tuning* prev_;
+};
+// Validation of a tuning record (KPM_OK or KPM_EINVAL with a message).
+kpm_status check_tuning(const kpm_sweep_tuning& t);
 
 // Which generic sweep kernel runs for this dtype / R / N (see kpm_sweep_tuning::gather):
 // true = the staged-gather sweep, false = the scalar-operand sweep.
@@ -222,6 +260,9 @@ hipError_t launch_reduce_partials(const double* partials, int nslots, int grid, 
                                   int sweep0, double* eta, hipStream_t s);
 hipError_t launch_eta_to_mu(const double* eta, int R, int M, double* mu, hipStream_t s);
 hipError_t launch_zero_ints(int* p, int n, hipStream_t s);
+// dst[0 .. bytes) = src[0 .. bytes) (16-byte aligned, bytes a multiple of 16):
+// a kernel rather than a copy node, so that it can sit in a captured graph
+hipError_t launch_copy16(void* dst, const void* src, size_t bytes, hipStream_t s);
 hipError_t launch_check_moments(const double* mu, int R, int M, int* flag, hipStream_t s);
 hipError_t launch_dos(const double* mu, int R, int M, int kernel, double kparam, double a,
                       double b, const double* E, int K, double* rho, hipStream_t s);
@@ -252,6 +293,12 @@ hipError_t launch_site_block(void* V, int64_t N, int R, const int64_t* rows, int
 hipError_t launch_plane_wave_block(void* V, const int L[3], int R, const double* k, const int32_t* orb, int dtype,
                                    hipStream_t s);
 hipError_t launch_phase_block(void* V, int64_t N, int R, int dtype, uint64_t seed, hipStream_t s);
+// Disorder potential V_n = gamma (u_n - 1/2), n < nsite, u_n from the counter
+// generator of launch_phase_block under the second key of the seed.
+hipError_t launch_potential(double* pot, int64_t nsite, double gamma, uint64_t seed, hipStream_t s);
+// STREAM-style copy / triad over `units` 16-byte units (kpm_stream)
+hipError_t launch_stream(int kind, int nontemporal, void* c, const void* a, const void* b, double s, int64_t units,
+                         int wg_per_cu, hipStream_t st);
 hipError_t launch_features(const double* mu, int n_inst, int R, int ld, int n_mom, const float* extra,
                            float* x, hipStream_t s);
 

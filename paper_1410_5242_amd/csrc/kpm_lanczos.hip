@@ -1,6 +1,6 @@
-// Spectral bounds from a few Lanczos steps (section "Problem Description":
-// the scaling a, b may come from Gershgorin's theorem or from a few Lanczos
-// sweeps).  The three-term recurrence
+// Spectral bounds from a short Lanczos run (section "Problem Description":
+// the scaling a, b comes either from Gershgorin's theorem or from Lanczos
+// iterations).  The three-term recurrence
 //   w = H q_j - alpha_j q_j - beta_{j-1} q_{j-1},  alpha_j = <q_j|H q_j>,
 //   beta_j = |w|,  q_{j+1} = w / beta_j
 // runs entirely on the device: alpha and beta stay in device memory and the

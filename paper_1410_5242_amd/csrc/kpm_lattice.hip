@@ -610,6 +610,11 @@ int lattice_grid(const kpm_hamiltonian* H) {
     return g > 0 ? g : 1;
 }
 
+int lattice_pieces(const kpm_hamiltonian* H, int R, int grid, int prefetch) {
+    // as launch_ts: pencils are split only at R = 32 on the record path
+    return (R == lattice::kR && prefetch == 2) ? lattice::pieces(lattice_tiles(H), grid, H->L[2]) : 1;
+}
+
 hipError_t launch_lattice(int dtype, int variant, const LatticeArgs& a, hipStream_t s) {
     if (dtype == KPM_C128) return lattice::launch_t<double>(variant, a, s);
     return lattice::launch_t<float>(variant, a, s);

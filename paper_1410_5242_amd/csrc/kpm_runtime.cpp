@@ -67,14 +67,24 @@ kpm_status grow(P** ptr, size_t* have, size_t need, const char* what) {
     return KPM_OK;
 }
 
-kpm_status ensure_vectors(kpm_hamiltonian* H, int R) {
+// The workspace of H for the calls on stream s (created on first use).
+Workspace* workspace(kpm_hamiltonian* H, hipStream_t s) {
+    std::lock_guard<std::mutex> g(H->lock);
+    auto it = H->ws.find(s);
+    if (it != H->ws.end()) return it->second;
+    Workspace* w = new Workspace();
+    H->ws.emplace(s, w);
+    return w;
+}
+
+kpm_status ensure_vectors(Workspace& w, const kpm_hamiltonian* H, int R) {
     const size_t need = static_cast<size_t>(H->nrows) * 2 * R * real_size(H->dtype);
     for (int i = 0; i < 2; ++i) {
-        size_t have = H->ws.vbytes;
-        kpm_status st = grow(&H->ws.vbuf[i], &have, need, "hipMalloc(vector block)");
+        size_t have = w.vbytes;
+        kpm_status st = grow(&w.vbuf[i], &have, need, "hipMalloc(vector block)");
         if (st != KPM_OK) return st;
     }
-    H->ws.vbytes = need;
+    if (w.vbytes < need) w.vbytes = need;
     return KPM_OK;
 }
 
@@ -97,10 +107,10 @@ int launch_grid(const kpm_hamiltonian* H, int R) {
     return use_lattice(H, R) ? lattice_grid(H) : sweep_grid(H->dtype, R, H->nrows);
 }
 
-kpm_status ensure_partials(kpm_hamiltonian* H, int R, int slots) {
+kpm_status ensure_partials(Workspace& w, const kpm_hamiltonian* H, int R, int slots) {
     const int grid = launch_grid(H, R);
     const size_t need = static_cast<size_t>(slots) * grid * 3 * R * sizeof(double);
-    return grow(&H->ws.partials, &H->ws.pbytes, need, "hipMalloc(partials)");
+    return grow(&w.partials, &w.pbytes, need, "hipMalloc(partials)");
 }
 
 // Sites in processing order: pencils of P x P sites over the full z extent,
@@ -118,37 +128,67 @@ std::vector<int32_t> pencil_schedule(const int L[3], int P) {
     return s;
 }
 
-// Make H's processing schedule match the current tuning.
-kpm_status ensure_schedule(kpm_hamiltonian* H) {
+// H's site schedule for the current tuning's pencil side (nullptr: natural
+// order); schedules are built once per side and kept until H is destroyed.
+kpm_status schedule_for(kpm_hamiltonian* H, const int32_t** out) {
+    *out = nullptr;
     const int P = get_tuning().pencil;
-    if (P == H->sched_pencil) return KPM_OK;
-    if (H->sched) {
-        KPM_HIP(hipFree(H->sched), "hipFree");
-        H->sched = nullptr;
-    }
-    H->sched_pencil = P;
     if (P <= 0) return KPM_OK;
+    std::lock_guard<std::mutex> g(H->lock);
+    auto it = H->sched.find(P);
+    if (it != H->sched.end()) {
+        *out = it->second;
+        return KPM_OK;
+    }
     std::vector<int32_t> s = pencil_schedule(H->L, P);
     if (static_cast<int64_t>(s.size()) * 4 != H->nrows) return fail(KPM_EINTERNAL, "schedule size mismatch");
-    KPM_HIP(hipMalloc(&H->sched, s.size() * sizeof(int32_t)), "hipMalloc(schedule)");
-    KPM_HIP(hipMemcpy(H->sched, s.data(), s.size() * sizeof(int32_t), hipMemcpyHostToDevice), "copy schedule");
+    int32_t* d = nullptr;
+    KPM_HIP(hipMalloc(&d, s.size() * sizeof(int32_t)), "hipMalloc(schedule)");
+    const hipError_t e = hipMemcpy(d, s.data(), s.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(d);
+        return hip_fail(e, "copy schedule");
+    }
+    H->sched.emplace(P, d);
+    *out = d;
     return KPM_OK;
 }
 
-kpm_status ensure_queue(kpm_hamiltonian* H) {
-    return grow(&H->ws.queue, &H->ws.qbytes, static_cast<size_t>(kReduceEvery) * kXcds * sizeof(int),
-                "hipMalloc(queue)");
+kpm_status ensure_queue(Workspace& w) {
+    return grow(&w.queue, &w.qbytes, static_cast<size_t>(kReduceEvery) * kXcds * sizeof(int), "hipMalloc(queue)");
 }
 
-kpm_status ensure_flag(kpm_hamiltonian* H) {
-    if (!H->ws.flag) KPM_HIP(hipMalloc(&H->ws.flag, sizeof(int)), "hipMalloc(flag)");
-    if (!H->ws.flag_host) KPM_HIP(hipHostMalloc(&H->ws.flag_host, sizeof(int)), "hipHostMalloc(flag)");
+kpm_status ensure_flag(Workspace& w) {
+    if (!w.flag) KPM_HIP(hipMalloc(&w.flag, sizeof(int)), "hipMalloc(flag)");
+    if (!w.flag_host) KPM_HIP(hipHostMalloc(&w.flag_host, sizeof(int)), "hipHostMalloc(flag)");
     return KPM_OK;
+}
+
+void free_workspace(Workspace* w) {
+    if (!w) return;
+    for (int i = 0; i < 2; ++i)
+        if (w->vbuf[i]) (void)hipFree(w->vbuf[i]);
+    if (w->partials) (void)hipFree(w->partials);
+    if (w->queue) (void)hipFree(w->queue);
+    if (w->eta) (void)hipFree(w->eta);
+    if (w->mu) (void)hipFree(w->mu);
+    if (w->flag) (void)hipFree(w->flag);
+    if (w->flag_host) (void)hipHostFree(w->flag_host);
+    for (int i = 0; i < 3; ++i)
+        if (w->naive[i]) (void)hipFree(w->naive[i]);
+    if (w->dot_part) (void)hipFree(w->dot_part);
+    if (w->lanczos) (void)hipFree(w->lanczos);
+    if (w->exec) (void)hipGraphExecDestroy(w->exec);
+    if (w->graph) (void)hipGraphDestroy(w->graph);
+    if (w->capture) (void)hipStreamDestroy(w->capture);
+    delete w;
 }
 
 // Event pairs around sweep launches (kpm_sweep_profile_*): every period-th
-// launch is timed (0: off).
+// launch is timed (0: off).  Guarded by `lock`; events are created once and
+// reused after each read.
 struct SweepProfile {
+    std::mutex lock;
     int period = 0;
     uint64_t seen = 0;
     std::vector<hipEvent_t> start, stop;
@@ -156,9 +196,17 @@ struct SweepProfile {
 };
 SweepProfile g_prof;
 
+// Launch through `launch`, bracketed by an event pair when the profile picks
+// this launch.  `capturing`: the launch is being recorded into a graph,
+// where no events are recorded.
 template <class Launch>
-hipError_t profiled(hipStream_t s, Launch&& launch) {
-    if (g_prof.period <= 0 || (g_prof.seen++ % static_cast<uint64_t>(g_prof.period)) != 0) return launch();
+hipError_t profiled(hipStream_t s, bool capturing, Launch&& launch) {
+    if (capturing) return launch();
+    std::unique_lock<std::mutex> g(g_prof.lock);
+    if (g_prof.period <= 0 || (g_prof.seen++ % static_cast<uint64_t>(g_prof.period)) != 0) {
+        g.unlock();
+        return launch();
+    }
     if (g_prof.used == g_prof.start.size()) {
         hipEvent_t e0, e1;
         hipError_t e = hipEventCreate(&e0);
@@ -167,32 +215,38 @@ hipError_t profiled(hipStream_t s, Launch&& launch) {
         g_prof.start.push_back(e0);
         g_prof.stop.push_back(e1);
     }
-    hipError_t e = hipEventRecord(g_prof.start[g_prof.used], s);
+    const size_t k = g_prof.used++;
+    hipError_t e = hipEventRecord(g_prof.start[k], s);
     if (e != hipSuccess) return e;
     if ((e = launch()) != hipSuccess) return e;
-    if ((e = hipEventRecord(g_prof.stop[g_prof.used], s)) != hipSuccess) return e;
-    ++g_prof.used;
-    return hipSuccess;
+    return hipEventRecord(g_prof.stop[k], s);
+}
+
+// Tile order the lattice sweep uses: tuning 3 (auto) is round-robin when
+// the workgroups take several pencils each, the per-die 2-D blocks otherwise
+int lattice_order(const kpm_hamiltonian* H, int grid) {
+    const int order = get_tuning().tile_order;
+    return order == 3 ? (lattice_tiles(H) > grid ? 2 : 0) : order;
 }
 
 // One fused sweep: the cache-blocked lattice kernel where it applies, the
 // generic gather kernel otherwise.
-hipError_t launch_any_sweep(kpm_hamiltonian* H, int R, int variant, const SweepArgs& a, hipStream_t s) {
+hipError_t launch_any_sweep(kpm_hamiltonian* H, int R, int variant, const SweepArgs& a, hipStream_t s,
+                            bool capturing = false) {
     if (use_lattice(H, R)) {
-        // tile order 3 (auto): round-robin when the workgroups take several
-        // pencils each, the per-die 2-D blocks otherwise
-        int order = get_tuning().tile_order;
-        if (order == 3) order = lattice_tiles(H) > a.grid ? 2 : 0;
+        const kpm_sweep_tuning t = get_tuning();
         LatticeArgs la{H->val, a.V, a.W, a.alpha, a.beta, a.gamma, a.partials,
                        {H->L[0], H->L[1], H->L[2]}, {H->periodic[0], H->periodic[1], H->periodic[2]}, a.grid,
-                       get_tuning().prefetch, get_tuning().stream, order, R};
-        return profiled(s, [&] { return launch_lattice(H->dtype, variant, la, s); });
+                       t.prefetch, t.stream, lattice_order(H, a.grid), R};
+        return profiled(s, capturing, [&] { return launch_lattice(H->dtype, variant, la, s); });
     }
-    return profiled(s, [&] { return launch_sweep(H->dtype, R, variant, a, s); });
+    return profiled(s, capturing, [&] { return launch_sweep(H->dtype, R, variant, a, s); });
 }
 
-// ---- batched solver: process-wide state, one set per device ----
-kpm_batch_tuning g_batch_tuning = {0, 0, 1, 4};
+// ---- batched solver: launch shape (process-wide) and state per (device, stream) ----
+constexpr kpm_batch_tuning kDefaultBatchTuning = {0, 0, 1, 4};
+std::mutex g_batch_lock;   // guards g_batch_tuning and the g_batch map (not the states in it)
+kpm_batch_tuning g_batch_tuning = kDefaultBatchTuning;
 
 struct BatchState {
     BatchInst* inst = nullptr;          // device instance table
@@ -213,7 +267,22 @@ struct BatchState {
     std::vector<int32_t> key_order;
     int key_dtype = -1, key_R = 0, key_M = 0, key_grid = 0, key_waves = 0, key_dynamic = -1, key_slab = -1;
 };
-std::vector<BatchState> g_batch;
+// One state per (device, stream): calls on one stream run in order and may
+// reuse it.  States are never freed before the process ends, so a pointer
+// taken under g_batch_lock stays valid.
+std::map<std::pair<int, hipStream_t>, BatchState*> g_batch;
+
+BatchState* batch_state(int dev, hipStream_t s) {
+    std::lock_guard<std::mutex> g(g_batch_lock);
+    BatchState*& b = g_batch[{dev, s}];
+    if (!b) b = new BatchState();
+    return b;
+}
+
+kpm_batch_tuning batch_tuning() {
+    std::lock_guard<std::mutex> g(g_batch_lock);
+    return g_batch_tuning;
+}
 
 void drop_graph(BatchState& b) {
     if (b.exec) (void)hipGraphExecDestroy(b.exec);
@@ -230,6 +299,19 @@ bool same_inst(const BatchInst& x, const BatchInst& y) {
            x.L[1] == y.L[1] && x.L[2] == y.L[2];
 }
 
+template <typename X>
+void key_add(std::vector<unsigned char>& k, const X& x) {
+    const auto* p = reinterpret_cast<const unsigned char*>(&x);
+    k.insert(k.end(), p, p + sizeof(X));
+}
+
+void drop_moments_graph(Workspace& w) {
+    if (w.exec) (void)hipGraphExecDestroy(w.exec);
+    if (w.graph) (void)hipGraphDestroy(w.graph);
+    w.exec = nullptr;
+    w.graph = nullptr;
+    w.graph_key.clear();
+}
 }  // namespace
 
 void set_error(const std::string& msg) { g_error = msg; }
@@ -249,7 +331,8 @@ kpm_status kpm_build_hamiltonian(const kpm_lattice_desc* d, void* stream, kpm_ha
     if (!out) return fail(KPM_EINVAL, "out is NULL");
     *out = nullptr;
     if (!d) return fail(KPM_EINVAL, "desc is NULL");
-    if (!d->potential) return fail(KPM_EINVAL, "potential is NULL");
+    if (!d->potential && (!std::isfinite(d->gamma) || d->gamma < 0.0))
+        return fail(KPM_EINVAL, "gamma must be finite and >= 0 when no potential is given");
     for (int j = 0; j < 3; ++j) {
         if (d->L[j] <= 0) return fail(KPM_EINVAL, "lattice side <= 0");
         if (d->periodic[j] && d->L[j] < 3)
@@ -265,8 +348,9 @@ kpm_status kpm_build_hamiltonian(const kpm_lattice_desc* d, void* stream, kpm_ha
     }
     const int64_t nsite = static_cast<int64_t>(d->L[0]) * d->L[1] * d->L[2];
     if (nsite > (INT32_MAX / 4)) return fail(KPM_ENOMEM, "lattice too large for int32 column indices");
-    for (int64_t i = 0; i < nsite; ++i)
-        if (!std::isfinite(d->potential[i])) return fail(KPM_EINVAL, "potential has a non-finite value");
+    if (d->potential)
+        for (int64_t i = 0; i < nsite; ++i)
+            if (!std::isfinite(d->potential[i])) return fail(KPM_EINVAL, "potential has a non-finite value");
 
     auto* H = new kpm_hamiltonian();
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -294,8 +378,11 @@ kpm_status kpm_build_hamiltonian(const kpm_lattice_desc* d, void* stream, kpm_ha
     else if ((e = hipMalloc(&pot_dev, nsite * sizeof(double))) != hipSuccess) st = hip_fail(e, "hipMalloc(potential)");
     else if ((e = hipMalloc(&bb, static_cast<size_t>(nblocks) * 2 * sizeof(double))) != hipSuccess) st = hip_fail(e, "hipMalloc(bounds)");
     else if ((e = hipMalloc(&bounds, 2 * sizeof(double))) != hipSuccess) st = hip_fail(e, "hipMalloc(bounds)");
-    else if ((e = hipMemcpyAsync(pot_dev, d->potential, nsite * sizeof(double), hipMemcpyHostToDevice, s)) != hipSuccess)
+    else if (d->potential &&
+             (e = hipMemcpyAsync(pot_dev, d->potential, nsite * sizeof(double), hipMemcpyHostToDevice, s)) != hipSuccess)
         st = hip_fail(e, "copy potential");
+    else if (!d->potential && (e = launch_potential(pot_dev, nsite, d->gamma, d->seed, s)) != hipSuccess)
+        st = hip_fail(e, "potential kernel");
     else if ((e = launch_build_ti(d->L[0], d->L[1], d->L[2], d->periodic, d->t, pot_dev, H->dtype, H->val,
                                   H->col, bb, nblocks, bounds, s)) != hipSuccess)
         st = hip_fail(e, "build kernel");
@@ -382,18 +469,8 @@ void kpm_destroy_hamiltonian(kpm_hamiltonian* H) {
     (void)hipDeviceSynchronize();
     if (H->val) (void)hipFree(H->val);
     if (H->col) (void)hipFree(H->col);
-    for (int i = 0; i < 2; ++i)
-        if (H->ws.vbuf[i]) (void)hipFree(H->ws.vbuf[i]);
-    if (H->ws.partials) (void)hipFree(H->ws.partials);
-    if (H->ws.queue) (void)hipFree(H->ws.queue);
-    if (H->sched) (void)hipFree(H->sched);
-    if (H->ws.eta) (void)hipFree(H->ws.eta);
-    if (H->ws.flag) (void)hipFree(H->ws.flag);
-    if (H->ws.flag_host) (void)hipHostFree(H->ws.flag_host);
-    for (int i = 0; i < 3; ++i)
-        if (H->ws.naive[i]) (void)hipFree(H->ws.naive[i]);
-    if (H->ws.dot_part) (void)hipFree(H->ws.dot_part);
-    if (H->ws.lanczos) (void)hipFree(H->ws.lanczos);
+    for (auto& kv : H->ws) free_workspace(kv.second);
+    for (auto& kv : H->sched) (void)hipFree(kv.second);
     delete H;
 }
 
@@ -413,84 +490,145 @@ kpm_status kpm_aug_spmmv(const kpm_hamiltonian* Hc, const void* V, void* W, int3
     const char* v0 = static_cast<const char*>(V);
     const char* w0 = static_cast<const char*>(W);
     if (v0 < w0 + bytes && w0 < v0 + bytes) return fail(KPM_EINVAL, "V and W overlap");
+    TuningScope scope(nullptr);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if ((st = ensure_schedule(H)) != KPM_OK) return st;
+    Workspace& w = *workspace(H, s);
+    const int32_t* sched = nullptr;
+    if ((st = schedule_for(H, &sched)) != KPM_OK) return st;
     const bool dots = (variant == KPM_FULL && eta != nullptr);
     if (dots) {
-        st = ensure_partials(H, R, 1);
+        st = ensure_partials(w, H, R, 1);
         if (st != KPM_OK) return st;
     }
-    if ((st = ensure_queue(H)) != KPM_OK) return st;
-    if (sweep_uses_queue(H, R)) KPM_HIP(launch_zero_ints(H->ws.queue, kXcds, s), "zero kernel");
-    SweepArgs a{H->val, H->col, H->nrows, V, W, H->sched, alpha, beta, gamma,
-                dots ? H->ws.partials : nullptr, launch_grid(H, R)};
-    a.queue = H->ws.queue;
+    if ((st = ensure_queue(w)) != KPM_OK) return st;
+    if (sweep_uses_queue(H, R)) KPM_HIP(launch_zero_ints(w.queue, kXcds, s), "zero kernel");
+    SweepArgs a{H->val, H->col, H->nrows, V, W, sched, alpha, beta, gamma,
+                dots ? w.partials : nullptr, launch_grid(H, R)};
+    a.queue = w.queue;
     for (int j = 0; j < 3; ++j) a.L[j] = H->L[j];
     const int launch_variant = (variant == KPM_FULL && !dots) ? KPM_NODOT : variant;
     KPM_HIP(launch_any_sweep(H, R, launch_variant, a, s), "sweep kernel");
-    if (dots) KPM_HIP(launch_reduce_partials(H->ws.partials, 1, a.grid, R, 0, eta, s), "reduce kernel");
+    if (dots) KPM_HIP(launch_reduce_partials(w.partials, 1, a.grid, R, 0, eta, s), "reduce kernel");
     return KPM_OK;
 }
 
 kpm_status kpm_moments(const kpm_hamiltonian* Hc, const void* V0, int32_t R, int32_t M, double* mu,
-                       double* eta_out, int32_t check, void* stream) {
+                       const kpm_run_opts* opts_in, void* stream) {
     g_error.clear();
-    if (!Hc || !V0 || !mu) return fail(KPM_EINVAL, "H, V0 or mu is NULL");
+    const kpm_run_opts opts = opts_in ? *opts_in : kpm_run_opts{};
+    if (!Hc || !V0) return fail(KPM_EINVAL, "H or V0 is NULL");
+    if (opts.variant != KPM_FULL && opts.variant != KPM_NODOT)
+        return fail(KPM_EINVAL, "kpm_moments runs the FULL or the NODOT variant");
+    const bool full = opts.variant == KPM_FULL;
+    if (full && !mu) return fail(KPM_EINVAL, "mu is NULL");
     if (!r_supported(R)) return fail(KPM_ENOTSUP, "R must be one of 1, 2, 4, 8, 16, 32, 64");
     if (M < 2 || (M % 2) != 0) return fail(KPM_EINVAL, "M must be even and >= 2");
+    if (reinterpret_cast<uintptr_t>(V0) % 16 != 0) return fail(KPM_EINVAL, "V0 must be 16-byte aligned");
+    kpm_status st;
+    if (opts.tuning && (st = check_tuning(*opts.tuning)) != KPM_OK) return st;
     auto* H = const_cast<kpm_hamiltonian*>(Hc);
-    kpm_status st = check_device(H);
-    if (st != KPM_OK) return st;
+    if ((st = check_device(H)) != KPM_OK) return st;
+    TuningScope scope(opts.tuning);
     hipStream_t s = static_cast<hipStream_t>(stream);
+    Workspace& w = *workspace(H, s);
     const int sweeps = M / 2;
     const int slots = sweeps < kReduceEvery ? sweeps : kReduceEvery;
-    if ((st = ensure_vectors(H, R)) != KPM_OK) return st;
-    if ((st = ensure_schedule(H)) != KPM_OK) return st;
-    if ((st = ensure_partials(H, R, slots)) != KPM_OK) return st;
-    if ((st = ensure_queue(H)) != KPM_OK) return st;
-    double* eta = eta_out;
-    if (!eta) {
-        if ((st = grow(&H->ws.eta, &H->ws.etabytes, static_cast<size_t>(M) * R * 2 * sizeof(double),
-                       "hipMalloc(eta)")) != KPM_OK)
+    const int32_t* sched = nullptr;
+    if ((st = ensure_vectors(w, H, R)) != KPM_OK) return st;
+    if ((st = schedule_for(H, &sched)) != KPM_OK) return st;
+    if (full && (st = ensure_partials(w, H, R, slots)) != KPM_OK) return st;
+    if ((st = ensure_queue(w)) != KPM_OK) return st;
+    double* eta = opts.eta_out;
+    if (full && !eta) {
+        if ((st = grow(&w.eta, &w.etabytes, static_cast<size_t>(M) * R * 2 * sizeof(double), "hipMalloc(eta)")) !=
+            KPM_OK)
             return st;
-        eta = H->ws.eta;
+        eta = w.eta;
     }
+    double* mu_dev = mu;
+    if (full && opts.mu_on_host) {
+        if ((st = grow(&w.mu, &w.mubytes, static_cast<size_t>(M) * R * sizeof(double), "hipMalloc(mu)")) != KPM_OK)
+            return st;
+        mu_dev = w.mu;
+    }
+    if (full && opts.check && (st = ensure_flag(w)) != KPM_OK) return st;
     const int grid = launch_grid(H, R);
     const size_t slot_elems = static_cast<size_t>(grid) * 3 * R;
     const size_t bytes = static_cast<size_t>(H->nrows) * 2 * R * real_size(H->dtype);
-    void* A = H->ws.vbuf[0];
-    void* B = H->ws.vbuf[1];
-    // nu_0 -> A (the caller's block stays untouched)
-    KPM_HIP(hipMemcpyAsync(A, V0, bytes, hipMemcpyDeviceToDevice, s), "copy V0");
-    const double inv_a = 1.0 / H->a;
-    for (int k = 0; k < sweeps; ++k) {
-        const int sl = k % kReduceEvery;
-        if (sl == 0)   // tile counters of the next kReduceEvery sweeps
-            KPM_HIP(launch_zero_ints(H->ws.queue, kReduceEvery * kXcds, s), "zero kernel");
-        SweepArgs a{H->val, H->col, H->nrows, nullptr, nullptr, H->sched, 0.0, 0.0, 0.0,
-                    H->ws.partials + sl * slot_elems, grid};
-        a.queue = H->ws.queue + sl * kXcds;
-        for (int j = 0; j < 3; ++j) a.L[j] = H->L[j];
-        if (k == 0) {
-            // nu_1 = Htilde nu_0 = (1/a) H nu_0 - (b/a) nu_0
-            a.V = A; a.W = B; a.alpha = inv_a; a.beta = -H->b * inv_a; a.gamma = 0.0;
-        } else {
-            // swap roles: V = nu_k, W = nu_{k-1} -> nu_{k+1} = 2 Htilde nu_k - nu_{k-1}
-            if (k % 2 == 1) { a.V = B; a.W = A; } else { a.V = A; a.W = B; }
-            a.alpha = 2.0 * inv_a; a.beta = -2.0 * H->b * inv_a; a.gamma = -1.0;
+    void* A = w.vbuf[0];
+    void* B = w.vbuf[1];
+    const double inv_a = 1.0 / H->a, b = H->b;
+    const int variant = opts.variant;
+
+    // the launch sequence of one call, on stream q
+    auto enqueue = [&](hipStream_t q, bool capturing) -> kpm_status {
+        // nu_0 -> A (the caller's block stays untouched)
+        KPM_HIP(launch_copy16(A, V0, bytes, q), "copy V0");
+        for (int k = 0; k < sweeps; ++k) {
+            const int sl = k % kReduceEvery;
+            if (sl == 0)   // tile counters of the next kReduceEvery sweeps
+                KPM_HIP(launch_zero_ints(w.queue, kReduceEvery * kXcds, q), "zero kernel");
+            SweepArgs a{H->val, H->col, H->nrows, nullptr, nullptr, sched, 0.0, 0.0, 0.0,
+                        full ? w.partials + sl * slot_elems : nullptr, grid};
+            a.queue = w.queue + sl * kXcds;
+            for (int j = 0; j < 3; ++j) a.L[j] = H->L[j];
+            if (k == 0) {
+                // nu_1 = Htilde nu_0 = (1/a) H nu_0 - (b/a) nu_0
+                a.V = A; a.W = B; a.alpha = inv_a; a.beta = -b * inv_a; a.gamma = 0.0;
+            } else {
+                // swap roles: V = nu_k, W = nu_{k-1} -> nu_{k+1} = 2 Htilde nu_k - nu_{k-1}
+                if (k % 2 == 1) { a.V = B; a.W = A; } else { a.V = A; a.W = B; }
+                a.alpha = 2.0 * inv_a; a.beta = -2.0 * b * inv_a; a.gamma = -1.0;
+            }
+            KPM_HIP(launch_any_sweep(H, R, variant, a, q, capturing), "sweep kernel");
+            if (full && (sl == kReduceEvery - 1 || k == sweeps - 1))
+                KPM_HIP(launch_reduce_partials(w.partials, sl + 1, grid, R, k - sl, eta, q), "reduce kernel");
         }
-        KPM_HIP(launch_any_sweep(H, R, KPM_FULL, a, s), "sweep kernel");
-        if (sl == kReduceEvery - 1 || k == sweeps - 1)
-            KPM_HIP(launch_reduce_partials(H->ws.partials, sl + 1, grid, R, k - sl, eta, s), "reduce kernel");
+        if (full) KPM_HIP(launch_eta_to_mu(eta, R, M, mu_dev, q), "eta_to_mu kernel");
+        return KPM_OK;
+    };
+
+    if (opts.use_graph) {
+        std::vector<unsigned char> key;
+        const kpm_sweep_tuning t = get_tuning();
+        key_add(key, V0); key_add(key, mu_dev); key_add(key, eta); key_add(key, R); key_add(key, M);
+        key_add(key, H->a); key_add(key, H->b); key_add(key, variant); key_add(key, t); key_add(key, grid);
+        key_add(key, A); key_add(key, B); key_add(key, w.partials); key_add(key, w.queue); key_add(key, sched);
+        if (!w.exec || w.graph_key != key) {
+            drop_moments_graph(w);
+            if (!w.capture) KPM_HIP(hipStreamCreateWithFlags(&w.capture, hipStreamNonBlocking), "hipStreamCreate");
+            KPM_HIP(hipStreamBeginCapture(w.capture, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+            const kpm_status se = enqueue(w.capture, true);
+            hipGraph_t g = nullptr;
+            const hipError_t ee = hipStreamEndCapture(w.capture, &g);
+            if (se != KPM_OK) {
+                if (g) (void)hipGraphDestroy(g);
+                return se;
+            }
+            if (ee != hipSuccess) return hip_fail(ee, "hipStreamEndCapture");
+            w.graph = g;
+            const hipError_t ei = hipGraphInstantiate(&w.exec, w.graph, nullptr, nullptr, 0);
+            if (ei != hipSuccess) {
+                drop_moments_graph(w);
+                return hip_fail(ei, "hipGraphInstantiate");
+            }
+            w.graph_key = key;
+        }
+        KPM_HIP(hipGraphLaunch(w.exec, s), "hipGraphLaunch");
+    } else if ((st = enqueue(s, false)) != KPM_OK) {
+        return st;
     }
-    KPM_HIP(launch_eta_to_mu(eta, R, M, mu, s), "eta_to_mu kernel");
-    if (check) {
-        if ((st = ensure_flag(H)) != KPM_OK) return st;
-        KPM_HIP(launch_check_moments(mu, R, M, H->ws.flag, s), "check kernel");
-        KPM_HIP(hipMemcpyAsync(H->ws.flag_host, H->ws.flag, sizeof(int), hipMemcpyDeviceToHost, s), "copy flag");
+    if (full && opts.check) {
+        KPM_HIP(launch_check_moments(mu_dev, R, M, w.flag, s), "check kernel");
+        KPM_HIP(hipMemcpyAsync(w.flag_host, w.flag, sizeof(int), hipMemcpyDeviceToHost, s), "copy flag");
         KPM_HIP(hipStreamSynchronize(s), "synchronise");
-        if (*H->ws.flag_host)
+        if (*w.flag_host)
             return fail(KPM_ESPECTRUM, "moments left [-mu_0, mu_0]: the scaled spectrum is not inside [-1, 1]");
+    }
+    if (full && opts.mu_on_host) {
+        KPM_HIP(hipMemcpyAsync(mu, mu_dev, static_cast<size_t>(M) * R * sizeof(double), hipMemcpyDeviceToHost, s),
+                "copy mu");
+        KPM_HIP(hipStreamSynchronize(s), "synchronise");
     }
     return KPM_OK;
 }
@@ -504,66 +642,69 @@ kpm_status kpm_moments_naive(const kpm_hamiltonian* Hc, const void* V0, int32_t 
     auto* H = const_cast<kpm_hamiltonian*>(Hc);
     kpm_status st = check_device(H);
     if (st != KPM_OK) return st;
+    TuningScope scope(nullptr);
     hipStream_t s = static_cast<hipStream_t>(stream);
+    Workspace& ws = *workspace(H, s);
+    const int32_t* sched = nullptr;
+    if ((st = schedule_for(H, &sched)) != KPM_OK) return st;
     const int64_t N = H->nrows;
     const size_t vb = static_cast<size_t>(N) * 2 * real_size(H->dtype);
     for (int i = 0; i < 3; ++i) {
-        size_t have = H->ws.naive_bytes;
-        if ((st = grow(&H->ws.naive[i], &have, vb, "hipMalloc(naive vector)")) != KPM_OK) return st;
+        size_t have = ws.naive_bytes;
+        if ((st = grow(&ws.naive[i], &have, vb, "hipMalloc(naive vector)")) != KPM_OK) return st;
     }
-    H->ws.naive_bytes = vb;
-    if (!H->ws.dot_part)
-        KPM_HIP(hipMalloc(&H->ws.dot_part, static_cast<size_t>(naive_dot_partials()) * 2 * sizeof(double)),
+    ws.naive_bytes = vb;
+    if (!ws.dot_part)
+        KPM_HIP(hipMalloc(&ws.dot_part, static_cast<size_t>(naive_dot_partials()) * 2 * sizeof(double)),
                 "hipMalloc(dot partials)");
-    if ((st = grow(&H->ws.eta, &H->ws.etabytes, static_cast<size_t>(M) * R * 2 * sizeof(double), "hipMalloc(eta)")) !=
+    if ((st = grow(&ws.eta, &ws.etabytes, static_cast<size_t>(M) * R * 2 * sizeof(double), "hipMalloc(eta)")) !=
         KPM_OK)
         return st;
-    double* eta = H->ws.eta;   // [M][R][2]
+    double* eta = ws.eta;   // [M][R][2]
     const int dt = H->dtype;
     const double inv_a = 1.0 / H->a, b = H->b;
     // one SpMV: u <- H v (the plain sweep at R = 1, which applies H unscaled)
     auto spmv = [&](const void* v, void* u) -> hipError_t {
-        SweepArgs a{H->val, H->col, N, v, u, H->sched, 1.0, 0.0, 0.0, nullptr, launch_grid(H, 1)};
-        a.queue = H->ws.queue;
+        SweepArgs a{H->val, H->col, N, v, u, sched, 1.0, 0.0, 0.0, nullptr, launch_grid(H, 1)};
+        a.queue = ws.queue;
         for (int j = 0; j < 3; ++j) a.L[j] = H->L[j];
         if (sweep_uses_queue(H, 1)) {
-            const hipError_t e = launch_zero_ints(H->ws.queue, kXcds, s);
+            const hipError_t e = launch_zero_ints(ws.queue, kXcds, s);
             if (e != hipSuccess) return e;
         }
         return launch_any_sweep(H, 1, KPM_PLAIN, a, s);
     };
     auto eta_at = [&](int n, int r) { return eta + (static_cast<int64_t>(n) * R + r) * 2; };
-    if ((st = ensure_queue(H)) != KPM_OK) return st;
-    if ((st = ensure_schedule(H)) != KPM_OK) return st;
+    if ((st = ensure_queue(ws)) != KPM_OK) return st;
     // the stochastic trace as an outer loop over the R start vectors
     for (int r = 0; r < R; ++r) {
-        void* v = H->ws.naive[0];
-        void* w = H->ws.naive[1];
-        void* u = H->ws.naive[2];
+        void* v = ws.naive[0];
+        void* w = ws.naive[1];
+        void* u = ws.naive[2];
         KPM_HIP(launch_column(dt, N, R, r, V0, v, s), "column kernel");
         // initialisation: w = nu_1 = (H v - b v) / a; eta_0 = <v|v>, eta_1 = <w|v>
         KPM_HIP(spmv(v, w), "spmv");
         KPM_HIP(launch_axpy(dt, N, -b, v, w, s), "axpy kernel");
         KPM_HIP(launch_scal(dt, N, inv_a, w, s), "scal kernel");
-        KPM_HIP(launch_dot(dt, N, v, v, H->ws.dot_part, eta_at(0, r), s), "nrm2 kernel");
-        KPM_HIP(launch_dot(dt, N, w, v, H->ws.dot_part, eta_at(1, r), s), "dot kernel");
+        KPM_HIP(launch_dot(dt, N, v, v, ws.dot_part, eta_at(0, r), s), "nrm2 kernel");
+        KPM_HIP(launch_dot(dt, N, w, v, ws.dot_part, eta_at(1, r), s), "dot kernel");
         for (int m = 1; m < M / 2; ++m) {
             std::swap(v, w);   // v = nu_m, w = nu_{m-1}
             KPM_HIP(spmv(v, u), "spmv");
             KPM_HIP(launch_axpy(dt, N, -b, v, u, s), "axpy kernel");
             KPM_HIP(launch_scal(dt, N, -1.0, w, s), "scal kernel");
             KPM_HIP(launch_axpy(dt, N, 2.0 * inv_a, u, w, s), "axpy kernel");
-            KPM_HIP(launch_dot(dt, N, v, v, H->ws.dot_part, eta_at(2 * m, r), s), "nrm2 kernel");
-            KPM_HIP(launch_dot(dt, N, w, v, H->ws.dot_part, eta_at(2 * m + 1, r), s), "dot kernel");
+            KPM_HIP(launch_dot(dt, N, v, v, ws.dot_part, eta_at(2 * m, r), s), "nrm2 kernel");
+            KPM_HIP(launch_dot(dt, N, w, v, ws.dot_part, eta_at(2 * m + 1, r), s), "dot kernel");
         }
     }
     KPM_HIP(launch_eta_to_mu(eta, R, M, mu, s), "eta_to_mu kernel");
     if (check) {
-        if ((st = ensure_flag(H)) != KPM_OK) return st;
-        KPM_HIP(launch_check_moments(mu, R, M, H->ws.flag, s), "check kernel");
-        KPM_HIP(hipMemcpyAsync(H->ws.flag_host, H->ws.flag, sizeof(int), hipMemcpyDeviceToHost, s), "copy flag");
+        if ((st = ensure_flag(ws)) != KPM_OK) return st;
+        KPM_HIP(launch_check_moments(mu, R, M, ws.flag, s), "check kernel");
+        KPM_HIP(hipMemcpyAsync(ws.flag_host, ws.flag, sizeof(int), hipMemcpyDeviceToHost, s), "copy flag");
         KPM_HIP(hipStreamSynchronize(s), "synchronise");
-        if (*H->ws.flag_host)
+        if (*ws.flag_host)
             return fail(KPM_ESPECTRUM, "moments left [-mu_0, mu_0]: the scaled spectrum is not inside [-1, 1]");
     }
     return KPM_OK;
@@ -577,32 +718,35 @@ kpm_status kpm_lanczos_bounds(const kpm_hamiltonian* Hc, int32_t steps, uint64_t
     auto* H = const_cast<kpm_hamiltonian*>(Hc);
     kpm_status st = check_device(H);
     if (st != KPM_OK) return st;
+    TuningScope scope(nullptr);
     hipStream_t s = static_cast<hipStream_t>(stream);
+    Workspace& ws = *workspace(H, s);
+    const int32_t* sched = nullptr;
+    if ((st = schedule_for(H, &sched)) != KPM_OK) return st;
     const int64_t N = H->nrows;
     const int dt = H->dtype;
     const size_t vb = static_cast<size_t>(N) * 2 * real_size(dt);
     for (int i = 0; i < 3; ++i) {
-        size_t have = H->ws.naive_bytes;
-        if ((st = grow(&H->ws.naive[i], &have, vb, "hipMalloc(Lanczos vector)")) != KPM_OK) return st;
+        size_t have = ws.naive_bytes;
+        if ((st = grow(&ws.naive[i], &have, vb, "hipMalloc(Lanczos vector)")) != KPM_OK) return st;
     }
-    H->ws.naive_bytes = vb;
-    if (!H->ws.dot_part)
-        KPM_HIP(hipMalloc(&H->ws.dot_part, static_cast<size_t>(naive_dot_partials()) * 2 * sizeof(double)),
+    ws.naive_bytes = vb;
+    if (!ws.dot_part)
+        KPM_HIP(hipMalloc(&ws.dot_part, static_cast<size_t>(naive_dot_partials()) * 2 * sizeof(double)),
                 "hipMalloc(dot partials)");
     // [steps][2] (alpha_j, beta_{j-1}), [steps] beta_j, <q|Hq>, |w|^2, the two extremes
     const size_t nd = 3 * static_cast<size_t>(steps) + 6;
-    if ((st = grow(&H->ws.lanczos, &H->ws.lanczos_bytes, nd * sizeof(double), "hipMalloc(Lanczos scalars)")) != KPM_OK)
+    if ((st = grow(&ws.lanczos, &ws.lanczos_bytes, nd * sizeof(double), "hipMalloc(Lanczos scalars)")) != KPM_OK)
         return st;
-    if ((st = ensure_queue(H)) != KPM_OK) return st;
-    if ((st = ensure_schedule(H)) != KPM_OK) return st;
-    double* ab = H->ws.lanczos;
+    if ((st = ensure_queue(ws)) != KPM_OK) return st;
+    double* ab = ws.lanczos;
     double* beta = ab + 2 * steps;
     double* dq = beta + steps;
     double* nrm = dq + 2;
     double* ext = nrm + 2;
-    void* qp = H->ws.naive[0];
-    void* q = H->ws.naive[1];
-    void* w = H->ws.naive[2];
+    void* qp = ws.naive[0];
+    void* q = ws.naive[1];
+    void* w = ws.naive[2];
     // q_0 = 0 (its coefficient is 0 in the first step, but 0 * garbage need not be 0)
     const int64_t words = static_cast<int64_t>(vb / sizeof(int));
     if (words > INT32_MAX) return fail(KPM_ENOTSUP, "Lanczos vector too large");
@@ -610,15 +754,15 @@ kpm_status kpm_lanczos_bounds(const kpm_hamiltonian* Hc, int32_t steps, uint64_t
     // q_1: a random-phase unit vector
     KPM_HIP(launch_phase_block(q, N, 1, dt, seed, s), "phase block kernel");
     for (int j = 0; j < steps; ++j) {
-        SweepArgs a{H->val, H->col, N, q, w, H->sched, 1.0, 0.0, 0.0, nullptr, launch_grid(H, 1)};
-        a.queue = H->ws.queue;
+        SweepArgs a{H->val, H->col, N, q, w, sched, 1.0, 0.0, 0.0, nullptr, launch_grid(H, 1)};
+        a.queue = ws.queue;
         for (int i = 0; i < 3; ++i) a.L[i] = H->L[i];
-        if (sweep_uses_queue(H, 1)) KPM_HIP(launch_zero_ints(H->ws.queue, kXcds, s), "zero kernel");
+        if (sweep_uses_queue(H, 1)) KPM_HIP(launch_zero_ints(ws.queue, kXcds, s), "zero kernel");
         KPM_HIP(launch_any_sweep(H, 1, KPM_PLAIN, a, s), "spmv");                       // w = H q
-        KPM_HIP(launch_dot(dt, N, q, w, H->ws.dot_part, dq, s), "dot kernel");           // alpha_j
+        KPM_HIP(launch_dot(dt, N, q, w, ws.dot_part, dq, s), "dot kernel");           // alpha_j
         KPM_HIP(launch_lanczos_update(dt, N, dq, j > 0 ? beta + j - 1 : nullptr, ab + 2 * j, q, qp, w, s),
                 "update kernel");                                                         // w -= alpha q + beta qp
-        KPM_HIP(launch_dot(dt, N, w, w, H->ws.dot_part, nrm, s), "nrm2 kernel");         // beta_j^2
+        KPM_HIP(launch_dot(dt, N, w, w, ws.dot_part, nrm, s), "nrm2 kernel");         // beta_j^2
         KPM_HIP(launch_lanczos_normalise(dt, N, nrm, w, qp, beta + j, s), "normalise kernel");
         std::swap(qp, q);   // q_{j-1} <- q_j, q_j <- q_{j+1}
     }
@@ -641,8 +785,10 @@ kpm_status kpm_set_scaling(kpm_hamiltonian* H, double a, double b) {
 }
 
 namespace {
-// scalar-product partials of kpm_dot, one buffer per device
-std::vector<double*> g_dot_part;
+// scalar-product partials of kpm_dot, one buffer per (device, stream), kept
+// until the process ends
+std::mutex g_dot_lock;
+std::map<std::pair<int, hipStream_t>, double*> g_dot_part;
 
 kpm_status blas1_args(int32_t dtype, int64_t n, std::initializer_list<const void*> ptrs) {
     if (dtype != KPM_C128 && dtype != KPM_C64) return fail(KPM_EINVAL, "unknown dtype");
@@ -679,11 +825,39 @@ kpm_status kpm_dot(int32_t dtype, int64_t n, const void* x, const void* y, doubl
     hipStream_t s = static_cast<hipStream_t>(stream);
     int dev = 0;
     KPM_HIP(hipGetDevice(&dev), "hipGetDevice");
-    if (static_cast<int>(g_dot_part.size()) <= dev) g_dot_part.resize(dev + 1, nullptr);
-    if (!g_dot_part[dev])
-        KPM_HIP(hipMalloc(&g_dot_part[dev], static_cast<size_t>(naive_dot_partials()) * 2 * sizeof(double)),
-                "hipMalloc(dot partials)");
-    KPM_HIP(launch_dot(dtype, n, x, y, g_dot_part[dev], out, s), "dot kernel");
+    double* part = nullptr;
+    {
+        std::lock_guard<std::mutex> g(g_dot_lock);
+        double*& p = g_dot_part[{dev, s}];
+        if (!p)
+            KPM_HIP(hipMalloc(&p, static_cast<size_t>(naive_dot_partials()) * 2 * sizeof(double)),
+                    "hipMalloc(dot partials)");
+        part = p;
+    }
+    KPM_HIP(launch_dot(dtype, n, x, y, part, out, s), "dot kernel");
+    return KPM_OK;
+}
+
+kpm_status kpm_stream(int32_t kind, void* c, const void* a, const void* b, double scalar, int64_t bytes,
+                      int32_t wg_per_cu, int32_t nontemporal, void* stream) {
+    g_error.clear();
+    if (kind != KPM_STREAM_COPY && kind != KPM_STREAM_TRIAD) return fail(KPM_EINVAL, "unknown stream kernel");
+    if (bytes < 0 || bytes % 16 != 0) return fail(KPM_EINVAL, "bytes must be a non-negative multiple of 16");
+    if (wg_per_cu < 1 || wg_per_cu > 32) return fail(KPM_EINVAL, "wg_per_cu must be in [1, 32]");
+    if (bytes == 0) return KPM_OK;
+    const bool triad = kind == KPM_STREAM_TRIAD;
+    if (!c || !a || (triad && !b)) return fail(KPM_EINVAL, "NULL array");
+    for (const void* p : {static_cast<const void*>(c), a, triad ? b : a})
+        if (reinterpret_cast<uintptr_t>(p) % 16 != 0) return fail(KPM_EINVAL, "arrays must be 16-byte aligned");
+    const char* cc = static_cast<const char*>(c);
+    auto overlap = [&](const void* x) {
+        const char* xc = static_cast<const char*>(x);
+        return xc < cc + bytes && cc < xc + bytes;
+    };
+    if (overlap(a) || (triad && overlap(b))) return fail(KPM_EINVAL, "c overlaps an input");
+    KPM_HIP(launch_stream(kind, nontemporal ? 1 : 0, c, a, b, scalar, bytes / 16, wg_per_cu,
+                          static_cast<hipStream_t>(stream)),
+            "stream kernel");
     return KPM_OK;
 }
 
@@ -771,15 +945,11 @@ kpm_status kpm_moment_features(const double* mu, int32_t n_inst, int32_t R, int3
 kpm_status kpm_set_sweep_tuning(const kpm_sweep_tuning* t) {
     g_error.clear();
     if (!t) {
-        set_tuning(kpm_sweep_tuning{0, kXcds, 8, 16, 0, 2, 3, 1, 1, 0, 4});
+        set_tuning(default_tuning());
         return KPM_OK;
     }
-    if (t->wg_per_cu < 0 || t->xcd_ways < 0 || t->chunk_tiles < 0 || t->pencil < 0 || t->dynamic < 0 ||
-        t->prefetch < 0 || t->prefetch > 2 || t->stream < 0 || t->stream > 3 || t->lattice < 0 || t->lattice > 2 ||
-        t->gather < 0 || t->gather > 2 || t->tile_order < 0 || t->tile_order > 3 || t->slab < 0)
-        return fail(KPM_EINVAL, "tuning fields must be >= 0");
-    if (t->wg_per_cu > 64 || t->xcd_ways > 64 || t->chunk_tiles > (1 << 20))
-        return fail(KPM_EINVAL, "tuning field out of range");
+    const kpm_status st = check_tuning(*t);
+    if (st != KPM_OK) return st;
     set_tuning(*t);
     return KPM_OK;
 }
@@ -794,13 +964,32 @@ kpm_status kpm_get_sweep_tuning(kpm_sweep_tuning* t) {
 kpm_status kpm_sweep_kernel(const kpm_hamiltonian* Hc, int32_t R, int32_t* kernel) {
     g_error.clear();
     if (!Hc || !kernel) return fail(KPM_EINVAL, "H or kernel is NULL");
+    TuningScope scope(nullptr);
     *kernel = use_lattice(Hc, R) ? 1 : (use_gather(Hc->dtype, R, Hc->nrows) ? 2 : 0);
+    return KPM_OK;
+}
+
+kpm_status kpm_sweep_plan(const kpm_hamiltonian* Hc, int32_t R, const kpm_sweep_tuning* tuning,
+                          kpm_sweep_plan_info* out) {
+    g_error.clear();
+    if (!Hc || !out) return fail(KPM_EINVAL, "H or out is NULL");
+    if (!r_supported(R)) return fail(KPM_ENOTSUP, "R must be one of 1, 2, 4, 8, 16, 32, 64");
+    kpm_status st;
+    if (tuning && (st = check_tuning(*tuning)) != KPM_OK) return st;
+    TuningScope scope(tuning);
+    const bool lat = use_lattice(Hc, R);
+    out->kernel = lat ? 1 : (use_gather(Hc->dtype, R, Hc->nrows) ? 2 : 0);
+    out->grid = launch_grid(Hc, R);
+    out->tile_order = lat ? lattice_order(Hc, out->grid) : -1;
+    out->pieces = lat ? lattice_pieces(Hc, R, out->grid, get_tuning().prefetch) : -1;
+    out->halves = lat ? R / 32 : -1;
     return KPM_OK;
 }
 
 kpm_status kpm_sweep_profile_enable(int32_t enable) {
     g_error.clear();
     if (enable < 0) return fail(KPM_EINVAL, "sweep profile period must be >= 0");
+    std::lock_guard<std::mutex> g(g_prof.lock);
     g_prof.period = enable;
     g_prof.seen = 0;
     return KPM_OK;
@@ -808,6 +997,7 @@ kpm_status kpm_sweep_profile_enable(int32_t enable) {
 
 kpm_status kpm_sweep_profile_read(int64_t* count, double* total_ms, double* min_ms, double* max_ms) {
     g_error.clear();
+    std::lock_guard<std::mutex> g(g_prof.lock);
     double tot = 0.0, lo = 0.0, hi = 0.0;
     for (size_t i = 0; i < g_prof.used; ++i) {
         KPM_HIP(hipEventSynchronize(g_prof.stop[i]), "hipEventSynchronize");
@@ -828,7 +1018,8 @@ kpm_status kpm_sweep_profile_read(int64_t* count, double* total_ms, double* min_
 kpm_status kpm_set_batch_tuning(const kpm_batch_tuning* t) {
     g_error.clear();
     if (!t) {
-        g_batch_tuning = kpm_batch_tuning{0, 0, 1, 4};
+        std::lock_guard<std::mutex> g(g_batch_lock);
+        g_batch_tuning = kDefaultBatchTuning;
         return KPM_OK;
     }
     if (t->waves != 0 && t->waves != 4 && t->waves != 8 && t->waves != 16)
@@ -836,6 +1027,7 @@ kpm_status kpm_set_batch_tuning(const kpm_batch_tuning* t) {
     if (t->wg_per_cu < 0 || t->wg_per_cu > 16) return fail(KPM_EINVAL, "wg_per_cu must be in [0, 16]");
     if (t->dynamic < 0) return fail(KPM_EINVAL, "dynamic must be >= 0");
     if (t->slab < 0) return fail(KPM_EINVAL, "slab must be >= 0");
+    std::lock_guard<std::mutex> g(g_batch_lock);
     g_batch_tuning = *t;
     return KPM_OK;
 }
@@ -843,7 +1035,7 @@ kpm_status kpm_set_batch_tuning(const kpm_batch_tuning* t) {
 kpm_status kpm_get_batch_tuning(kpm_batch_tuning* t) {
     g_error.clear();
     if (!t) return fail(KPM_EINVAL, "tuning is NULL");
-    *t = g_batch_tuning;
+    *t = batch_tuning();
     return KPM_OK;
 }
 
@@ -871,9 +1063,9 @@ kpm_status kpm_moments_batched(const kpm_hamiltonian* const* H, const void* cons
         if (n * R * pair >= lim || n * kWidth * pair >= lim)
             return fail(KPM_ENOTSUP, "an instance's vector block or matrix reaches 4 GiB");
     }
-    if (static_cast<int>(g_batch.size()) <= dev) g_batch.resize(dev + 1);
-    BatchState& b = g_batch[dev];
     hipStream_t s = static_cast<hipStream_t>(stream);
+    BatchState& b = *batch_state(dev, s);
+    const kpm_batch_tuning bt = batch_tuning();
     const size_t rs = real_size(dtype);
 
     // instance table: two work blocks and the sweep products per instance
@@ -906,8 +1098,8 @@ kpm_status kpm_moments_batched(const kpm_hamiltonian* const* H, const void* cons
         inst[i] = BatchInst{H[i]->val, H[i]->col, V0[i], base, base + blk, b.eta + eta_per * i,
                             mu + static_cast<size_t>(i) * R * M, H[i]->nrows, 1.0 / H[i]->a, H[i]->b / H[i]->a,
                             {H[i]->L[0], H[i]->L[1], H[i]->L[2]}, 0,
-                            g_batch_tuning.slab > 0
-                                ? SlabGeom::make(H[i]->L[0], H[i]->L[1], H[i]->L[2], g_batch_tuning.slab,
+                            bt.slab > 0
+                                ? SlabGeom::make(H[i]->L[0], H[i]->L[1], H[i]->L[2], bt.slab,
                                                  batched_rows_per_pass(dtype, R))
                                 : SlabGeom{}};
     }
@@ -921,18 +1113,18 @@ kpm_status kpm_moments_batched(const kpm_hamiltonian* const* H, const void* cons
     if (max_w == 0) return fail(KPM_EINTERNAL, "no batched kernel for this dtype and R");
     // 8 waves (one workgroup per CU) by default: measured faster than 16 on
     // the 512-instance family, whose sweep is bound by the texture-address path
-    int waves = g_batch_tuning.waves > 0 ? g_batch_tuning.waves : (max_w < 8 ? max_w : 8);
+    int waves = bt.waves > 0 ? bt.waves : (max_w < 8 ? max_w : 8);
     if (waves > max_w) waves = max_w;
-    const int per_cu = g_batch_tuning.wg_per_cu > 0 ? g_batch_tuning.wg_per_cu : 1;
+    const int per_cu = bt.wg_per_cu > 0 ? bt.wg_per_cu : 1;
     int grid = device_cus() * per_cu;
     if (grid > n_inst) grid = n_inst;
-    const int dynamic = g_batch_tuning.dynamic ? 1 : 0;
-    BatchArgs args{b.inst, b.order, n_inst, b.ints, b.ints + 1, M, grid, waves, dynamic, g_batch_tuning.slab};
+    const int dynamic = bt.dynamic ? 1 : 0;
+    BatchArgs args{b.inst, b.order, n_inst, b.ints, b.ints + 1, M, grid, waves, dynamic, bt.slab};
 
     const bool use_graph = (flags & KPM_BATCH_GRAPH) != 0;
     bool hit = use_graph && b.exec && b.key_dtype == dtype && b.key_R == R && b.key_M == M &&
                b.key_grid == grid && b.key_waves == waves && b.key_dynamic == dynamic &&
-               b.key_slab == g_batch_tuning.slab &&
+               b.key_slab == bt.slab &&
                b.key_inst.size() == inst.size() && b.key_order == order;
     for (size_t i = 0; hit && i < inst.size(); ++i) hit = same_inst(b.key_inst[i], inst[i]);
 
@@ -967,7 +1159,7 @@ kpm_status kpm_moments_batched(const kpm_hamiltonian* const* H, const void* cons
             b.key_grid = grid;
             b.key_waves = waves;
             b.key_dynamic = dynamic;
-            b.key_slab = g_batch_tuning.slab;
+            b.key_slab = bt.slab;
             KPM_HIP(hipGraphLaunch(b.exec, s), "hipGraphLaunch");
         } else {
             KPM_HIP(launch_zero_ints(b.ints, 2, s), "zero kernel");

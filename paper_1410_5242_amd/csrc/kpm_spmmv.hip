@@ -2,6 +2,8 @@
 // per-workgroup scalar-product partials, the eta -> mu doubling identity,
 // the moment sanity check), the sweep's tuning state and its dispatch to the
 // per-precision instantiations.
+#include <atomic>
+
 #include "kpm_internal.h"
 
 namespace kpm {
@@ -50,6 +52,14 @@ __global__ void __launch_bounds__(256) zero_ints_kernel(int* __restrict__ p, int
     if (i < n) p[i] = 0;
 }
 
+// dst[i] = src[i] over n 16-byte units, grid-stride
+__global__ void __launch_bounds__(256)
+copy16_kernel(const int4* __restrict__ src, int4* __restrict__ dst, int64_t n) {
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride)
+        dst[i] = src[i];
+}
+
 // mu_{2m} = 2 eta_{2m} - mu_0, mu_{2m+1} = 2 Re eta_{2m+1} - mu_1.
 __global__ void __launch_bounds__(256)
 eta_to_mu_kernel(const double* __restrict__ eta, int R, int M, double* __restrict__ mu) {
@@ -77,25 +87,62 @@ check_moments_kernel(const double* __restrict__ mu, int R, int M, int* __restric
 }  // namespace
 
 namespace {
-kpm_sweep_tuning g_tuning = {0, kXcds, 8, 16, 0, 2, 3, 1, 1, 3, 4};
+// wg_per_cu, xcd_ways, chunk_tiles, pencil, dynamic, prefetch, stream,
+// lattice, gather, tile_order, slab
+constexpr kpm_sweep_tuning kDefaultTuning = {0, kXcds, 8, 16, 0, 2, 3, 1, 1, 3, 4};
+std::mutex g_tuning_lock;
+kpm_sweep_tuning g_tuning = kDefaultTuning;
+thread_local const kpm_sweep_tuning* t_call = nullptr;   // snapshot of the running call
+
+kpm_sweep_tuning global_tuning() {
+    std::lock_guard<std::mutex> g(g_tuning_lock);
+    return g_tuning;
+}
+}  // namespace
+
+kpm_sweep_tuning default_tuning() { return kDefaultTuning; }
+kpm_sweep_tuning get_tuning() { return t_call ? *t_call : global_tuning(); }
+void set_tuning(const kpm_sweep_tuning& t) {
+    std::lock_guard<std::mutex> g(g_tuning_lock);
+    g_tuning = t;
 }
 
-kpm_sweep_tuning get_tuning() { return g_tuning; }
-void set_tuning(const kpm_sweep_tuning& t) { g_tuning = t; }
+TuningScope::TuningScope(const kpm_sweep_tuning* override)
+    : snap_(override ? *override : get_tuning()), prev_(t_call) {
+    t_call = &snap_;
+}
+TuningScope::~TuningScope() { t_call = prev_; }
+
+kpm_status check_tuning(const kpm_sweep_tuning& t) {
+    if (t.wg_per_cu < 0 || t.xcd_ways < 0 || t.chunk_tiles < 0 || t.pencil < 0 || t.dynamic < 0 ||
+        t.prefetch < 0 || t.prefetch > 2 || t.stream < 0 || t.stream > 3 || t.lattice < 0 || t.lattice > 2 ||
+        t.gather < 0 || t.gather > 2 || t.tile_order < 0 || t.tile_order > 3 || t.slab < 0) {
+        set_error("tuning field out of range (negative, or above its largest option)");
+        return KPM_EINVAL;
+    }
+    if (t.wg_per_cu > 64 || t.xcd_ways > 64 || t.chunk_tiles > (1 << 20) || t.pencil > 4096 || t.slab > 65536) {
+        set_error("tuning field out of range");
+        return KPM_EINVAL;
+    }
+    return KPM_OK;
+}
 
 int device_cus() {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 256;
-    static int cached[64] = {0};
+    static std::atomic<int> cached[64];
     if (dev < 0 || dev >= 64) return 256;
-    if (!cached[dev]) {
+    int c = cached[dev].load(std::memory_order_relaxed);
+    if (!c) {
         hipDeviceProp_t p;
-        cached[dev] = hipGetDeviceProperties(&p, dev) == hipSuccess ? p.multiProcessorCount : 256;
+        c = hipGetDeviceProperties(&p, dev) == hipSuccess ? p.multiProcessorCount : 256;
+        cached[dev].store(c, std::memory_order_relaxed);
     }
-    return cached[dev];
+    return c;
 }
 
 bool use_gather(int dtype, int R, int64_t nrows) {
+    const kpm_sweep_tuning g_tuning = get_tuning();
     if (g_tuning.gather == 2) return false;
     // 32-bit buffer offsets with room for the read-ahead past the last pass
     const uint64_t rs = dtype == KPM_C128 ? 8 : 4;
@@ -106,6 +153,7 @@ bool use_gather(int dtype, int R, int64_t nrows) {
 }
 
 int sweep_grid(int dtype, int R, int64_t nrows) {
+    const kpm_sweep_tuning g_tuning = get_tuning();
     int per_cu;
     if (use_gather(dtype, R, nrows)) {
         // 16 waves per CU by default, no more workgroups than the LDS holds
@@ -121,6 +169,7 @@ int sweep_grid(int dtype, int R, int64_t nrows) {
 }
 
 hipError_t launch_sweep(int dtype, int R, int variant, const SweepArgs& a_in, hipStream_t s) {
+    const kpm_sweep_tuning g_tuning = get_tuning();
     SweepArgs a = a_in;
     a.xcd_ways = g_tuning.xcd_ways > 0 ? g_tuning.xcd_ways : 1;
     a.slab = g_tuning.slab;
@@ -144,6 +193,16 @@ hipError_t launch_reduce_partials(const double* partials, int nslots, int grid, 
 hipError_t launch_zero_ints(int* p, int n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     zero_ints_kernel<<<(n + 255) / 256, 256, 0, s>>>(p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy16(void* dst, const void* src, size_t bytes, hipStream_t s) {
+    const int64_t n = static_cast<int64_t>(bytes / 16);
+    if (n <= 0) return hipSuccess;
+    int64_t blocks = (n + 255) / 256;
+    const int64_t cap = static_cast<int64_t>(device_cus()) * 16;   // 16 workgroups of 256 per CU
+    if (blocks > cap) blocks = cap;
+    copy16_kernel<<<static_cast<int>(blocks), 256, 0, s>>>(static_cast<const int4*>(src), static_cast<int4*>(dst), n);
     return hipGetLastError();
 }
 

@@ -7,7 +7,9 @@
 // element c = i R + r is key + (c + 1) gamma, gamma = 0x9E3779B97F4A7C15,
 // key = mix(seed + gamma); u = (top 53 bits of mix(state)) / 2^53 and
 // v_ir = exp(2 pi i u) / sqrt(N), computed in FP64 and rounded to the
-// storage precision.
+// storage precision.  The disorder potential of a Hamiltonian built without
+// a caller array draws from the same generator under the key
+// mix(seed + 2 gamma) (the second SplitMix64 output of the seed).
 #include "kpm_internal.h"
 
 #include <cmath>
@@ -34,6 +36,17 @@ phase_block_kernel(T* __restrict__ V, int64_t n, uint64_t key, double scale) {
     sincos(6.283185307179586476925286766559 * u, &s, &co);
     V[2 * c] = static_cast<T>(co * scale);
     V[2 * c + 1] = static_cast<T>(s * scale);
+}
+
+// Disorder potential V_n = gamma (u_n - 1/2) ~ U[-gamma/2, gamma/2) of the
+// Hamiltonian (eq. "Ham", onsite term), site n drawing counter n under `key`
+__global__ void __launch_bounds__(256)
+potential_kernel(double* __restrict__ pot, int64_t n, uint64_t key, double gamma) {
+    const int64_t c = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    const uint64_t z = mix64(key + static_cast<uint64_t>(c + 1) * kGamma);
+    const double u = static_cast<double>(z >> 11) * (1.0 / 9007199254740992.0);
+    pot[c] = gamma * (u - 0.5);
 }
 
 // Deterministic start vectors of the local and momentum-resolved spectral
@@ -121,6 +134,14 @@ hipError_t launch_phase_block(void* V, int64_t N, int R, int dtype, uint64_t see
         phase_block_kernel<double><<<blocks, 256, 0, s>>>(static_cast<double*>(V), n, key, scale);
     else
         phase_block_kernel<float><<<blocks, 256, 0, s>>>(static_cast<float*>(V), n, key, scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_potential(double* pot, int64_t nsite, double gamma, uint64_t seed, hipStream_t s) {
+    if (nsite <= 0) return hipSuccess;
+    // second output of SplitMix64 started at `seed` (the start block uses the first)
+    const uint64_t key = mix64(seed + 2 * kGamma);
+    potential_kernel<<<static_cast<int>((nsite + 255) / 256), 256, 0, s>>>(pot, nsite, key, gamma);
     return hipGetLastError();
 }
 

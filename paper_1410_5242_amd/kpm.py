@@ -54,6 +54,8 @@ class LatticeDesc(ctypes.Structure):
         ("L", ctypes.c_int32 * 3),
         ("periodic", ctypes.c_int32 * 3),
         ("t", ctypes.c_double),
+        ("gamma", ctypes.c_double),
+        ("seed", ctypes.c_uint64),
         ("potential", ctypes.c_void_p),
         ("dtype", ctypes.c_int32),
         ("margin", ctypes.c_double),
@@ -63,16 +65,27 @@ class LatticeDesc(ctypes.Structure):
     ]
 
 
+class RunOpts(ctypes.Structure):
+    _fields_ = [("check", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("variant", ctypes.c_int32),
+                ("mu_on_host", ctypes.c_int32), ("tuning", ctypes.POINTER(SweepTuning)),
+                ("eta_out", ctypes.c_void_p)]
+
+
+class SweepPlan(ctypes.Structure):
+    _fields_ = [("kernel", ctypes.c_int32), ("grid", ctypes.c_int32), ("tile_order", ctypes.c_int32),
+                ("pieces", ctypes.c_int32), ("halves", ctypes.c_int32)]
+
+
 _LIB = None
 EXPORTS = ("kpm_build_hamiltonian", "kpm_hamiltonian_info", "kpm_export_csr",
            "kpm_destroy_hamiltonian", "kpm_aug_spmmv", "kpm_moments", "kpm_dos",
-           "kpm_set_sweep_tuning", "kpm_get_sweep_tuning", "kpm_sweep_kernel", "kpm_sweep_profile_enable", "kpm_sweep_profile_read", "kpm_moments_batched",
+           "kpm_set_sweep_tuning", "kpm_get_sweep_tuning", "kpm_sweep_kernel", "kpm_sweep_plan", "kpm_sweep_profile_enable", "kpm_sweep_profile_read", "kpm_moments_batched",
            "kpm_set_batch_tuning", "kpm_get_batch_tuning", "kpm_mlp_create", "kpm_mlp_destroy",
            "kpm_mlp_param_count", "kpm_mlp_set_params", "kpm_mlp_get_params", "kpm_mlp_get_grads",
            "kpm_mlp_forward", "kpm_mlp_backward", "kpm_mlp_adam_step", "kpm_mlp_train_step",
            "kpm_mlp_gemm_bf16", "kpm_dos_batched", "kpm_moment_features", "kpm_random_phase_block",
            "kpm_moments_naive", "kpm_axpy", "kpm_scal", "kpm_dot", "kpm_site_block", "kpm_plane_wave_block",
-           "kpm_lanczos_bounds", "kpm_set_scaling",
+           "kpm_lanczos_bounds", "kpm_set_scaling", "kpm_stream",
            "kpm_last_error", "kpm_version")
 
 
@@ -98,7 +111,7 @@ def lib():
     L.kpm_aug_spmmv.restype = ctypes.c_int
     L.kpm_aug_spmmv.argtypes = [vp, vp, vp, i32, dbl, dbl, dbl, i32, vp, vp]
     L.kpm_moments.restype = ctypes.c_int
-    L.kpm_moments.argtypes = [vp, vp, i32, i32, vp, vp, i32, vp]
+    L.kpm_moments.argtypes = [vp, vp, i32, i32, vp, ctypes.POINTER(RunOpts), vp]
     L.kpm_moments_naive.restype = ctypes.c_int
     L.kpm_moments_naive.argtypes = [vp, vp, i32, i32, vp, i32, vp]
     L.kpm_axpy.restype = ctypes.c_int
@@ -115,6 +128,8 @@ def lib():
     L.kpm_get_sweep_tuning.argtypes = [ctypes.POINTER(SweepTuning)]
     L.kpm_sweep_kernel.restype = ctypes.c_int
     L.kpm_sweep_kernel.argtypes = [vp, i32, ctypes.POINTER(i32)]
+    L.kpm_sweep_plan.restype = ctypes.c_int
+    L.kpm_sweep_plan.argtypes = [vp, i32, ctypes.POINTER(SweepTuning), ctypes.POINTER(SweepPlan)]
     L.kpm_sweep_profile_enable.restype = ctypes.c_int
     L.kpm_sweep_profile_enable.argtypes = [i32]
     L.kpm_sweep_profile_read.restype = ctypes.c_int
@@ -160,6 +175,8 @@ def lib():
     L.kpm_plane_wave_block.argtypes = [vp, vp, i32, vp, vp, i32, vp]
     L.kpm_random_phase_block.restype = ctypes.c_int
     L.kpm_random_phase_block.argtypes = [vp, i64, i32, i32, ctypes.c_uint64, vp]
+    L.kpm_stream.restype = ctypes.c_int
+    L.kpm_stream.argtypes = [i32, vp, vp, vp, dbl, i64, i32, i32, vp]
     L.kpm_last_error.restype = ctypes.c_char_p
     L.kpm_last_error.argtypes = []
     L.kpm_version.restype = ctypes.c_char_p
@@ -216,16 +233,24 @@ class Hamiltonian:
             pass
 
 
-def build_hamiltonian(L, potential, t: float = 1.0, periodic=(1, 1, 1), dtype: str = "c128",
-                      margin: float = 1.01, fixed_scale=None, stream=None) -> Hamiltonian:
-    """kpm_build_hamiltonian: H of eq. "Ham" on the device plus its Gershgorin scaling."""
-    pot = np.ascontiguousarray(potential, dtype=np.float64).reshape(-1)
+def build_hamiltonian(L, potential=None, t: float = 1.0, periodic=(1, 1, 1), dtype: str = "c128",
+                      margin: float = 1.01, fixed_scale=None, gamma: float = 0.0, seed: int = 0,
+                      stream=None) -> Hamiltonian:
+    """kpm_build_hamiltonian: H of eq. "Ham" on the device plus its Gershgorin scaling.
+
+    `potential` is the host array of V_n; None draws V_n ~ U[-gamma/2, gamma/2) on the device
+    from the library's counter generator keyed by `seed`."""
     d = LatticeDesc()
     for j in range(3):
         d.L[j] = int(L[j])
         d.periodic[j] = 1 if periodic[j] else 0
     d.t = float(t)
-    d.potential = pot.ctypes.data
+    d.gamma = float(gamma)
+    d.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
+    pot = None
+    if potential is not None:
+        pot = np.ascontiguousarray(potential, dtype=np.float64).reshape(-1)
+        d.potential = pot.ctypes.data
     d.dtype = _DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
     d.margin = float(margin)
     if fixed_scale is not None:
@@ -255,9 +280,24 @@ def aug_spmmv(H: Hamiltonian, V: torch.Tensor, W: torch.Tensor, alpha: float, be
                                _VARIANTS[variant], _dptr(eta) if eta is not None else None, _stream(stream)))
 
 
+def _tuning_struct(tuning):
+    """A SweepTuning from a dict of fields (missing ones at the library defaults), or None."""
+    if tuning is None:
+        return None
+    fields = dict(DEFAULT_SWEEP_TUNING)
+    fields.update(tuning)
+    return SweepTuning(*[int(fields[k]) for k, _ in SweepTuning._fields_])
+
+
 def moments(H: Hamiltonian, V0: torch.Tensor, M: int, mu: torch.Tensor | None = None,
-            eta: torch.Tensor | None = None, check: bool = True, stream=None) -> torch.Tensor:
-    """kpm_moments: mu[R][M] (float64, device) for the [N][R] start block V0."""
+            eta: torch.Tensor | None = None, check: bool = True, graph: bool = False, variant: str = "full",
+            tuning: dict | None = None, stream=None):
+    """kpm_moments: mu[R][M] (float64) for the [N][R] start block V0.
+
+    mu may be a device tensor (default) or a host numpy array (filled in place, the call
+    synchronises); graph=True captures the launch sequence once and replays it; variant
+    "nodot" runs the recurrence without the scalar products (mu is not written); tuning is a
+    per-call launch shape (dict of kpm_sweep_tuning fields)."""
     if V0.dim() != 2 or V0.shape[0] != H.N:
         raise ValueError("V0 must be [N][R]")
     if V0.dtype != H.torch_dtype:
@@ -265,8 +305,22 @@ def moments(H: Hamiltonian, V0: torch.Tensor, M: int, mu: torch.Tensor | None = 
     R = V0.shape[1]
     if mu is None:
         mu = torch.empty((R, M), dtype=torch.float64, device=V0.device)
-    _check(lib().kpm_moments(H.handle, _dptr(V0), R, int(M), _dptr(mu),
-                             _dptr(eta) if eta is not None else None, 1 if check else 0, _stream(stream)))
+    opts = RunOpts()
+    opts.check = 1 if check else 0
+    opts.use_graph = 1 if graph else 0
+    opts.variant = _VARIANTS[variant]
+    t = _tuning_struct(tuning)
+    if t is not None:
+        opts.tuning = ctypes.pointer(t)
+    opts.eta_out = _dptr(eta).value if eta is not None else None
+    if isinstance(mu, np.ndarray):
+        if mu.dtype != np.float64 or mu.shape != (R, M) or not mu.flags.c_contiguous:
+            raise ValueError("host mu must be a contiguous float64 [R][M] array")
+        opts.mu_on_host = 1
+        mu_ptr = ctypes.c_void_p(mu.ctypes.data)
+    else:
+        mu_ptr = _dptr(mu)
+    _check(lib().kpm_moments(H.handle, _dptr(V0), R, int(M), mu_ptr, ctypes.byref(opts), _stream(stream)))
     return mu
 
 
@@ -447,6 +501,10 @@ def moment_features(mu: torch.Tensor, n_mom: int, extra: torch.Tensor | None = N
     return x
 
 
+DEFAULT_SWEEP_TUNING = {"wg_per_cu": 0, "xcd_ways": 8, "chunk_tiles": 8, "pencil": 16, "dynamic": 0,
+                        "prefetch": 2, "stream": 3, "lattice": 1, "gather": 1, "tile_order": 3, "slab": 4}
+
+
 def set_sweep_tuning(wg_per_cu: int = 0, xcd_ways: int = 8, chunk_tiles: int = 8, pencil: int = 16,
                      dynamic: int = 0, prefetch: int = 2, stream: int = 3, lattice: int = 1, gather: int = 1,
                      tile_order: int = 3, slab: int = 4):
@@ -473,6 +531,16 @@ def sweep_kernel(H: Hamiltonian, R: int) -> str:
     k = ctypes.c_int32()
     _check(lib().kpm_sweep_kernel(H.handle, int(R), ctypes.byref(k)))
     return {0: "aug_spmmv_kernel", 1: "lattice_kernel", 2: "gather_sweep_kernel"}[k.value]
+
+
+def sweep_plan(H: Hamiltonian, R: int, tuning: dict | None = None) -> dict:
+    """kpm_sweep_plan: kernel, grid, resolved tile order, z-pieces and 32-column halves of a sweep."""
+    p = SweepPlan()
+    t = _tuning_struct(tuning)
+    _check(lib().kpm_sweep_plan(H.handle, int(R), ctypes.byref(t) if t is not None else None, ctypes.byref(p)))
+    names = {0: "aug_spmmv_kernel", 1: "lattice_kernel", 2: "gather_sweep_kernel"}
+    return {"kernel": names[p.kernel], "grid": p.grid, "tile_order": p.tile_order, "pieces": p.pieces,
+            "halves": p.halves}
 
 
 def sweep_profile_enable(on=True):
@@ -601,6 +669,21 @@ def gemm_bf16(A: torch.Tensor, B: torch.Tensor, trans_a: bool = False, trans_b: 
     _check(lib().kpm_mlp_gemm_bf16(_dptr(A), _dptr(B), M, N, K, int(trans_a), int(trans_b), _dptr(C),
                                    _stream(stream)))
     return C
+
+
+STREAM_COPY, STREAM_TRIAD = 0, 1
+
+
+def stream_kernel(kind: str, c: torch.Tensor, a: torch.Tensor, b: torch.Tensor | None = None, scalar: float = 3.0,
+                  wg_per_cu: int = 4, nontemporal: bool = True, stream=None):
+    """kpm_stream: STREAM copy (c = a) or triad (c = a + scalar b, FP64) over the bytes of c."""
+    k = {"copy": STREAM_COPY, "triad": STREAM_TRIAD}[kind]
+    nbytes = c.numel() * c.element_size()
+    if a.numel() * a.element_size() != nbytes or (b is not None and b.numel() * b.element_size() != nbytes):
+        raise ValueError("arrays must have the same size in bytes")
+    _check(lib().kpm_stream(k, _dptr(c), _dptr(a), _dptr(b) if b is not None else None, float(scalar), nbytes,
+                            int(wg_per_cu), 1 if nontemporal else 0, _stream(stream)))
+    return c
 
 
 def version() -> str:

@@ -53,9 +53,27 @@ def test_argument_validation_without_device(L):
     d.L[0] = d.L[1] = d.L[2] = 4
     d.periodic[0] = d.periodic[1] = d.periodic[2] = 1
     d.t, d.margin = 1.0, 1.01
-    assert L.kpm_build_hamiltonian(ctypes.byref(d), None, ctypes.byref(out)) == kpm.KPM_EINVAL  # no potential
+    d.gamma = -1.0   # no potential array: the generated one needs a finite gamma >= 0
+    assert L.kpm_build_hamiltonian(ctypes.byref(d), None, ctypes.byref(out)) == kpm.KPM_EINVAL
+    assert b"gamma" in L.kpm_last_error()
+    d.gamma = float("nan")
+    assert L.kpm_build_hamiltonian(ctypes.byref(d), None, ctypes.byref(out)) == kpm.KPM_EINVAL
     fake = ctypes.c_void_p(0x1000)
-    assert L.kpm_moments(None, fake, 1, 8, fake, None, 0, None) == kpm.KPM_EINVAL
+    assert L.kpm_moments(None, fake, 1, 8, fake, None, None) == kpm.KPM_EINVAL
+    opts = kpm.RunOpts()
+    opts.variant = kpm.PLAIN   # moments run the FULL or NODOT variant
+    assert L.kpm_moments(fake, fake, 1, 8, fake, ctypes.byref(opts), None) == kpm.KPM_EINVAL
+    opts.variant = kpm.FULL
+    assert L.kpm_moments(fake, fake, 1, 7, fake, ctypes.byref(opts), None) == kpm.KPM_EINVAL      # odd M
+    assert L.kpm_moments(fake, fake, 3, 8, fake, ctypes.byref(opts), None) == kpm.KPM_ENOTSUP     # R
+    assert L.kpm_moments(fake, ctypes.c_void_p(0x1008), 1, 8, fake, ctypes.byref(opts), None) == kpm.KPM_EINVAL
+    bad = kpm.SweepTuning(*[0] * 11)
+    bad.prefetch = 9
+    opts.tuning = ctypes.pointer(bad)   # a per-call tuning is validated like kpm_set_sweep_tuning
+    assert L.kpm_moments(fake, fake, 1, 8, fake, ctypes.byref(opts), None) == kpm.KPM_EINVAL
+    assert L.kpm_set_sweep_tuning(ctypes.byref(bad)) == kpm.KPM_EINVAL
+    plan = kpm.SweepPlan()
+    assert L.kpm_sweep_plan(None, 32, None, ctypes.byref(plan)) == kpm.KPM_EINVAL
     assert L.kpm_aug_spmmv(None, fake, fake, 1, 1.0, 0.0, 0.0, 0, None, None) == kpm.KPM_EINVAL
     assert L.kpm_dos(None, 1, 8, 0, 0.0, 1.0, 0.0, fake, 4, fake, None) == kpm.KPM_EINVAL
     assert L.kpm_dos(fake, 1, 8, 0, 0.0, 1.0, 0.0, fake, 0, fake, None) == kpm.KPM_EINVAL   # K = 0
@@ -86,3 +104,26 @@ def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(kpm, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError, match="not built"):
         kpm.lib()
+
+
+def test_struct_layouts_match_the_header():
+    # the ctypes mirrors of the header's structs: field names in header order
+    from paper_1410_5242_amd import kpm
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+
+    def fields(struct_end):
+        body = re.search(r"typedef struct[^{]*\{([^}]*)\}\s*" + struct_end + r"\s*;", text).group(1)
+        names = []
+        for decl in body.split(";"):
+            decl = decl.strip()
+            if not decl:
+                continue
+            for part in decl.split(","):
+                m = re.search(r"([A-Za-z_][A-Za-z_0-9]*)\s*(\[\d+\])?\s*$", part.strip())
+                names.append(m.group(1))
+        return names
+
+    for cls, name in ((kpm.LatticeDesc, "kpm_lattice_desc"), (kpm.RunOpts, "kpm_run_opts"),
+                      (kpm.SweepTuning, "kpm_sweep_tuning"), (kpm.BatchTuning, "kpm_batch_tuning"),
+                      (kpm.SweepPlan, "kpm_sweep_plan_info")):
+        assert [f[0] for f in cls._fields_] == fields(name), name

@@ -1,0 +1,213 @@
+"""GPU tests of the C ABI's options and ownership rules: the counter-generated
+potential, kpm_moments options (HIP-graph replay, host moments, the NODOT
+variant, a per-call tuning), the launch plan query, and calls that overlap on
+two streams (per-stream workspaces), each against the CPU oracle."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1410_5242_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL_C128 = 1e-12
+
+
+def kpm():
+    from paper_1410_5242_amd import kpm as K
+    return K
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def device():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    return torch.device("cuda:0")
+
+
+def oracle_problem(L, pot, periodic=(1, 1, 1)):
+    Ho = O.ti_hamiltonian(L, pot, periodic=periodic)
+    a, b = O.scaling(*O.gershgorin(Ho))
+    return Ho, a, b
+
+
+@pytest.mark.parametrize("L,gamma,seed", [((5, 4, 7), 2.0, 11), ((8, 8, 8), 1.0, 0), ((3, 3, 3), 0.0, 5)])
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_generated_potential_matches_oracle_generator(L, gamma, seed, dtype):
+    # kpm_lattice_desc without a potential array: V_n from the device's counter
+    # generator; the oracle draws the same numbers from its own implementation
+    say("generated potential", L, gamma, seed, dtype)
+    K = kpm()
+    H = K.build_hamiltonian(L, None, gamma=gamma, seed=seed, dtype=dtype)
+    pot = O.potential_counter(L, gamma, seed)
+    Ho, a, b = oracle_problem(L, pot)
+    rp, col, val = K.export_csr(H)
+    assert np.array_equal(rp, Ho.rowptr)
+    ref = Ho.val if dtype == "c128" else Ho.val.astype(np.complex64).astype(np.complex128)
+    # same entries per row (the library keeps its slot order, the oracle sorts columns)
+    for i in range(0, Ho.n, max(1, Ho.n // 97)):
+        s, e = rp[i], rp[i + 1]
+        o1, o2 = np.argsort(col[s:e]), np.argsort(Ho.col[s:e])
+        assert np.array_equal(col[s:e][o1], Ho.col[s:e][o2])
+        assert np.array_equal(val[s:e][o1], ref[s:e][o2])
+    assert H.a == pytest.approx(a, rel=1e-15) and H.b == pytest.approx(b, abs=1e-15)
+    if dtype == "c128":
+        v0 = inputs.phase_block(Ho.n, 2, 1)
+        mu = K.moments(H, torch.from_numpy(v0).cuda(), 64).cpu().numpy()
+        assert np.abs(mu - O.kpm_moments(Ho, a, b, v0, 64)).max() <= TOL_C128
+    H.close()
+
+
+def test_moments_graph_replays_match_eager_and_oracle():
+    # the 8^3 correctness workload (R = 1, M = 128): captured once, replayed with
+    # eager work and synchronisations between replays; each replay reads the start
+    # block anew, so changing its contents changes the result
+    K = kpm()
+    L, M = (8, 8, 8), 128
+    pot = inputs.potential(L, 1.0, 0)
+    Ho, a, b = oracle_problem(L, pot)
+    H = K.build_hamiltonian(L, pot)
+    blocks = [inputs.phase_block(Ho.n, 1, s) for s in (0, 1, 2)]
+    refs = [O.kpm_moments(Ho, a, b, v, M) for v in blocks]
+    V0 = torch.from_numpy(blocks[0]).cuda()
+    mu = torch.empty((1, M), dtype=torch.float64, device="cuda")
+    eager = K.moments(H, V0, M).cpu().numpy()
+    assert np.abs(eager - refs[0]).max() <= TOL_C128
+    for rep in range(6):
+        k = rep % 3
+        V0.copy_(torch.from_numpy(blocks[k]))
+        junk = torch.randn(1 << 16, device="cuda") * 3.0     # eager work between replays
+        mu.fill_(float("nan"))
+        K.moments(H, V0, M, mu=mu, graph=True)
+        torch.cuda.synchronize()
+        got = mu.cpu().numpy()
+        say("graph replay", rep, float(np.abs(got - refs[k]).max()), float(junk.sum()))
+        assert np.abs(got - refs[k]).max() <= TOL_C128
+        if k == 0:
+            assert np.array_equal(got, eager)      # same launches, same sums
+    # another M captures a new graph; the old key no longer matches
+    mu2 = torch.empty((1, 64), dtype=torch.float64, device="cuda")
+    K.moments(H, V0, 64, mu=mu2, graph=True)
+    V0.copy_(torch.from_numpy(blocks[0]))
+    K.moments(H, V0, 64, mu=mu2, graph=True)
+    assert np.abs(mu2.cpu().numpy() - refs[0][:, :64]).max() <= TOL_C128
+    H.close()
+
+
+@pytest.mark.parametrize("L,R", [((16, 16, 12), 32), ((10, 9, 7), 8)])
+def test_moments_graph_wide_blocks(L, R):
+    # the graph path on the lattice sweep (R = 32) and the staged-gather sweep
+    K = kpm()
+    M = 40
+    pot = inputs.potential(L, 1.5, 3)
+    Ho, a, b = oracle_problem(L, pot)
+    v0 = inputs.phase_block(Ho.n, R, 4)
+    ref = O.kpm_moments(Ho, a, b, v0, M)
+    H = K.build_hamiltonian(L, pot)
+    V0 = torch.from_numpy(v0).cuda()
+    mu = torch.empty((R, M), dtype=torch.float64, device="cuda")
+    eta = torch.empty((M, R, 2), dtype=torch.float64, device="cuda")
+    for rep in range(3):
+        mu.zero_()
+        K.moments(H, V0, M, mu=mu, eta=eta, graph=True, check=True)
+        torch.cuda.synchronize()
+        assert np.abs(mu.cpu().numpy() - ref).max() <= TOL_C128
+    ref_eta = O.kpm_eta(Ho, a, b, v0, M)
+    got_eta = eta.cpu().numpy()[..., 0] + 1j * eta.cpu().numpy()[..., 1]
+    assert np.abs(got_eta - ref_eta).max() <= TOL_C128
+    H.close()
+
+
+def test_moments_host_output_nodot_and_per_call_tuning():
+    K = kpm()
+    L, R, M = (12, 12, 8), 4, 48
+    pot = inputs.potential(L, 1.0, 9)
+    Ho, a, b = oracle_problem(L, pot)
+    v0 = inputs.phase_block(Ho.n, R, 9)
+    ref = O.kpm_moments(Ho, a, b, v0, M)
+    H = K.build_hamiltonian(L, pot)
+    V0 = torch.from_numpy(v0).cuda()
+    # host mu: filled in place, the call synchronises
+    host = np.full((R, M), np.nan)
+    K.moments(H, V0, M, mu=host)
+    assert np.abs(host - ref).max() <= TOL_C128
+    # NODOT: the recurrence without products; mu is not touched
+    mu = torch.full((R, M), 7.0, dtype=torch.float64, device="cuda")
+    K.moments(H, V0, M, mu=mu, variant="nodot", check=False)
+    torch.cuda.synchronize()
+    assert bool((mu == 7.0).all())
+    # a per-call tuning gives what the same process-wide tuning gives, bit for bit,
+    # and leaves the process-wide setting alone
+    before = K.get_sweep_tuning()
+    t = dict(gather=2, pencil=0, wg_per_cu=4)
+    per_call = K.moments(H, V0, M, tuning=t).cpu().numpy()
+    assert K.get_sweep_tuning() == before
+    try:
+        K.set_sweep_tuning(**t)
+        glob = K.moments(H, V0, M).cpu().numpy()
+    finally:
+        K.reset_sweep_tuning()
+    assert np.array_equal(per_call, glob)
+    assert np.abs(per_call - ref).max() <= TOL_C128
+    H.close()
+
+
+def test_sweep_plan_of_the_headline_lattice():
+    # 64^3, R = 32: one 4 x 4-site pencil per workgroup on the whole chip, dealt to
+    # the 8 dies as 2-D blocks of pencils (tile order 0), whole pencils, one half
+    K = kpm()
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    H = K.build_hamiltonian((64, 64, 64), None, gamma=1.0, seed=0)
+    p = K.sweep_plan(H, 32)
+    say("headline plan", p, "CUs", cus)
+    assert p["kernel"] == "lattice_kernel" and p["halves"] == 1 and p["pieces"] == 1
+    assert p["grid"] == min(256, cus - cus % 8)
+    if cus >= 256:
+        assert p["tile_order"] == 0
+    assert K.sweep_plan(H, 64)["halves"] == 2
+    g = K.sweep_plan(H, 8)
+    assert g["kernel"] == "gather_sweep_kernel" and g["pieces"] == -1
+    assert K.sweep_plan(H, 32, tuning={"lattice": 0})["kernel"] == "gather_sweep_kernel"
+    H.close()
+
+
+def test_two_streams_overlap_with_separate_workspaces():
+    # one Hamiltonian, two start blocks, two streams: kpm_moments and kpm_dot run
+    # concurrently without a synchronisation between the streams; each result
+    # matches the oracle (a shared workspace would mix the two runs)
+    K = kpm()
+    L, R, M = (16, 16, 16), 32, 64
+    pot = inputs.potential(L, 1.0, 21)
+    Ho, a, b = oracle_problem(L, pot)
+    vs = [inputs.phase_block(Ho.n, R, s) for s in (21, 22)]
+    refs = [O.kpm_moments(Ho, a, b, v, M) for v in vs]
+    H = K.build_hamiltonian(L, pot)
+    V = [torch.from_numpy(v).cuda() for v in vs]
+    x = [torch.from_numpy(v[:, 0].copy()).cuda() for v in vs]
+    y = [torch.from_numpy(v[:, 1].copy()).cuda() for v in vs]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    torch.cuda.synchronize()
+    mus, dots = [None, None], [None, None]
+    for rep in range(3):
+        for i in (0, 1):
+            with torch.cuda.stream(streams[i]):
+                mus[i] = K.moments(H, V[i], M, check=False, stream=streams[i])
+                dots[i] = K.dot(x[i], y[i], stream=streams[i])
+        torch.cuda.synchronize()
+        for i in (0, 1):
+            err = float(np.abs(mus[i].cpu().numpy() - refs[i]).max())
+            d = dots[i].cpu().numpy()
+            ref_d = O.block_dot(vs[i][:, 0], vs[i][:, 1])[0]
+            say("two streams", rep, i, err, abs(complex(d[0], d[1]) - ref_d))
+            assert err <= TOL_C128
+            assert abs(complex(d[0], d[1]) - ref_d) <= 1e-14
+    H.close()

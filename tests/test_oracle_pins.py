@@ -4,8 +4,10 @@ Every check here is independent of the oracle's own code path: a Kronecker
 construction of eq. "Ham", the Bloch-band closed form of the clean lattice,
 dense eigendecomposition, the diagonal (t = 0) closed form, the exact trace
 with an identity start block, the Chebyshev product identity checked against
-the direct recurrence, the sum rule and positivity of the Jackson kernel, and
-the code-balance numbers printed in the paper.
+the direct recurrence, the sum rule and positivity of the Jackson kernel, the
+closed form of the Lorentz-damped delta function and its Fejer limit, exactly
+rounded sums (math.fsum) for the pairwise scalar products, and the
+code-balance numbers printed in the paper.
 """
 import json
 import math
@@ -285,6 +287,52 @@ def test_jackson_kernel_properties():
     assert abs(gl[0] - 1.0) < 1e-15 and np.all(np.diff(gl) < 0)
 
 
+def _lorentz_cosine_sum(M, lam, phi):
+    """C(phi) = sum_{n<M} g_n cos(n phi) for g_n = sinh(lam (1 - n/M)) / sinh(lam), in closed
+    form: sinh(lam (1 - n/M)) = (e^lam q^n - e^-lam q^-n) / 2 with q = e^(-lam/M), and
+    sum_{n<M} z^n = (1 - z^M) / (1 - z) for z = q^(+-1) e^(i phi)."""
+    def geo(q):
+        z = q * np.exp(1j * phi)
+        return ((1.0 - z ** M) / (1.0 - z)).real
+    q = math.exp(-lam / M)
+    return (math.exp(lam) * geo(q) - math.exp(-lam) * geo(1.0 / q)) / (2.0 * math.sinh(lam))
+
+
+@pytest.mark.parametrize("M,lam", [(64, 4.0), (512, 4.0), (2000, 1.5)])
+def test_lorentz_delta_matches_closed_form(M, lam):
+    # exact moments of one eigenvalue at x0 = cos(t0): mu_n = cos(n t0).  With
+    # x = cos(t), 2 g_n cos(n t0) cos(n t) = g_n [cos(n (t + t0)) + cos(n (t - t0))], so
+    # rho(x) = [C(t + t0) + C(t - t0) - g_0] / (pi sin t), C the damped cosine sum
+    K = 4096
+    E = O.midpoint_grid(K, 1.0, 0.0)
+    th = np.arccos(E)
+    for x0 in (-0.7, 0.0, 0.3):
+        t0 = math.acos(x0)
+        mu = np.cos(np.arange(M) * t0)[None, :]
+        rho = O.dos(mu, O.lorentz(M, lam), 1.0, 0.0, E)
+        ref = (_lorentz_cosine_sum(M, lam, th + t0) + _lorentz_cosine_sum(M, lam, th - t0) - 1.0) / (
+            math.pi * np.sin(th))
+        assert np.abs(rho - ref).max() <= 1e-9 * np.abs(ref).max()
+        assert rho.min() > 0.0                      # the Lorentz kernel is positive
+        assert abs(E[np.argmax(rho)] - x0) < lam / M  # within the broadening width
+
+
+def test_lorentz_kernel_reduces_to_fejer():
+    # sinh(lam (1 - n/M)) / sinh(lam) = (1 - n/M) (1 + O(lam^2)): as lam -> 0 the
+    # Lorentz factors become the Fejer factors 1 - n/M, a positive kernel
+    for M in (16, 128, 2000):
+        n = np.arange(M)
+        fejer = 1.0 - n / M
+        assert np.abs(O.lorentz(M, 1e-5) - fejer).max() <= 1e-10
+        g = O.lorentz(M, 1e-3)
+        assert np.abs(g - fejer).max() <= 1e-6 and np.all(g <= fejer + 1e-15)
+    M, K = 256, 4096
+    E = O.midpoint_grid(K, 1.0, 0.0)
+    for x0 in (-0.4, 0.5):
+        mu = np.cos(np.arange(M) * np.arccos(x0))[None, :]
+        assert O.dos(mu, O.lorentz(M, 1e-6), 1.0, 0.0, E).min() > -1e-9
+
+
 def test_jackson_delta_is_positive_and_normalised():
     # exact moments of a single eigenvalue at x0: mu_n = T_n(x0)
     M, K = 256, 4096
@@ -388,3 +436,60 @@ def test_phase_block_counter_properties():
     assert chi2 < 50.0            # 15 degrees of freedom: p < 1e-5 for a fair generator
     # the moment estimate of a random-phase block: mu_0 = sum |v|^2 = 1 exactly per column
     assert abs(np.vdot(v[:, 0], v[:, 0]).real - 1.0) <= 1e-13
+
+
+# --------------------------------------------------------------------------
+# Scalar products: pairwise summation against exactly rounded sums
+# --------------------------------------------------------------------------
+def _fsum_c(z):
+    return complex(math.fsum(z.real.tolist()), math.fsum(z.imag.tolist()))
+
+
+def test_block_dot_is_within_the_pairwise_bound_at_a_million_rows():
+    # The oracle's scalar product must certify 1e-12 moments at N = 2^20 rows.
+    # Its products conj(x) y are rounded exactly as NumPy rounds them; math.fsum
+    # gives their exactly rounded sum, so the difference is the summation error
+    # alone, which for pairwise summation with leaves of 8 rows is below
+    # (7 + log2(N / 8)) u sum |x| |y| = 24 u (a running sum over these rows
+    # errs by about 10x more, 2e-14 to 3e-14 here)
+    N, R = 1 << 20, 2
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal((N, R)) + 1j * rng.standard_normal((N, R))
+    x /= np.sqrt((np.abs(x) ** 2).sum(axis=0))
+    y = x + 1e-3 * (rng.standard_normal((N, R)) + 1j * rng.standard_normal((N, R)))
+    u = 2.0 ** -53
+    for a, b in ((x, x), (y, x), (x, y)):
+        got = O.block_dot(a, b)
+        for r in range(R):
+            p = np.conj(a[:, r]) * b[:, r]
+            bound = 24 * u * np.abs(p).sum()
+            assert abs(got[r] - _fsum_c(p)) <= bound
+    # a random-phase unit block: every column's squared norm is 1 to 1e-15
+    v = O.phase_block_counter(N, 4, 9)
+    assert np.abs(O.block_dot(v, v) - 1.0).max() <= 1e-15
+
+
+def test_block_dot_small_cases():
+    # leaves of one to nine rows, a single row, conjugation of the bra
+    rng = np.random.default_rng(4)
+    for N in (1, 2, 7, 8, 9, 17, 1000):
+        x = rng.standard_normal((N, 3)) + 1j * rng.standard_normal((N, 3))
+        y = rng.standard_normal((N, 3)) + 1j * rng.standard_normal((N, 3))
+        got = O.block_dot(x, y)
+        for r in range(3):
+            assert abs(got[r] - np.vdot(x[:, r], y[:, r])) <= 1e-13 * max(1.0, np.abs(x[:, r] * y[:, r]).sum())
+    assert O.block_dot(np.array([1j]), np.array([1.0]))[0] == -1j
+
+
+def test_potential_counter_follows_the_published_generator():
+    # key = second SplitMix64 output of the seed; site n takes output n + 1 of the
+    # generator started at the key; V = gamma (u - 1/2) with u the top 53 bits / 2^53
+    seed, gamma = 12345, 2.5
+    key = O.splitmix64_sequence(seed, 2)[1]
+    outs = O.splitmix64_sequence(key, 6)
+    ref = [gamma * ((o >> 11) / 2.0 ** 53 - 0.5) for o in outs]
+    assert O.potential_counter((6, 1, 1), gamma, seed).tolist() == ref
+    v = O.potential_counter((50, 40, 30), 4.0, 7)
+    assert v.min() >= -2.0 and v.max() < 2.0
+    assert abs(v.mean()) < 0.02 and abs(v.var() - 16.0 / 12.0) < 0.02   # U[-2, 2): var = 4^2 / 12
+    assert np.abs(v - O.potential_counter((50, 40, 30), 4.0, 8)).max() > 1.0
