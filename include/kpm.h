@@ -189,6 +189,21 @@ kpm_status kpm_axpy(int32_t dtype, int64_t n, double alpha, const void* x, void*
 kpm_status kpm_scal(int32_t dtype, int64_t n, double alpha, void* x, void* stream);
 kpm_status kpm_dot(int32_t dtype, int64_t n, const void* x, const void* y, double* out, void* stream);
 
+/* kpm_dot for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same result, computed by the same kernels in the same order, so it equals
+ * kpm_dot bit for bit.  Its partial sums live in a 32 KiB array the library
+ * holds in each GPU's memory from load to process exit (2048 workgroup
+ * partials of two doubles: the dot grid never has more workgroups, so every
+ * n fits and no size is rejected).  The call allocates nothing: no hipMalloc,
+ * no hipFree, no allocating library routine; its first call on a device only
+ * looks up that device's array address.  Every call on one GPU shares the
+ * array: calls that overlap on one GPU (other streams, other threads) race
+ * and may return wrong sums; calls ordered on one stream are safe.  Nothing
+ * in the array needs clearing (each launch writes every partial it reads).
+ * Errors: as kpm_dot; KPM_EDEVICE if the array's address cannot be found. */
+kpm_status kpm_dot_noalloc(int32_t dtype, int64_t n, const void* x, const void* y, double* out, void* stream);
+
 /* Density of states per unit energy from moments (the reconstruction step
  * the paper leaves to the KPM literature):
  *   mubar_n = (1/R) sum_r mu[r][n]                 (stochastic trace)

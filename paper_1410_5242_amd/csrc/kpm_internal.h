@@ -273,6 +273,10 @@ hipError_t launch_dos_batched(const double* mu, int n_inst, int R, int ld, int M
 // given storage type; scalar products in FP64, out = sum conj(x_i) y_i
 // through part[naive_dot_partials()][2]); column r of an [n][R] block.
 int naive_dot_partials();
+// Device address, on the current device, of the library's file-scope array of
+// naive_dot_partials() x 2 doubles that kpm_dot_noalloc reduces through
+// (resolved on the first call per device, no allocation).
+hipError_t dot_scratch(double** out);
 hipError_t launch_axpy(int dtype, int64_t n, double alpha, const void* x, void* y, hipStream_t s);
 hipError_t launch_scal(int dtype, int64_t n, double alpha, void* x, hipStream_t s);
 hipError_t launch_dot(int dtype, int64_t n, const void* x, const void* y, double* part, double* out, hipStream_t s);

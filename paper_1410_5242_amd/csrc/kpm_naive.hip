@@ -10,6 +10,9 @@
 // before the products) and are reduced in two stages, per-workgroup
 // partials and one workgroup that sums them in index order, so a result
 // does not depend on timing.
+#include <mutex>
+#include <vector>
+
 #include "kpm_internal.h"
 
 namespace kpm {
@@ -187,9 +190,34 @@ hipError_t column_t(int64_t n, int R, int r, const void* V, void* v, hipStream_t
     return hipGetLastError();
 }
 
+// Partial sums of kpm_dot_noalloc: one array per GPU, held for the life of
+// the process.  Host code never passes this name to a kernel (on the host it
+// is a stand-in, not a device address); it resolves the device address once
+// per device with hipGetSymbolAddress and uses that.
+static __device__ __align__(256) double scratch[2 * kMaxBlocks];
+
+std::mutex g_scratch_lock;
+std::vector<double*> g_scratch_ptr;   // per device; nullptr until resolved
+
 }  // namespace
 
 int naive_dot_partials() { return kMaxBlocks; }
+
+hipError_t dot_scratch(double** out) {
+    *out = nullptr;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> g(g_scratch_lock);
+    if (static_cast<int>(g_scratch_ptr.size()) <= dev) g_scratch_ptr.resize(dev + 1, nullptr);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        if ((e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch))) != hipSuccess) return e;
+        g_scratch_ptr[dev] = static_cast<double*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
 
 hipError_t launch_axpy(int dtype, int64_t n, double alpha, const void* x, void* y, hipStream_t s) {
     return dtype == KPM_C128 ? axpy_t<double>(n, alpha, x, y, s) : axpy_t<float>(n, alpha, x, y, s);

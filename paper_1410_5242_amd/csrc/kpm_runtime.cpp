@@ -838,6 +838,20 @@ kpm_status kpm_dot(int32_t dtype, int64_t n, const void* x, const void* y, doubl
     return KPM_OK;
 }
 
+kpm_status kpm_dot_noalloc(int32_t dtype, int64_t n, const void* x, const void* y, double* out, void* stream) {
+    g_error.clear();
+    kpm_status st = blas1_args(dtype, n, {x, y});
+    if (st != KPM_OK) return st;
+    if (!out) return fail(KPM_EINVAL, "out is NULL");
+    // the same two kernels as kpm_dot; their partial sums go to the library's
+    // static array on this device (one workgroup's partial per slot: the grid
+    // never exceeds naive_dot_partials() workgroups, so every n fits)
+    double* part = nullptr;
+    KPM_HIP(dot_scratch(&part), "hipGetSymbolAddress(scratch)");
+    KPM_HIP(launch_dot(dtype, n, x, y, part, out, static_cast<hipStream_t>(stream)), "dot kernel");
+    return KPM_OK;
+}
+
 kpm_status kpm_stream(int32_t kind, void* c, const void* a, const void* b, double scalar, int64_t bytes,
                       int32_t wg_per_cu, int32_t nontemporal, void* stream) {
     g_error.clear();

@@ -84,7 +84,7 @@ EXPORTS = ("kpm_build_hamiltonian", "kpm_hamiltonian_info", "kpm_export_csr",
            "kpm_mlp_param_count", "kpm_mlp_set_params", "kpm_mlp_get_params", "kpm_mlp_get_grads",
            "kpm_mlp_forward", "kpm_mlp_backward", "kpm_mlp_adam_step", "kpm_mlp_train_step",
            "kpm_mlp_gemm_bf16", "kpm_dos_batched", "kpm_moment_features", "kpm_random_phase_block",
-           "kpm_moments_naive", "kpm_axpy", "kpm_scal", "kpm_dot", "kpm_site_block", "kpm_plane_wave_block",
+           "kpm_moments_naive", "kpm_axpy", "kpm_scal", "kpm_dot", "kpm_dot_noalloc", "kpm_site_block", "kpm_plane_wave_block",
            "kpm_lanczos_bounds", "kpm_set_scaling", "kpm_stream",
            "kpm_last_error", "kpm_version")
 
@@ -120,6 +120,8 @@ def lib():
     L.kpm_scal.argtypes = [i32, i64, dbl, vp, vp]
     L.kpm_dot.restype = ctypes.c_int
     L.kpm_dot.argtypes = [i32, i64, vp, vp, vp, vp]
+    L.kpm_dot_noalloc.restype = ctypes.c_int
+    L.kpm_dot_noalloc.argtypes = [i32, i64, vp, vp, vp, vp]
     L.kpm_dos.restype = ctypes.c_int
     L.kpm_dos.argtypes = [vp, i32, i32, i32, dbl, dbl, dbl, vp, i32, vp, vp]
     L.kpm_set_sweep_tuning.restype = ctypes.c_int
@@ -370,6 +372,18 @@ def dot(x: torch.Tensor, y: torch.Tensor, out: torch.Tensor | None = None, strea
     if out is None:
         out = torch.empty(2, dtype=torch.float64, device=x.device)
     _check(lib().kpm_dot(dt, x.numel(), _dptr(x), _dptr(y), _dptr(out), _stream(stream)))
+    return out
+
+
+def dot_noalloc(x: torch.Tensor, y: torch.Tensor, out: torch.Tensor, stream=None) -> torch.Tensor:
+    """kpm_dot_noalloc: kpm_dot through the library's static per-GPU partials array (allocates
+    nothing; `out` is a caller-provided float64 device tensor of 2 elements)."""
+    dt = _blas1_vec(x)
+    if _blas1_vec(y) != dt or x.numel() != y.numel():
+        raise ValueError("x and y must have the same dtype and length")
+    if out.dtype != torch.float64 or out.numel() < 2 or not out.is_cuda:
+        raise ValueError("out must be a float64 device tensor with 2 elements")
+    _check(lib().kpm_dot_noalloc(dt, x.numel(), _dptr(x), _dptr(y), _dptr(out), _stream(stream)))
     return out
 
 
