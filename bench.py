@@ -79,30 +79,94 @@ def traffic_record(kernel: str, workload: str):
     return rec.get("hbm_bytes_per_launch")
 
 
+def _oracle_sweeps_rate(Ho, a, b, v0, target_s, max_sweeps=512):
+    """Seconds per sweep of the oracle's blocked recurrence, from as many sweeps as fit in about
+    target_s (at least one, at most max_sweeps); returns (sweeps, seconds)."""
+    import oracle as O
+    t0 = time.perf_counter()
+    O.kpm_eta(Ho, a, b, v0, 2)                 # one sweep (with the first touch of its buffers)
+    t1 = time.perf_counter() - t0
+    sweeps = int(max(1, min(max_sweeps, target_s / max(t1, 1e-3))))
+    t0 = time.perf_counter()
+    O.kpm_eta(Ho, a, b, v0, 2 * sweeps)
+    return sweeps, time.perf_counter() - t0
+
+
+def host_cores() -> dict:
+    aff = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return {"cpu_count": os.cpu_count(), "affinity": aff, "OMP_NUM_THREADS": os.environ.get("OMP_NUM_THREADS")}
+
+
 def cpu_baseline(L, gamma, R, dtype, target_s=15.0):
-    """Time the plain CPU oracle on a bounded number of sweeps of the same workload."""
-    import numpy as np
+    """Time the plain CPU oracle on a bounded number of sweeps of the same workload, on all the
+    threads the process may use (OMP_NUM_THREADS, else every core it may run on), then on one."""
     import oracle as O
     from paper_1410_5242_amd import inputs
     pot = inputs.potential(L, gamma, 0)
     Ho = O.ti_hamiltonian(L, pot)
     a, b = O.scaling(*O.gershgorin(Ho))
     v0 = inputs.phase_block(Ho.n, R, 0)
-    O.kpm_eta(Ho, a, b, v0, 2)                 # first touch of the oracle's buffers
-    t0 = time.perf_counter()
-    O.kpm_eta(Ho, a, b, v0, 8)
-    t1 = (time.perf_counter() - t0) / 4.0      # per sweep
-    sweeps = int(max(1, min(512, target_s / max(t1, 1e-3))))
-    t0 = time.perf_counter()
-    O.kpm_eta(Ho, a, b, v0, 2 * sweeps)
-    dt = time.perf_counter() - t0
     Sd = 16  # the oracle always runs in complex128
     bps = sweep_bytes(Ho.n, 13 * Ho.n, R, Sd)
+    cores = host_cores()
+    threads = int(cores["OMP_NUM_THREADS"] or cores["affinity"])
+    O.set_lib_threads(threads)
     threads = O.lib_threads()
+    sweeps, dt = _oracle_sweeps_rate(Ho, a, b, v0, target_s)
+    O.set_lib_threads(1)
+    sweeps1, dt1 = _oracle_sweeps_rate(Ho, a, b, v0, target_s / 3)
+    O.set_lib_threads(threads)
     return {"value": round(bps * sweeps / dt / 1e9, 3), "unit": "GB/s", "cores": threads,
             "kind": "oracle",
             "sample": f"{sweeps} sweeps (M={2 * sweeps}) of the same lattice, R and seed, complex128, "
-                      f"{dt:.2f} s; Gflop/s {sweep_flops(Ho.n, R) * sweeps / dt / 1e9:.2f}"}
+                      f"{dt:.2f} s on {threads} threads; Gflop/s {sweep_flops(Ho.n, R) * sweeps / dt / 1e9:.2f}",
+            "host": cores,
+            "single_thread": {"value": round(bps * sweeps1 / dt1 / 1e9, 3), "unit": "GB/s", "cores": 1,
+                              "sample": f"{sweeps1} sweeps, {dt1:.2f} s"}}
+
+
+def cpu_oracle_subsets(target_s=8.0):
+    """The oracle on bounded subsets of the other workloads, extrapolated linearly (stated per entry):
+    the 128 x 128 x 64 precision lattice (complex128, per sweep), the batched family (R = 8, M = 512,
+    per instance) and the learned family's truth runs (R = 16, M = 2048, per instance)."""
+    import numpy as np
+    import oracle as O
+    from paper_1410_5242_amd import inputs, learned
+    out = {"threads": O.lib_threads()}
+    L, R = (128, 128, 64), 32
+    pot = inputs.potential(L, 2.0, 0)
+    t0 = time.perf_counter()
+    Ho = O.ti_hamiltonian(L, pot)
+    a, b = O.scaling(*O.gershgorin(Ho))
+    build = time.perf_counter() - t0
+    v0 = inputs.phase_block(Ho.n, R, 0)
+    sweeps, dt = _oracle_sweeps_rate(Ho, a, b, v0, 2 * target_s, max_sweeps=20)
+    bps = sweep_bytes(Ho.n, 13 * Ho.n, R, 16)
+    out["precision_128x128x64_r32_m2000"] = {
+        "sample": f"{sweeps} sweeps", "seconds_per_sweep": round(dt / sweeps, 4), "GBps": round(bps * sweeps / dt / 1e9, 2),
+        "build_s": round(build, 2), "full_run_s_extrapolated": round(dt / sweeps * 1000, 1)}
+    del Ho, v0
+    for name, fam, Rf, M, n_total in (
+            ("batched_512_r8_m512", inputs.instance_family(512, (12, 16, 20, 24), 4.0, 0), 8, 512, 512),
+            ("learned_truth_r16_m2048", learned.family(21000, learned.TRAIN_SEED), 16, 2048, 21000)):
+        t_inst, done, t_start = [], 0, time.perf_counter()
+        for f in fam:
+            Hf = O.ti_hamiltonian(f["L"], inputs.potential(f["L"], f["gamma"], f["pot_seed"]))
+            af, bf = O.scaling(*O.gershgorin(Hf))
+            vf = inputs.phase_block(Hf.n, Rf, f["vec_seed"])
+            t0 = time.perf_counter()
+            O.kpm_eta(Hf, af, bf, vf, M)
+            t_inst.append(time.perf_counter() - t0)
+            done += 1
+            if time.perf_counter() - t_start > target_s:
+                break
+        mean_n = float(np.mean([4 * f["L"][0] ** 3 for f in fam]))
+        done_n = float(np.mean([4 * f["L"][0] ** 3 for f in fam[:done]]))
+        per = float(np.mean(t_inst)) * mean_n / done_n
+        out[name] = {"sample": f"first {done} of {n_total} instances at full M, R", "seconds_per_instance": round(per, 3),
+                     "all_instances_s_extrapolated": round(per * n_total, 1),
+                     "note": "per-instance time scaled by the family's mean N over the sample's mean N"}
+    return out
 
 
 def leg_precision(log_fn=None):
@@ -135,13 +199,23 @@ def leg_precision(log_fn=None):
         times[dt] = ev[0].elapsed_time(ev[1]) / 1e3
         mus[dt], rhos[dt] = mu.cpu().numpy(), rho.cpu().numpy()
         Sd = 16 if dt == "c128" else 8
-        bps = sweep_bytes(H.N, 13 * H.N, R, Sd, 0 if kpm.sweep_kernel(H, R) == "lattice_kernel" else 4)
+        bps = sweep_bytes(H.N, 13 * H.N, R, Sd)
         res[dt] = {"seconds": round(times[dt], 4), "GBps": round(bps * (M // 2) / times[dt] / 1e9, 1),
                    "sweep_kernel": kpm.sweep_kernel(H, R), "autotuned": tuned}
         kpm.reset_sweep_tuning()
         H.close()
         del V0
     dE = 2.0 * a / K
+    # against the FP64 oracle: its first 400 moments (200 sweeps) of this lattice, seed and start
+    # block, stored by tests/golden/make_oracle_moments.py
+    gold = os.path.join(ROOT, "tests", "golden", "ti128x128x64_g2_r32_m400_mu.npy")
+    if os.path.exists(gold):
+        ref = np.load(gold, allow_pickle=False)
+        Mp = ref.shape[1]
+        res["vs_oracle_prefix"] = {"moments": Mp, "sweeps": Mp // 2,
+                                   "c128_max_abs_mu_error": float(np.abs(mus["c128"][:, :Mp] - ref).max()),
+                                   "c64_max_abs_mu_error": float(np.abs(mus["c64"][:, :Mp] - ref).max()),
+                                   "c64_mean_abs_mu_error": float(np.abs(mus["c64"][:, :Mp] - ref).mean())}
     d = np.abs(mus["c64"] - mus["c128"])
     res["max_abs_mu_error"] = float(d.max())
     res["mean_abs_mu_error"] = float(d.mean())
@@ -150,6 +224,90 @@ def leg_precision(log_fn=None):
     res["within_bound"] = bool(res["max_abs_mu_error"] <= 1e-5 and res["dos_l1_error"] <= 1e-5)
     res["speedup_c64"] = round(times["c128"] / times["c64"], 3)
     return res
+
+
+def leg_stream(nbytes: int = 4 << 30, reps: int = 5):
+    """Attainable HBM bandwidth b, the bound the paper measures for each machine (Table
+    "tab:architectures", eq. "eq:roofline_mem"): the library's STREAM read, copy and triad kernels
+    on arrays 16 times the last-level cache, best launch over workgroups per CU and load / store
+    hint.  b is the highest of the three: what the memory delivers to a kernel of ours."""
+    import torch
+    from paper_1410_5242_amd import kpm
+    n = nbytes // 8
+    a = torch.full((n,), 1.0, dtype=torch.float64, device="cuda")
+    b = torch.full((n,), 2.0, dtype=torch.float64, device="cuda")
+    c = torch.empty_like(a)
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    part = torch.zeros(cus * 8, dtype=torch.float64, device="cuda")
+    out = {"workload": f"{nbytes >> 30} GiB FP64 arrays, 256-thread workgroups, best of {reps} launches per shape; "
+                       "read moves 1x, copy 2x, triad 3x the array bytes", "points": []}
+    best = {}
+    for kind, traffic in (("read", nbytes), ("copy", 2 * nbytes), ("triad", 3 * nbytes)):
+        for wg in (1, 2, 4, 8):
+            for nt in (False, True):
+                if kind == "read":
+                    part.zero_()
+                    args = (kind, part, a, None, 0.0, wg, nt)
+                else:
+                    args = (kind, c, a, b if kind == "triad" else None, 3.0, wg, nt)
+                kpm.stream_kernel(*args)
+                ts = []
+                for _ in range(reps):
+                    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+                    ev[0].record()
+                    kpm.stream_kernel(*args)
+                    ev[1].record()
+                    torch.cuda.synchronize()
+                    ts.append(ev[0].elapsed_time(ev[1]) * 1e-3)
+                gbs = traffic / min(ts) / 1e9
+                out["points"].append({"kind": kind, "wg_per_cu": wg, "nontemporal": nt, "GBps": round(gbs, 1)})
+                if gbs > best.get(kind, {"GBps": 0.0})["GBps"]:
+                    best[kind] = {"GBps": round(gbs, 1), "wg_per_cu": wg, "nontemporal": nt}
+                if kind == "read" and float(part.sum().item()) != float(n):
+                    raise RuntimeError("STREAM read kernel summed wrong values")
+        if kind != "read":
+            expect = 1.0 if kind == "copy" else 7.0
+            if not bool(torch.all(c == expect).item()):
+                raise RuntimeError(f"STREAM {kind} kernel wrote wrong values")
+    for k in ("read", "copy", "triad"):
+        out[k] = best[k]
+    out["b_GBps"] = max(best[k]["GBps"] for k in ("read", "copy", "triad"))
+    out["b_copy_GBps"] = best["copy"]["GBps"]
+    del a, b, c, part
+    return out
+
+
+def leg_small(reps: int = 50):
+    """The small correctness workload timed: 8 x 8 x 8 lattice (N = 2048), gamma = 1, R = 1, M = 128,
+    complex128 (64 sweeps, launch-bound): kpm_moments launched op by op against its launch sequence
+    captured once in a HIP graph and replayed."""
+    import numpy as np
+    import torch
+    from paper_1410_5242_amd import inputs, kpm
+    L, R, M = (8, 8, 8), 1, 128
+    H = kpm.build_hamiltonian(L, inputs.potential(L, 1.0, 0))
+    V0 = torch.from_numpy(inputs.phase_block(H.N, R, 0)).cuda()
+    mu_e = kpm.moments(H, V0, M, check=False).cpu().numpy()
+    mu = torch.empty((R, M), dtype=torch.float64, device="cuda")
+    kpm.moments(H, V0, M, mu=mu, check=False, graph=True)
+    torch.cuda.synchronize()
+    same = bool(np.array_equal(mu.cpu().numpy(), mu_e))
+    out = {"workload": f"TI 8x8x8 periodic (N={H.N}), gamma=1, R={R}, M={M}, complex128; {reps} back-to-back calls, "
+                       "device-resident mu, one synchronisation at the end", "graph_equals_eager": same,
+           "sweep_kernel": kpm.sweep_kernel(H, R)}
+    for name, graph in (("eager", False), ("graph", True)):
+        for _ in range(3):
+            kpm.moments(H, V0, M, mu=mu, check=False, graph=graph)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            kpm.moments(H, V0, M, mu=mu, check=False, graph=graph)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        out[name] = {"us_per_call": round(dt * 1e6, 1), "us_per_sweep": round(dt * 1e6 / (M // 2), 2)}
+    out["graph_speedup"] = round(out["eager"]["us_per_call"] / out["graph"]["us_per_call"], 2)
+    H.close()
+    return out
 
 
 def leg_batched():
@@ -213,7 +371,7 @@ def leg_variants(sweeps: int = 10):
         W = kpm.random_phase_block(N, R, 2, "c128")
         eta = torch.zeros((2, R, 2), dtype=torch.float64, device="cuda")
         kernel = kpm.sweep_kernel(H, R)
-        Si = 0 if kernel == "lattice_kernel" else 4
+        Si = 4   # the paper's model bytes for every kernel (the lattice sweep reads no indices)
         for var in ("full", "nodot", "plain"):
             e = eta if var == "full" else None
             kpm.aug_spmmv(H, V, W, 2.0 / H.a, -2.0 * H.b / H.a, -1.0, var, e)
@@ -244,8 +402,7 @@ def leg_ladder(steps: int = 200, repeats: int = 3):
     step (one moment pair): the naive algorithm (one SpMV and five BLAS-1 calls per step, one
     vector at a time), the fused sweep at R = 1 (the vector-at-a-time "throughput mode"), and
     the blocked fused sweep at R = 32.  Bytes per step and vector from the traffic model of
-    Table "kpm_analysis" (naive) and of the fused algorithms (index bytes only where the
-    kernel reads them)."""
+    Table "kpm_analysis" (naive) and of the fused algorithms, index bytes included."""
     import time
     import torch
     from paper_1410_5242_amd import autotune, inputs, kpm
@@ -282,8 +439,7 @@ def leg_ladder(steps: int = 200, repeats: int = 3):
     t_block = timed(lambda: kpm.moments(H, VR, M, check=False)) / steps / R
     kernR = kpm.sweep_kernel(H, R)
     kpm.reset_sweep_tuning()
-    Si1 = 0 if kern1 == "lattice_kernel" else 4
-    SiR = 0 if kernR == "lattice_kernel" else 4
+    Si1 = SiR = 4   # the paper's model bytes (index bytes counted for every kernel)
     stages = [
         ("naive (SpMV + axpy, scal, axpy, nrm2, dot)", "R=1", t_naive, nnz * (Sd + 4) + 13 * N * Sd),
         ("fused sweep, one vector at a time", f"R=1, {kern1}", t_fused1, nnz * (Sd + Si1) + 3 * N * Sd),
@@ -477,9 +633,10 @@ def main():
                     help="short run for hardware counters: a 1 GiB device copy (the calibration kernel "
                          "of known traffic) and --probe-sweeps fused sweeps of the workload")
     ap.add_argument("--probe-sweeps", type=int, default=8)
-    ap.add_argument("--legs", default="variants,ladder,precision,batched,spectral,slab,bounds,time_to_dos",
-                    help="extra measurements after the headline step: any of variants, precision, batched, "
-                         "time_to_dos (comma separated), or none")
+    ap.add_argument("--legs", default="small,variants,ladder,precision,batched,spectral,slab,bounds,time_to_dos,"
+                                      "oracle_subsets",
+                    help="extra measurements after the headline step (comma separated): any of small, variants, "
+                         "ladder, precision, batched, spectral, slab, bounds, time_to_dos, oracle_subsets; or none")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU sharding is a design, "
@@ -546,10 +703,11 @@ def main():
 
     sweeps_per_step = M // 2
     nnz = 13 * N
-    # the lattice kernel stores the matrix structure implicitly: no index bytes
-    Si = 0 if sweep_kernel == "lattice_kernel" else 4
-    bps = sweep_bytes(N, nnz, R, Sd, Si)
-    bps_crs = sweep_bytes(N, nnz, R, Sd, 4)
+    # algorithmic bytes: the paper's minimum traffic of the blocked sweep with CRS / SELL
+    # storage, Nnz (S_d + S_i) + 3 R S_d N; the lattice kernel reads no column indices, so the
+    # bytes it must move are the same with S_i = 0 (reported beside it)
+    bps = sweep_bytes(N, nnz, R, Sd, 4)
+    bps_stored = sweep_bytes(N, nnz, R, Sd, 0 if sweep_kernel == "lattice_kernel" else 4)
     fps = sweep_flops(N, R)
     value = bps * sweeps_per_step / (ms_per_step * 1e-3) / 1e9
     gflops = fps * sweeps_per_step / (ms_per_step * 1e-3) / 1e9
@@ -576,7 +734,7 @@ def main():
                         f"gamma={gamma}, R={R}, M={M}, {dtype}, Jackson DOS on {K} energies",
             "sweeps_per_step": sweeps_per_step,
             "bytes_per_sweep": bps,
-            "bytes_per_sweep_crs_model": bps_crs,
+            "bytes_per_sweep_kernel_minimum": bps_stored,
             "flops_per_sweep": fps,
         },
         "pct_hbm_peak": round(100.0 * value / HBM_PEAK_GBS, 2),
@@ -605,18 +763,35 @@ def main():
     kpm.reset_sweep_tuning()
     H.close()
     del V0
+    log("[bench] attainable bandwidth (STREAM copy / triad)")
+    out["stream"] = leg_stream()
+    torch.cuda.empty_cache()
+    b_meas = out["stream"]["b_GBps"]
+    out["roofline"]["measured_b_GBps"] = b_meas
+    out["roofline"]["frac_of_measured_b"] = round(achieved / b_meas, 4)
+    out["roofline"]["measured_b_copy_GBps"] = out["stream"]["b_copy_GBps"]
+    out["pct_of_measured_b"] = round(100.0 * value / b_meas, 2)
     legs = [x for x in args.legs.split(",") if x and x != "none"]
-    for name, fn in (("variants", leg_variants), ("ladder", leg_ladder), ("precision", leg_precision),
-                     ("batched", leg_batched), ("spectral", leg_spectral), ("slab", leg_slab), ("bounds", leg_bounds),
-                     ("time_to_dos", leg_time_to_dos)):
+    for name, fn in (("small", leg_small), ("variants", leg_variants), ("ladder", leg_ladder),
+                     ("precision", leg_precision), ("batched", leg_batched), ("spectral", leg_spectral),
+                     ("slab", leg_slab), ("bounds", leg_bounds), ("time_to_dos", leg_time_to_dos)):
         if name in legs:
             log(f"[bench] leg {name}")
             out[name] = fn()
             torch.cuda.synchronize()
             torch.cuda.empty_cache()
+    # fractions of the measured bandwidth b beside those of the 8 TB/s peak
+    for rec in [out.get("precision", {}).get(d, {}) for d in ("c128", "c64")] + [out.get("batched", {})] + \
+            out.get("slab", {}).get("points", []):
+        for key in ("GBps", "GBps_paper_model"):
+            if key in rec:
+                rec[f"pct_of_measured_b{key[4:]}"] = round(100.0 * rec[key] / b_meas, 1)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(L, gamma, R, dtype, args.cpu_target_s)
+        if "oracle_subsets" in legs:
+            log("[bench] oracle on subsets of the other workloads")
+            out["cpu_baseline"]["subsets"] = cpu_oracle_subsets()
     print(json.dumps(out), flush=True)
 
 

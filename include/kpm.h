@@ -523,16 +523,22 @@ kpm_status kpm_mlp_gemm_bf16(const uint16_t* A, const uint16_t* B, int32_t M, in
                              int32_t trans_b, float* C, void* stream);
 
 /* Attainable-bandwidth reference for the roofline (the paper bounds every
- * kernel by a measured copy bandwidth b, Table "tab:architectures" and eq.
- * "eq:roofline_mem"): STREAM-style kernels over `bytes` (a multiple of 16)
- * of 16-byte-aligned device arrays,
+ * kernel by a measured attainable bandwidth b, Table "tab:architectures" and
+ * eq. "eq:roofline_mem"): STREAM-style kernels over `bytes` (a multiple of
+ * 16) of 16-byte-aligned device arrays,
  *   KPM_STREAM_COPY:   c = a              (traffic 2 x bytes)
  *   KPM_STREAM_TRIAD:  c = a + scalar b   (FP64 elements; traffic 3 x bytes)
- * with wg_per_cu workgroups of 256 threads per compute unit (1 .. 32), each
- * thread keeping four 16-byte loads in flight, and non-temporal stores when
- * `nontemporal` is nonzero.  c must not overlap a or b; b is unused by copy.
- * Errors: KPM_EINVAL. */
-enum { KPM_STREAM_COPY = 0, KPM_STREAM_TRIAD = 1 };
+ *   KPM_STREAM_READ:   c[g] = sum of the FP64 values of a that workgroup g
+ *                      read (traffic 1 x bytes); c must hold one double per
+ *                      workgroup, at most (compute units x wg_per_cu), and
+ *                      the sum of c[0 .. grid-1] is the sum of a's values
+ *                      (c beyond the grid is not written)
+ * with wg_per_cu workgroups of 256 threads per compute unit (1 .. 32; fewer
+ * when the array has fewer 4 KiB pieces than that), each thread keeping four
+ * (read: eight) 16-byte loads in flight.  `nontemporal` nonzero: copy and
+ * triad store, and read loads, with the non-temporal hint.  c must not
+ * overlap a or b; b is unused by copy and read.  Errors: KPM_EINVAL. */
+enum { KPM_STREAM_COPY = 0, KPM_STREAM_TRIAD = 1, KPM_STREAM_READ = 2 };
 kpm_status kpm_stream(int32_t kind, void* c, const void* a, const void* b, double scalar, int64_t bytes,
                       int32_t wg_per_cu, int32_t nontemporal, void* stream);
 

@@ -44,6 +44,8 @@ def lib():
         L.oracle_kpm_direct.argtypes = L.oracle_kpm_eta.argtypes
         L.oracle_threads.restype = ctypes.c_int
         L.oracle_threads.argtypes = []
+        L.oracle_set_threads.restype = None
+        L.oracle_set_threads.argtypes = [ctypes.c_int]
         L.oracle_splitmix64_next.restype = ctypes.c_uint64
         L.oracle_splitmix64_next.argtypes = [p]
         L.oracle_phase_block.restype = None
@@ -97,6 +99,11 @@ def block_dot(x: np.ndarray, y: np.ndarray) -> np.ndarray:
 def lib_threads() -> int:
     """OpenMP threads the oracle's row loops run on."""
     return int(lib().oracle_threads())
+
+
+def set_lib_threads(n: int) -> None:
+    """Run the oracle's later row loops on n OpenMP threads (results do not depend on n)."""
+    lib().oracle_set_threads(int(n))
 
 
 def _ptr(a: np.ndarray):

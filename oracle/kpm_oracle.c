@@ -30,6 +30,11 @@ typedef double complex zc;
 /* Number of OpenMP threads the row loops use. */
 int oracle_threads(void) { return omp_get_max_threads(); }
 
+/* Set the number of OpenMP threads of later row loops (n >= 1).  Results do
+ * not depend on it: every row and every column sum is computed by one thread
+ * in a fixed order. */
+void oracle_set_threads(int n) { if (n >= 1) omp_set_num_threads(n); }
+
 /* ------------------------------------------------------------------------- */
 /* Dirac matrices of the topological-insulator Hamiltonian (eq. "Ham").      */
 /* Orbital index o = 2*tau + s: the first Kronecker factor (tau) is the      */

@@ -855,7 +855,8 @@ kpm_status kpm_dot_noalloc(int32_t dtype, int64_t n, const void* x, const void* 
 kpm_status kpm_stream(int32_t kind, void* c, const void* a, const void* b, double scalar, int64_t bytes,
                       int32_t wg_per_cu, int32_t nontemporal, void* stream) {
     g_error.clear();
-    if (kind != KPM_STREAM_COPY && kind != KPM_STREAM_TRIAD) return fail(KPM_EINVAL, "unknown stream kernel");
+    if (kind != KPM_STREAM_COPY && kind != KPM_STREAM_TRIAD && kind != KPM_STREAM_READ)
+        return fail(KPM_EINVAL, "unknown stream kernel");
     if (bytes < 0 || bytes % 16 != 0) return fail(KPM_EINVAL, "bytes must be a non-negative multiple of 16");
     if (wg_per_cu < 1 || wg_per_cu > 32) return fail(KPM_EINVAL, "wg_per_cu must be in [1, 32]");
     if (bytes == 0) return KPM_OK;
@@ -864,9 +865,11 @@ kpm_status kpm_stream(int32_t kind, void* c, const void* a, const void* b, doubl
     for (const void* p : {static_cast<const void*>(c), a, triad ? b : a})
         if (reinterpret_cast<uintptr_t>(p) % 16 != 0) return fail(KPM_EINVAL, "arrays must be 16-byte aligned");
     const char* cc = static_cast<const char*>(c);
+    // the read kernel writes one double per workgroup, the others `bytes`
+    const int64_t c_bytes = kind == KPM_STREAM_READ ? static_cast<int64_t>(device_cus()) * wg_per_cu * 8 : bytes;
     auto overlap = [&](const void* x) {
         const char* xc = static_cast<const char*>(x);
-        return xc < cc + bytes && cc < xc + bytes;
+        return xc < cc + c_bytes && cc < xc + bytes;
     };
     if (overlap(a) || (triad && overlap(b))) return fail(KPM_EINVAL, "c overlaps an input");
     KPM_HIP(launch_stream(kind, nontemporal ? 1 : 0, c, a, b, scalar, bytes / 16, wg_per_cu,

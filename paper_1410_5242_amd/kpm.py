@@ -685,15 +685,20 @@ def gemm_bf16(A: torch.Tensor, B: torch.Tensor, trans_a: bool = False, trans_b: 
     return C
 
 
-STREAM_COPY, STREAM_TRIAD = 0, 1
+STREAM_COPY, STREAM_TRIAD, STREAM_READ = 0, 1, 2
 
 
 def stream_kernel(kind: str, c: torch.Tensor, a: torch.Tensor, b: torch.Tensor | None = None, scalar: float = 3.0,
-                  wg_per_cu: int = 4, nontemporal: bool = True, stream=None):
-    """kpm_stream: STREAM copy (c = a) or triad (c = a + scalar b, FP64) over the bytes of c."""
-    k = {"copy": STREAM_COPY, "triad": STREAM_TRIAD}[kind]
-    nbytes = c.numel() * c.element_size()
-    if a.numel() * a.element_size() != nbytes or (b is not None and b.numel() * b.element_size() != nbytes):
+                  wg_per_cu: int = 1, nontemporal: bool = True, stream=None):
+    """kpm_stream: STREAM copy (c = a) or triad (c = a + scalar b, FP64) over the bytes of c, or
+    read: per-workgroup sums of a's FP64 values into c (c needs compute units x wg_per_cu doubles)."""
+    k = {"copy": STREAM_COPY, "triad": STREAM_TRIAD, "read": STREAM_READ}[kind]
+    nbytes = a.numel() * a.element_size()
+    if k == STREAM_READ:
+        cus = torch.cuda.get_device_properties(c.device).multi_processor_count
+        if c.dtype != torch.float64 or c.numel() < cus * wg_per_cu:
+            raise ValueError(f"read needs a float64 c of at least {cus * wg_per_cu} elements")
+    elif c.numel() * c.element_size() != nbytes or (b is not None and b.numel() * b.element_size() != nbytes):
         raise ValueError("arrays must have the same size in bytes")
     _check(lib().kpm_stream(k, _dptr(c), _dptr(a), _dptr(b) if b is not None else None, float(scalar), nbytes,
                             int(wg_per_cu), 1 if nontemporal else 0, _stream(stream)))

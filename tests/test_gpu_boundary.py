@@ -211,3 +211,39 @@ def test_two_streams_overlap_with_separate_workspaces():
             assert err <= TOL_C128
             assert abs(complex(d[0], d[1]) - ref_d) <= 1e-14
     H.close()
+
+
+@pytest.mark.parametrize("kind", ["copy", "triad"])
+@pytest.mark.parametrize("n", [2, 518, 3 * (1 << 20) + 14])
+@pytest.mark.parametrize("wg,nt", [(1, False), (2, True), (8, True)])
+def test_stream_kernels_write_every_unit(kind, n, wg, nt):
+    # the attainable-bandwidth kernels on lengths that leave partial unroll groups and
+    # grids smaller than the device; integer-valued inputs make the triad exact
+    K = kpm()
+    say("stream", kind, n, wg, nt)
+    a = torch.arange(n, dtype=torch.float64, device="cuda")
+    b = torch.arange(n, dtype=torch.float64, device="cuda") * 2.0 - 5.0
+    c = torch.full((n,), float("nan"), dtype=torch.float64, device="cuda")
+    K.stream_kernel(kind, c, a, b if kind == "triad" else None, 3.0, wg_per_cu=wg, nontemporal=nt)
+    torch.cuda.synchronize()
+    expect = a if kind == "copy" else a + 3.0 * b
+    assert torch.equal(c, expect)
+    # a length that is not a whole number of 16-byte units is refused
+    with pytest.raises(K.KPMError):
+        K.stream_kernel(kind, c[:n - 1], a[:n - 1], b[:n - 1] if kind == "triad" else None)
+
+
+@pytest.mark.parametrize("n", [2, 518, 3 * (1 << 20) + 14])
+@pytest.mark.parametrize("wg,nt", [(1, False), (1, True), (4, True)])
+def test_stream_read_kernel_sums_every_unit(n, wg, nt):
+    # the read-only bandwidth kernel: per-workgroup sums of integer values, exact in FP64
+    K = kpm()
+    say("stream read", n, wg, nt)
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    a = torch.arange(n, dtype=torch.float64, device="cuda") - 7.0
+    part = torch.zeros(cus * wg, dtype=torch.float64, device="cuda")
+    K.stream_kernel("read", part, a, wg_per_cu=wg, nontemporal=nt)
+    torch.cuda.synchronize()
+    assert float(part.sum().item()) == float(a.sum().item()) == float(n * (n - 1) // 2 - 7 * n)
+    with pytest.raises(ValueError):       # c too small for the grid
+        K.stream_kernel("read", part[:cus * wg - 1], a, wg_per_cu=wg)
