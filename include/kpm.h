@@ -460,8 +460,9 @@ kpm_status kpm_moments_batched(const kpm_hamiltonian* const* H, const void* cons
  *              g, g + grid, ... of that list.
  *   slab       a workgroup walks its instance's lattice in blocks of this
  *              many y-lines, each block plane by plane (0 = natural row
- *              order); default 4 (5 % faster than the natural order on
- *              the 512-instance family).  Only the order of work changes.
+ *              order, the default: fastest on the 512-instance family
+ *              since the solver derives its gather offsets from the
+ *              lattice).  Only the order of work changes.
  * kpm_set_batch_tuning(NULL) restores the defaults.  Errors: KPM_EINVAL. */
 typedef struct {
     int32_t waves;

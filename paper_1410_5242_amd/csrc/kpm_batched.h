@@ -18,11 +18,20 @@
 //
 // Thread mapping (wave64): a lane owns CPL consecutive complex elements of
 // a block row (16 bytes where the block is wide enough), so a wave covers
-// 64 CPL / R block rows per pass.  The matrix rows of a pass (values and
-// column indices, contiguous in memory) are copied by the wave into its own
-// LDS slot with coalesced loads one pass ahead, and every lane then reads
-// the entries of its own row from LDS; the 13 neighbour rows of V are
-// gathered straight from memory.
+// 64 CPL / R block rows per pass.  The matrix values of a pass (contiguous
+// in memory) are copied by the wave into its own LDS slot with coalesced
+// loads one pass ahead, and every lane then reads the entries of its own row
+// from LDS; the 13 neighbour rows of V are gathered straight from memory.
+//
+// Column indices are not read: every Hamiltonian of the library comes from
+// its lattice builder, whose slot order fixes the column of each entry (slot
+// 0 the row itself; then for axis x, y, z the site n - e_j and n + e_j, each
+// with the same orbital o and the partner orbital, o ^ 3 for x and y, o ^ 2
+// for z; a neighbour beyond an open side is a padding slot of value 0).  A
+// lane derives its row's site (x, y, z) with two reciprocal multiplications
+// and forms the 13 gather offsets, which saves the 13 x 4 bytes of indices
+// per row that a sweep would otherwise stream.  The extra integer work per
+// pass needs two waves per SIMD to hide (8-wave workgroups).
 //
 // The pass body has no divergent branches, so that the compiler's count of
 // outstanding memory operations stays exact and a pass never waits for the
@@ -74,6 +83,49 @@ struct Shape {
     // staging one pass ahead keeps the staged words live across the pass
     static constexpr bool kAhead = kLoadsV * kVecV + kLoadsC * kVecC <= 16;
 };
+
+// The batched solver stages the values only (its columns follow from the
+// lattice): the value part of Shape.
+template <typename T, int R>
+struct ValShape : Shape<T, R> {
+    using B = Shape<T, R>;
+    static constexpr int kStageWords = B::kColOff;
+    static constexpr bool kAhead = B::kLoadsV * B::kVecV <= 16;
+};
+
+// Byte offsets, within a block of rows of R complex numbers of kCB bytes, of
+// the 13 rows that row `row` gathers (site n = row / 4, orbital o = row % 4),
+// in the lattice builder's slot order, plus the lane's part lp of a row.  A
+// neighbour beyond an open side is taken as if the side were periodic: its
+// two slots hold exact zeros, so any finite row serves, and the wrapped site
+// is always a valid row.  That keeps the computation free of per-slot
+// selects: per axis and direction one compare, one select and two adds.
+template <int R, unsigned kCB>
+__host__ __device__ inline void gather_offsets(uint32_t row, const BatchInst& d, uint32_t lp,
+                                               uint32_t (&off)[kWidth]) {
+    constexpr uint32_t RB = R * kCB;     // bytes per block row
+    constexpr uint32_t SB = 4 * RB;      // bytes per site
+    const uint32_t n = row >> 2, o = row & 3u;
+    const uint32_t Lx = static_cast<uint32_t>(d.L[0]), Ly = static_cast<uint32_t>(d.L[1]);
+    const uint32_t Lz = static_cast<uint32_t>(d.L[2]);
+    const uint32_t sxy = Lx * Ly;
+    const uint32_t q = d.by_lx.div(n);          // n / Lx
+    const uint32_t z = d.by_lxy.div(n);         // n / (Lx Ly)
+    const uint32_t x = n - q * Lx, y = q - z * Ly;
+    const uint32_t so = o * RB + lp;            // same orbital
+    const uint32_t sp = (o ^ 3u) * RB + lp;     // partner orbital, x and y
+    const uint32_t sz = (o ^ 2u) * RB + lp;     // partner orbital, z
+    const uint32_t m[6] = {x > 0 ? n - 1 : n + (Lx - 1),         x + 1 < Lx ? n + 1 : n - (Lx - 1),
+                           y > 0 ? n - Lx : n + (Ly - 1) * Lx,   y + 1 < Ly ? n + Lx : n - (Ly - 1) * Lx,
+                           z > 0 ? n - sxy : n + (Lz - 1) * sxy, z + 1 < Lz ? n + sxy : n - (Lz - 1) * sxy};
+    off[0] = n * SB + so;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const uint32_t base = m[k] * SB;
+        off[1 + 2 * k] = base + so;
+        off[2 + 2 * k] = base + (k < 4 ? sp : sz);
+    }
+}
 
 // Order in which the passes of a sweep visit a lattice's rows (site n =
 // x + Lx (y + Ly z), rows 4n .. 4n + 3).  The lattice is cut into blocks of
@@ -223,7 +275,7 @@ template <> struct PassOrder<false> {
 
 template <typename T, int R, int WAVES>
 constexpr int lds_bytes() {
-    using S = Shape<T, R>;
+    using S = ValShape<T, R>;
     return WAVES * (S::kAhead ? 2 : 1) * S::kStageWords * 4 + 2 * WAVES * 3 * R * 8 + 16;
 }
 
@@ -316,13 +368,12 @@ template <typename T, int R, int WAVES, bool SLAB>
 __global__ void __launch_bounds__(64 * WAVES, (min_waves<T, R, WAVES>()))
 batched_kernel(const BatchInst* __restrict__ insts, const int32_t* __restrict__ order, int n_inst,
                int* __restrict__ counter, int* __restrict__ flag, int M, int slab) {
-    using S = Shape<T, R>;
+    using S = ValShape<T, R>;
     constexpr int CPL = S::CPL;
     using LV = Lanes<T, CPL>;
     using Cv = typename LV::type;
     using P2 = typename Pair<T>::type;
     using WV = Words<S::kVecV>;
-    using WC = Words<S::kVecC>;
     constexpr int LPR = S::LPR;
     constexpr int RPW = S::RPW;
     constexpr int kVW = S::kValWords;
@@ -357,7 +408,6 @@ batched_kernel(const BatchInst* __restrict__ insts, const int32_t* __restrict__ 
         const int64_t npass = sl0.npass();
         const uint64_t vbytes = static_cast<uint64_t>(N) * R * kCB;
         const __amdgpu_buffer_rsrc_t val_rs = rsrc(d.val, static_cast<uint64_t>(N) * kVW * 4);
-        const __amdgpu_buffer_rsrc_t col_rs = rsrc(d.col, static_cast<uint64_t>(N) * kWidth * 4);
 
         // nu_0 -> a: the recurrence overwrites the block holding nu_{k-1}
         {
@@ -371,25 +421,18 @@ batched_kernel(const BatchInst* __restrict__ insts, const int32_t* __restrict__ 
         // block must be stored before the first sweep reads it
         __syncthreads();
 
-        // matrix rows of the pass starting at row r0 (values, then column
-        // indices); lanes past the end of a part fetch words that are never read
-        auto fetch = [&](int64_t r0, typename WV::type* wv, typename WC::type* wc) {
+        // matrix values of the pass starting at row r0; lanes past the end of
+        // the pass fetch words that are never read
+        auto fetch = [&](int64_t r0, typename WV::type* wv) {
             const unsigned pv = static_cast<unsigned>(r0) * (kVW * 4);
-            const unsigned pc = static_cast<unsigned>(r0) * (kWidth * 4);
 #pragma unroll
             for (int i = 0; i < S::kLoadsV; ++i)
                 wv[i] = WV::template load<kStream<R>>(val_rs, pv + (lane + 64 * i) * (4 * S::kVecV));
-#pragma unroll
-            for (int i = 0; i < S::kLoadsC; ++i)
-                wc[i] = WC::template load<kStream<R>>(col_rs, pc + (lane + 64 * i) * (4 * S::kVecC));
         };
-        auto put = [&](int* dst, const typename WV::type* wv, const typename WC::type* wc) {
+        auto put = [&](int* dst, const typename WV::type* wv) {
 #pragma unroll
             for (int i = 0; i < S::kLoadsV; ++i)
                 *reinterpret_cast<typename WV::type*>(dst + (lane + 64 * i) * S::kVecV) = wv[i];
-#pragma unroll
-            for (int i = 0; i < S::kLoadsC; ++i)
-                *reinterpret_cast<typename WC::type*>(dst + S::kColOff + (lane + 64 * i) * S::kVecC) = wc[i];
         };
 
         for (int k = 0; k < sweeps; ++k) {
@@ -406,31 +449,30 @@ batched_kernel(const BatchInst* __restrict__ insts, const int32_t* __restrict__ 
 #pragma unroll
             for (int t = 0; t < CPL; ++t) ae[t] = aor[t] = aoi[t] = 0.0;
             typename WV::type wv[S::kLoadsV];
-            typename WC::type wc[S::kLoadsC];
             int buf = 0;
             PassOrder<SLAB> sl = sl0;
             int64_t row0, nr;
             sl.cur(row0, nr);
             if constexpr (S::kAhead) {
-                fetch(row0, wv, wc);
-                put(stage[wave][0], wv, wc);
+                fetch(row0, wv);
+                put(stage[wave][0], wv);
             }
             for (int64_t q = wave; q < npass; q += WAVES) {
                 if constexpr (!S::kAhead) {
                     wave_sync();   // every lane has read the slot before it is refilled
-                    fetch(row0, wv, wc);
-                    put(stage[wave][0], wv, wc);
+                    fetch(row0, wv);
+                    put(stage[wave][0], wv);
                 }
                 wave_sync();
                 const int* st = stage[wave][buf];
-                // gathers of the 13 neighbour rows
+                const int64_t row = row0 + sub;
+                // gathers of the 13 neighbour rows (a lane past the end of the
+                // pass or of the lattice takes those of the last row)
+                uint32_t goff[kWidth];
+                gather_offsets<R, kCB>(static_cast<uint32_t>(row < N ? row : N - 1), d, cc * CPL * kCB, goff);
                 Cv v[kWidth];
 #pragma unroll
-                for (int j = 0; j < kWidth; ++j) {
-                    const unsigned c = static_cast<unsigned>(st[S::kColOff + sub * kWidth + j]);
-                    v[j] = LV::load(vrs, (c * R + cc * CPL) * kCB);
-                }
-                const int64_t row = row0 + sub;
+                for (int j = 0; j < kWidth; ++j) v[j] = LV::load(vrs, goff[j]);
                 // slab order: rows past the end of a pass belong to other
                 // passes and get an offset past the block (the old-W load
                 // reads zero, the store is dropped); natural order: only rows
@@ -449,7 +491,7 @@ batched_kernel(const BatchInst* __restrict__ insts, const int32_t* __restrict__ 
                 int64_t row0n, nrn;
                 sl.advance();
                 sl.cur(row0n, nrn);
-                if constexpr (S::kAhead) fetch(row0n, wv, wc);
+                if constexpr (S::kAhead) fetch(row0n, wv);
                 const int* sv = st + sub * kVW;
                 Cv acc;
 #pragma unroll
@@ -482,7 +524,7 @@ batched_kernel(const BatchInst* __restrict__ insts, const int32_t* __restrict__ 
                     aoi[t] = fma(wr, vi, fma(-wi, vr, aoi[t]));
                 }
                 if constexpr (S::kAhead) {
-                    put(stage[wave][buf ^ 1], wv, wc);
+                    put(stage[wave][buf ^ 1], wv);
                     buf ^= 1;
                 }
                 row0 = row0n;

@@ -183,8 +183,8 @@ struct SlabGeom {
 
 // One instance of the batched solver (device-side descriptor).
 struct BatchInst {
-    const void* val;        // H: [N][kWidth] complex, diagonal in slot 0
-    const int32_t* col;     // H: [N][kWidth]
+    const void* val;        // H: [N][kWidth] complex, diagonal in slot 0 (the builder's slot order:
+                            // the columns follow from the row and the lattice, see batched_kernel)
     const void* v0;         // start block [N][R] (read-only)
     void* a;                // work blocks [N][R]
     void* b;
@@ -195,6 +195,7 @@ struct BatchInst {
     double shift;           // b/a
     int32_t L[3];           // lattice sides (rows 4 (x + Lx (y + Ly z)) + o)
     int32_t pad;
+    FastDiv by_lx, by_lxy;  // site index -> (x, y, z): division by Lx and by Lx Ly
     SlabGeom geom;          // slab pass order of this instance (used when the slab tuning is on)
 };
 

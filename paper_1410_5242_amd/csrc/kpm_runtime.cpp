@@ -244,7 +244,7 @@ hipError_t launch_any_sweep(kpm_hamiltonian* H, int R, int variant, const SweepA
 }
 
 // ---- batched solver: launch shape (process-wide) and state per (device, stream) ----
-constexpr kpm_batch_tuning kDefaultBatchTuning = {0, 0, 1, 4};
+constexpr kpm_batch_tuning kDefaultBatchTuning = {0, 0, 1, 0};
 std::mutex g_batch_lock;   // guards g_batch_tuning and the g_batch map (not the states in it)
 kpm_batch_tuning g_batch_tuning = kDefaultBatchTuning;
 
@@ -294,8 +294,8 @@ void drop_graph(BatchState& b) {
 }
 
 bool same_inst(const BatchInst& x, const BatchInst& y) {
-    return x.val == y.val && x.col == y.col && x.v0 == y.v0 && x.a == y.a && x.b == y.b && x.eta == y.eta &&
-           x.mu == y.mu && x.nrows == y.nrows && x.inv_a == y.inv_a && x.shift == y.shift && x.L[0] == y.L[0] &&
+    return x.val == y.val && x.v0 == y.v0 && x.a == y.a && x.b == y.b && x.eta == y.eta && x.mu == y.mu &&
+           x.nrows == y.nrows && x.inv_a == y.inv_a && x.shift == y.shift && x.L[0] == y.L[0] &&
            x.L[1] == y.L[1] && x.L[2] == y.L[2];
 }
 
@@ -1112,13 +1112,22 @@ kpm_status kpm_moments_batched(const kpm_hamiltonian* const* H, const void* cons
     for (int i = 0; i < n_inst; ++i) {
         const size_t blk = (static_cast<size_t>(H[i]->nrows) * 2 * R * rs + 255) / 256 * 256;
         char* base = static_cast<char*>(b.vec) + voff[i];
-        inst[i] = BatchInst{H[i]->val, H[i]->col, V0[i], base, base + blk, b.eta + eta_per * i,
-                            mu + static_cast<size_t>(i) * R * M, H[i]->nrows, 1.0 / H[i]->a, H[i]->b / H[i]->a,
-                            {H[i]->L[0], H[i]->L[1], H[i]->L[2]}, 0,
-                            bt.slab > 0
-                                ? SlabGeom::make(H[i]->L[0], H[i]->L[1], H[i]->L[2], bt.slab,
-                                                 batched_rows_per_pass(dtype, R))
-                                : SlabGeom{}};
+        BatchInst& t = inst[i];
+        t = BatchInst{};
+        t.val = H[i]->val;
+        t.v0 = V0[i];
+        t.a = base;
+        t.b = base + blk;
+        t.eta = b.eta + eta_per * i;
+        t.mu = mu + static_cast<size_t>(i) * R * M;
+        t.nrows = H[i]->nrows;
+        t.inv_a = 1.0 / H[i]->a;
+        t.shift = H[i]->b / H[i]->a;
+        for (int j = 0; j < 3; ++j) t.L[j] = H[i]->L[j];
+        t.by_lx.init(static_cast<uint32_t>(H[i]->L[0]));
+        t.by_lxy.init(static_cast<uint32_t>(H[i]->L[0]) * static_cast<uint32_t>(H[i]->L[1]));
+        if (bt.slab > 0)
+            t.geom = SlabGeom::make(H[i]->L[0], H[i]->L[1], H[i]->L[2], bt.slab, batched_rows_per_pass(dtype, R));
     }
     // longest first (greedy longest-processing-time order), ties by index
     std::vector<int32_t> order(n_inst);
@@ -1128,8 +1137,9 @@ kpm_status kpm_moments_batched(const kpm_hamiltonian* const* H, const void* cons
 
     const int max_w = batched_max_waves(dtype, R);
     if (max_w == 0) return fail(KPM_EINTERNAL, "no batched kernel for this dtype and R");
-    // 8 waves (one workgroup per CU) by default: measured faster than 16 on
-    // the 512-instance family, whose sweep is bound by the texture-address path
+    // 8 waves (one workgroup per CU, two waves per SIMD) by default: one wave
+    // per SIMD leaves the integer work of the gather offsets exposed, and 16
+    // waves measured slower on the 512-instance family
     int waves = bt.waves > 0 ? bt.waves : (max_w < 8 ? max_w : 8);
     if (waves > max_w) waves = max_w;
     const int per_cu = bt.wg_per_cu > 0 ? bt.wg_per_cu : 1;

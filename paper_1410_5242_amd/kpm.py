@@ -408,7 +408,7 @@ def moments_batched(Hs, V0s, M: int, mu: torch.Tensor | None = None, check: bool
     return mu
 
 
-def set_batch_tuning(waves: int = 0, wg_per_cu: int = 0, dynamic: int = 1, slab: int = 4):
+def set_batch_tuning(waves: int = 0, wg_per_cu: int = 0, dynamic: int = 1, slab: int = 0):
     """kpm_set_batch_tuning: launch shape of the batched solver (process-wide)."""
     _check(lib().kpm_set_batch_tuning(ctypes.byref(BatchTuning(waves, wg_per_cu, dynamic, slab))))
 
