@@ -148,7 +148,7 @@ def cpu_oracle_subsets(target_s=8.0):
     del Ho, v0
     for name, fam, Rf, M, n_total in (
             ("batched_512_r8_m512", inputs.instance_family(512, (12, 16, 20, 24), 4.0, 0), 8, 512, 512),
-            ("learned_truth_r16_m2048", learned.family(21000, learned.TRAIN_SEED), 16, 2048, 21000)):
+            ("learned_truth_r16_m4096", learned.family(22000, learned.TRAIN_SEED), 16, learned.M_TRUTH, 22000)):
         t_inst, done, t_start = [], 0, time.perf_counter()
         for f in fam:
             Hf = O.ti_hamiltonian(f["L"], inputs.potential(f["L"], f["gamma"], f["pot_seed"]))

@@ -2,42 +2,45 @@
 
 Workload: held-out instances of the learned-reconstruction family (cubic
 lattices L = 16 .. 24, disorder gamma ~ U[0, 4], R = 16 random vectors, the
-fixed family scaling).  Truth: the complex128 Jackson DOS at M = 2048 with
+fixed family scaling).  Truth: the complex128 Jackson DOS at M = 4096 with
 the same vectors; every shorter run is a prefix of it, so the L1 error
 sum_k |rho - rho_truth| dE on the 512-bin grid measures truncation (or
-reconstruction) only.  For a target eps, the KPM variants use the smallest
-M in {64, ..., 2048} whose mean L1 error over the instances is <= eps.
+reconstruction) only.  For a target eps (0.08 and 0.05, fixed before
+measuring), the KPM variants use the smallest M in {64, ..., 2048} whose
+mean L1 error over the instances is within eps.
 
 Variants, each timed from device-resident Hamiltonians and start blocks to
-the DOS of every instance on the host (building H is reported apart):
+the DOS of every instance on the host (building H is reported apart), all
+on every instance:
   plain    complex128, one kpm_moments + kpm_dos per instance
-  mixed    complex64 storage, FP64 products, one call per instance
+  mixed    complex64 storage, FP64 products, one call per instance (its own
+           L1 error measured from its own moments)
   batched  complex64, all instances in one kpm_moments_batched launch
            plus one kpm_dos_batched
   learned  batched complex64 run to M = 128, network, and a batched plain
            rerun at the eps-M of the instances whose predicted error
-           exceeds eps (fallback)
+           exceeds the threshold calibrated for eps on validation data
+Every variant reports its mean L1 error and the fraction of instances whose
+own error exceeds eps (the KPM variants meet eps on the mean, not on every
+instance, and so does the learned one by its calibration).
 """
 from __future__ import annotations
 
 import time
 
-import numpy as np
 import torch
 
 from . import autotune as AT
 from . import kpm as K
 from . import learned as LN
 
-M_CHOICES = (64, 128, 256, 512, 1024, 2048)
-
 
 def _sync():
     torch.cuda.synchronize()
 
 
-def run(n_inst: int = 1000, eps_list=(0.05, 0.02), per_instance_sample: int = 100, seed: int = LN.TEST_SEED + 7,
-        weights: str = LN.WEIGHTS, log=print) -> dict:
+def run(n_inst: int = 1000, eps_list=LN.EPS_TARGETS, seed: int = LN.TEST_SEED + 7, weights: str = LN.WEIGHTS,
+        log=print) -> dict:
     R = LN.R_TRUTH
     fam = LN.family(n_inst, seed)
     t0 = time.perf_counter()
@@ -50,36 +53,45 @@ def run(n_inst: int = 1000, eps_list=(0.05, 0.02), per_instance_sample: int = 10
     E = LN.energy_grid()
     a = torch.full((n_inst,), LN.A_FAMILY, dtype=torch.float64, device="cuda")
     b = torch.full((n_inst,), LN.B_FAMILY, dtype=torch.float64, device="cuda")
-    log(f"[time-to-dos] {n_inst} instances built ({build_s:.1f} s); truth run")
+    log(f"[time-to-dos] {n_inst} instances built ({build_s:.1f} s); truth run (M={LN.M_TRUTH}, complex128)")
     mu_truth = K.moments_batched(H128, V128, LN.M_TRUTH)
     p = K.dos_batched(mu_truth, a, b, E, masses=True)
-    err_M = {M: float(LN.l1(K.dos_batched(mu_truth, a, b, E, M=M, masses=True), p).mean()) for M in M_CHOICES}
-    net, _ = LN.load_weights(weights, max_batch=1024)
+    err_M = {M: LN.l1(K.dos_batched(mu_truth, a, b, E, M=M, masses=True), p) for M in LN.M_CHOICES}
+    net, meta = LN.load_weights(weights, max_batch=1024)
+    calib = meta.get("fallback", {})
     # batched launch shape from the committed tuning cache (tuned on this family); it then holds for
     # every batched call below, the fallback reruns included
     tuned = AT.apply_batched(AT.TuningCache(), H64, R)
     out = {"n_instances": n_inst, "R": R, "truth_M": LN.M_TRUTH, "build_s": round(build_s, 2),
            "batched_tuning": dict(K.get_batch_tuning(), autotuned=tuned),
-           "kpm_mean_l1_by_M": {str(k): round(v, 5) for k, v in err_M.items()},
-           "per_instance_variants_timed_on": per_instance_sample, "targets": {}}
+           "kpm_mean_l1_by_M": {str(k): round(float(v.mean()), 5) for k, v in err_M.items()},
+           "network_m_truth": meta.get("m_truth"), "targets": {}}
     rho = torch.empty((n_inst, LN.K_BINS), dtype=torch.float64, device="cuda")
-    ns = min(per_instance_sample, n_inst)
+
+    def over(err, eps):
+        return round(float((err > eps).double().mean()), 4)
 
     for eps in eps_list:
-        M = next(m for m in M_CHOICES if err_M[m] <= eps)
+        M = next((m for m in LN.M_CHOICES if float(err_M[m].mean()) <= eps), None)
+        if M is None:
+            out["targets"][str(eps)] = {"skipped": "no candidate M meets this target"}
+            continue
         res = {"M": M}
-        # plain / mixed: one call pair per instance, timed on the first ns and scaled
+        # plain / mixed: one call pair per instance, every instance
         for name, Hs, Vs in (("plain_c128", H128, V128), ("mixed_c64", H64, V64)):
             mu = torch.empty((R, M), dtype=torch.float64, device="cuda")
             K.moments(Hs[0], Vs[0], M, mu=mu)
             _sync()
             t0 = time.perf_counter()
-            for i in range(ns):
+            for i in range(n_inst):
                 K.moments(Hs[i], Vs[i], M, mu=mu, check=False)
                 K.dos(mu, LN.A_FAMILY, LN.B_FAMILY, E, rho=rho[i])
-            host = rho[:ns].cpu()
-            dt = (time.perf_counter() - t0) * n_inst / ns
-            res[name] = {"seconds": round(dt, 3), "timed_instances": ns, "mean_l1": round(err_M[M], 5)}
+            host = rho.cpu()
+            dt = time.perf_counter() - t0
+            # bin masses as kpm_dos_batched forms them: midpoint densities normalised to sum 1
+            err = LN.l1(rho / rho.sum(dim=1, keepdim=True), p)
+            res[name] = {"seconds": round(dt, 3), "mean_l1": round(float(err.mean()), 5),
+                         "over_eps_fraction": over(err, eps)}
             del host
         # batched: one launch for all instances
         K.moments_batched(H64[:8], V64[:8], M)
@@ -89,34 +101,43 @@ def run(n_inst: int = 1000, eps_list=(0.05, 0.02), per_instance_sample: int = 10
         q_b = K.dos_batched(mu_b, a, b, E, masses=True)
         host = q_b.cpu()
         dt = time.perf_counter() - t0
-        res["batched_c64"] = {"seconds": round(dt, 3), "mean_l1": round(float(LN.l1(q_b, p).mean()), 5)}
-        # learned: batched short run, network, fallback reruns at M
-        mu_s = torch.empty((n_inst, R, LN.N_MOM), dtype=torch.float64, device="cuda")
-        _sync()
-        t0 = time.perf_counter()
-        K.moments_batched(H64, V64, LN.N_MOM, mu=mu_s, check=False)
-        x = LN.features(mu_s, fam)
-        q, e = LN.predict(net, x)
-        fb = e > eps
-        idx = torch.nonzero(fb).flatten().tolist()
-        out_q = q.double()
-        if idx:
-            mu_f = K.moments_batched([H64[i] for i in idx], [V64[i] for i in idx], M, check=False)
-            out_q[fb] = K.dos_batched(mu_f, a[:len(idx)], b[:len(idx)], E, masses=True)
-        host = out_q.cpu()
-        dt = time.perf_counter() - t0
-        err = LN.l1(out_q, p)
-        res["learned"] = {"seconds": round(dt, 3), "mean_l1": round(float(err.mean()), 5),
-                          "max_l1": round(float(err.max()), 5),
-                          "fallback_fraction": round(len(idx) / n_inst, 4),
-                          "accepted_over_eps_fraction": round(float(((err > eps) & ~fb).double().mean()), 4)}
+        err = LN.l1(q_b, p)
+        res["batched_c64"] = {"seconds": round(dt, 3), "mean_l1": round(float(err.mean()), 5),
+                              "over_eps_fraction": over(err, eps)}
+        # learned: batched short run, network, fallback reruns at M above the calibrated threshold
+        rec = calib.get(str(eps))
+        if rec is not None and rec.get("M") == M:
+            tau = rec["tau"]
+            mu_s = torch.empty((n_inst, R, LN.N_MOM), dtype=torch.float64, device="cuda")
+            _sync()
+            t0 = time.perf_counter()
+            K.moments_batched(H64, V64, LN.N_MOM, mu=mu_s, check=False)
+            x = LN.features(mu_s, fam)
+            q, e = LN.predict(net, x)
+            fb = e > tau
+            idx = torch.nonzero(fb).flatten().tolist()
+            out_q = q.double()
+            if idx:
+                mu_f = K.moments_batched([H64[i] for i in idx], [V64[i] for i in idx], M, check=False)
+                out_q[fb] = K.dos_batched(mu_f, a[:len(idx)], b[:len(idx)], E, masses=True)
+            host = out_q.cpu()
+            dt = time.perf_counter() - t0
+            err = LN.l1(out_q, p)
+            res["learned"] = {"seconds": round(dt, 3), "mean_l1": round(float(err.mean()), 5),
+                              "max_l1": round(float(err.max()), 5), "threshold": round(tau, 5),
+                              "fallback_fraction": round(len(idx) / n_inst, 4),
+                              "over_eps_fraction": over(err, eps),
+                              "accepted_over_eps_fraction": round(float(((err > eps) & ~fb).double().mean()), 4)}
+        else:
+            res["learned"] = {"skipped": "the network carries no threshold calibrated for this target and M"}
         del host
         base = res["plain_c128"]["seconds"]
         for k in ("mixed_c64", "batched_c64", "learned"):
-            res[k]["speedup_vs_plain"] = round(base / max(res[k]["seconds"], 1e-9), 2)
+            if "seconds" in res[k]:
+                res[k]["speedup_vs_plain"] = round(base / max(res[k]["seconds"], 1e-9), 2)
         out["targets"][str(eps)] = res
-        log(f"[time-to-dos] eps {eps}: M={M} " + " ".join(f"{k}={v['seconds']}s" for k, v in res.items()
-                                                          if isinstance(v, dict)))
+        log(f"[time-to-dos] eps {eps}: M={M} " + " ".join(
+            f"{k}={v['seconds']}s/L1 {v['mean_l1']}" for k, v in res.items() if isinstance(v, dict) and "seconds" in v))
     K.reset_batch_tuning()
     for H in H128 + H64:
         H.close()

@@ -2,11 +2,11 @@
 
 (1) The family data path (fixed family scaling, device start blocks,
 batched solver, batched DOS masses, moment features) against the CPU oracle.
-(2) The trained network against plain KPM on held-out instances: at the same
-moment budget (the first 128 moments) the network's DOS is closer to the
-M = 2048 truth than the Jackson DOS from those moments, and the fallback
-returns, for every instance whose predicted error exceeds the target,
-exactly the plain KPM DOS.
+(2) The trained network against plain KPM on held-out instances: from the
+first 128 moments the network's DOS is closer to the M = 4096 truth than the
+Jackson DOS of 512 moments, and the fallback returns, for every instance
+whose predicted error exceeds the calibrated threshold, exactly the plain
+KPM DOS.
 """
 import os
 import sys
@@ -61,20 +61,28 @@ def test_trained_network_gains_over_short_kpm_and_fallback_contract():
     say("learned vs short KPM")
     net, meta = LN.load_weights()
     assert meta["n_in"] == LN.N_MOM + 1 and meta["n_out"] == LN.K_BINS
-    fam = LN.family(48, LN.TEST_SEED + 100)      # instances the network never saw
+    assert meta["m_truth"] == LN.M_TRUTH
+    fam = LN.family(400, LN.TEST_SEED + 100)      # instances the network never saw
     x, p, mu = LN.dataset(fam)
     q, e = LN.predict(net, x)
     l1_net = LN.l1(q, p)
-    l1_kpm = LN.l1(LN.masses(mu, LN.N_MOM), p)
-    say("mean L1: network", float(l1_net.mean()), "Jackson KPM at M=128", float(l1_kpm.mean()))
-    assert float(l1_net.mean()) < float(l1_kpm.mean())
+    l1_128 = LN.l1(LN.masses(mu, LN.N_MOM), p)
+    l1_512 = LN.l1(LN.masses(mu, 512), p)
+    say("mean L1: network", float(l1_net.mean()), "Jackson KPM at M=128", float(l1_128.mean()),
+        "at M=512", float(l1_512.mean()))
+    # what the network gains: from 128 moments it is closer to the truth than plain KPM from
+    # 128 moments (by a wide margin) and than plain KPM from 512 moments
+    assert float(l1_net.mean()) < 0.75 * float(l1_128.mean())
+    assert float(l1_net.mean()) < float(l1_512.mean())
     # the error head orders the instances: predicted and actual errors correlate
-    assert np.corrcoef(e.double().cpu().numpy(), l1_net.cpu().numpy())[0, 1] > 0.3
-    eps, M_fb = 0.05, 512
-    out, fb = LN.reconstruct(net, fam, eps, M_fb, dtype="c128", mu_short=mu[:, :, :LN.N_MOM].contiguous())
+    assert np.corrcoef(e.double().cpu().numpy(), l1_net.cpu().numpy())[0, 1] > 0.5
+    eps = 0.08
+    rec = meta["fallback"][str(eps)]
+    tau, M_fb = rec["tau"], rec["M"]
+    out, fb = LN.reconstruct(net, fam, eps, M_fb, dtype="c64", mu_short=mu[:, :, :LN.N_MOM].contiguous(), tau=tau)
     idx = torch.nonzero(fb).flatten().tolist()
     assert torch.equal(out[~fb], q[~fb].double())
-    assert bool((e[~fb] <= eps).all())
+    assert bool((e[~fb] <= tau).all())
     if idx:
         ref = LN.masses(mu[idx].contiguous(), M_fb)
         assert torch.allclose(out[fb], ref, rtol=0, atol=1e-14)
