@@ -310,6 +310,9 @@ def leg_small(reps: int = 50):
     return out
 
 
+BATCH_TUNING_OVERRIDE = None   # (waves, wg_per_cu, dynamic, slab) from --batch-tuning
+
+
 def leg_batched():
     """512 independent realisations, L in {12, 16, 20, 24}, gamma ~ U[0, 4], R = 8, M = 512, complex64:
     one persistent launch (graph replay), throughput over all instance sweeps."""
@@ -325,7 +328,11 @@ def leg_batched():
     torch.cuda.synchronize()
     build_s = time.perf_counter() - t0
     cache = autotune.TuningCache()
-    tuned = autotune.apply_batched(cache, Hs, R)
+    if BATCH_TUNING_OVERRIDE is not None:
+        kpm.set_batch_tuning(*BATCH_TUNING_OVERRIDE)
+        tuned = "override"
+    else:
+        tuned = autotune.apply_batched(cache, Hs, R)
     mu = kpm.moments_batched(Hs, V0s, M, graph=True)
     torch.cuda.synchronize()
     ts = []
@@ -356,7 +363,8 @@ def leg_batched():
 def leg_variants(sweeps: int = 10):
     """Single fused sweeps on the 64^3 complex128 lattice for every block width R and the three
     variants (the paper's split of the sweep into plain SpMMV, the update without scalar
-    products, and the full fused sweep): GB/s from the library's per-launch HIP events."""
+    products, and the full fused sweep): GB/s from the library's per-launch HIP events.  At
+    R = 32 and 64 the index-reading staged-gather sweep runs as well, forced by the tuning."""
     import torch
     from paper_1410_5242_amd import autotune, inputs, kpm
     L = (64, 64, 64)
@@ -364,9 +372,16 @@ def leg_variants(sweeps: int = 10):
     N, Sd = H.N, 16
     out = {"workload": f"TI {L[0]}x{L[1]}x{L[2]} periodic, complex128, {sweeps} sweeps per point", "points": []}
     cache = autotune.TuningCache()
-    for R in kpm.SUPPORTED_R:
+    for R, force_gather in [(R, False) for R in kpm.SUPPORTED_R] + [(32, True), (64, True)]:
         kpm.reset_sweep_tuning()
         tuned = autotune.apply_sweep(cache, H, R, L)
+        if force_gather:
+            # the index-reading staged-gather sweep at the widths the lattice sweep takes, in its
+            # best measured shape (two workgroups per CU, no die split, natural row order)
+            t = kpm.get_sweep_tuning()
+            t.update(lattice=0, gather=1, wg_per_cu=2, xcd_ways=1, slab=0)
+            kpm.set_sweep_tuning(**t)
+            tuned = False
         V = kpm.random_phase_block(N, R, 1, "c128")
         W = kpm.random_phase_block(N, R, 2, "c128")
         eta = torch.zeros((2, R, 2), dtype=torch.float64, device="cuda")
@@ -594,19 +609,24 @@ COPY_BYTES = 1 << 30
 
 
 def probe(args, H, V0, M, R, Sd):
-    """Copy calibration plus a few sweeps, for rocprofv3 --pmc runs."""
+    """Calibration kernels of known traffic plus a few sweeps, for rocprofv3 --pmc runs: the
+    library's STREAM read (reads COPY_BYTES) and copy (reads and writes COPY_BYTES) kernels, then
+    --probe-sweeps fused sweeps of the workload."""
     import torch
     from paper_1410_5242_amd import kpm
-    x = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=V0.device)
-    y = torch.empty_like(x)
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    a = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device=V0.device)
+    c = torch.empty_like(a)
+    cus = torch.cuda.get_device_properties(V0.device).multi_processor_count
+    part = torch.zeros(cus, dtype=torch.float64, device=V0.device)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
     ev[0].record()
-    for _ in range(3):
-        y.copy_(x)
+    kpm.stream_kernel("read", part, a, wg_per_cu=1, nontemporal=True)
     ev[1].record()
+    kpm.stream_kernel("copy", c, a, wg_per_cu=1, nontemporal=True)
+    ev[2].record()
     torch.cuda.synchronize()
-    copy_ms = ev[0].elapsed_time(ev[1]) / 3
-    del x, y
+    read_ms, copy_ms = ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])
+    del a, c
     kpm.sweep_profile_read()
     kpm.sweep_profile_enable(True)
     mu = kpm.moments(H, V0, 2 * args.probe_sweeps)
@@ -614,9 +634,8 @@ def probe(args, H, V0, M, R, Sd):
     kpm.sweep_profile_enable(False)
     n, tot, lo, hi = kpm.sweep_profile_read()
     bps = sweep_bytes(H.N, 13 * H.N, R, Sd)
-    print(json.dumps({"probe": True, "copy_bytes_read": COPY_BYTES, "copy_bytes_written": COPY_BYTES,
-                      "copy_ms": round(copy_ms, 4), "copy_GBps": round(2 * COPY_BYTES / copy_ms / 1e6, 1),
-                      "sweeps": n, "sweep_avg_ms": round(tot / max(n, 1), 5),
+    print(json.dumps({"probe": True, "calibration_bytes": COPY_BYTES, "read_ms": round(read_ms, 4),
+                      "copy_ms": round(copy_ms, 4), "sweeps": n, "sweep_avg_ms": round(tot / max(n, 1), 5),
                       "sweep_algorithmic_bytes": bps, "mu0": float(mu[0, 0].item())}), flush=True)
     H.close()
 
@@ -630,14 +649,19 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-target-s", type=float, default=15.0)
     ap.add_argument("--probe", action="store_true",
-                    help="short run for hardware counters: a 1 GiB device copy (the calibration kernel "
-                         "of known traffic) and --probe-sweeps fused sweeps of the workload")
+                    help="short run for hardware counters: the STREAM read and copy kernels over 1 GiB "
+                         "(calibration kernels of known traffic) and --probe-sweeps fused sweeps of the workload")
     ap.add_argument("--probe-sweeps", type=int, default=8)
+    ap.add_argument("--batch-tuning", default=None,
+                    help="waves,wg_per_cu,dynamic,slab for the batched leg instead of the tuning cache")
     ap.add_argument("--legs", default="small,variants,ladder,precision,batched,spectral,slab,bounds,time_to_dos,"
                                       "oracle_subsets",
                     help="extra measurements after the headline step (comma separated): any of small, variants, "
                          "ladder, precision, batched, spectral, slab, bounds, time_to_dos, oracle_subsets; or none")
     args = ap.parse_args()
+    if args.batch_tuning:
+        global BATCH_TUNING_OVERRIDE
+        BATCH_TUNING_OVERRIDE = tuple(int(v) for v in args.batch_tuning.split(","))
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU sharding is a design, "
               f"not built", file=sys.stderr)
