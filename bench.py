@@ -470,6 +470,80 @@ def leg_ladder(steps: int = 200, repeats: int = 3):
     return out
 
 
+def leg_custom_roofline(sweeps: int = 20):
+    """The paper's custom roofline P* = min(P*_MEM, P*_LLC) (eq. "eq:roofline_custom"): P*_LLC
+    is measured on a down-sized problem whose whole working set (matrix and the three vector
+    blocks) fits the 256 MB last-level cache, with the same kernel and launch shape as the
+    full-size run; P*_MEM is the attainable HBM rate b over the model bytes (Omega = 1).
+    Per block width R on 64 x 64 x Z lattices (complex128, Z chosen for about 130 MB), and for
+    the batched solver on 256 instances of 8^3 sites (complex64, R = 8)."""
+    import torch
+    from paper_1410_5242_amd import autotune, inputs, kpm
+    cache = autotune.TuningCache()
+    out = {"workload": "complex128 TI lattices 64 x 64 x Z, Z = max(3, ~130 MB / (16384 rows x model bytes per "
+                       "row)); sweeps timed with the library's per-launch HIP events", "points": []}
+    for R in kpm.SUPPORTED_R:
+        row_bytes = 13 * 20 + 3 * R * 16
+        Z = max(3, int(round(130e6 / (16384 * row_bytes))))
+        L = (64, 64, Z)
+        H = kpm.build_hamiltonian(L, inputs.potential(L, 1.0, 0))
+        kpm.reset_sweep_tuning()
+        autotune.apply_sweep(cache, H, R, (64, 64, 64))   # the full-size run's launch shape
+        V = kpm.random_phase_block(H.N, R, 1, "c128")
+        W = kpm.random_phase_block(H.N, R, 2, "c128")
+        eta = torch.zeros((2, R, 2), dtype=torch.float64, device="cuda")
+        for _ in range(3):
+            kpm.aug_spmmv(H, V, W, 2.0 / H.a, -2.0 * H.b / H.a, -1.0, "full", eta)
+        torch.cuda.synchronize()
+        kpm.sweep_profile_read()
+        kpm.sweep_profile_enable(True)
+        for _ in range(sweeps):
+            kpm.aug_spmmv(H, V, W, 2.0 / H.a, -2.0 * H.b / H.a, -1.0, "full", eta)
+        torch.cuda.synchronize()
+        kpm.sweep_profile_enable(False)
+        n, tot, lo, hi = kpm.sweep_profile_read()
+        avg = tot / n * 1e-3
+        byts = sweep_bytes(H.N, 13 * H.N, R, 16)
+        out["points"].append({"R": R, "L": list(L), "working_set_MB": round(byts / 1e6, 1),
+                              "kernel": kpm.sweep_kernel(H, R), "avg_us": round(avg * 1e6, 2),
+                              "llc_GBps": round(byts / avg / 1e9, 1),
+                              "llc_gflops": round(sweep_flops(H.N, R) / avg / 1e9, 1)})
+        del V, W
+        H.close()
+        torch.cuda.empty_cache()
+    kpm.reset_sweep_tuning()
+    # batched solver: 256 instances of 8^3 sites, one per CU, all resident in the last-level cache
+    n, Rb, M = 256, 8, 512
+    fam = inputs.instance_family(n, (8,), 4.0, 0)
+    Hs = [kpm.build_hamiltonian(f["L"], inputs.potential(f["L"], f["gamma"], f["pot_seed"]), dtype="c64")
+          for f in fam]
+    V0s = [kpm.random_phase_block(H.N, Rb, f["vec_seed"], "c64") for f, H in zip(fam, Hs)]
+    if BATCH_TUNING_OVERRIDE is not None:
+        kpm.set_batch_tuning(*BATCH_TUNING_OVERRIDE)
+    else:
+        autotune.apply_batched(cache, Hs, Rb)
+    mu = kpm.moments_batched(Hs, V0s, M, graph=True)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(3):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record()
+        kpm.moments_batched(Hs, V0s, M, mu=mu, check=False, graph=True)
+        ev[1].record()
+        torch.cuda.synchronize()
+        ts.append(ev[0].elapsed_time(ev[1]) / 1e3)
+    t = min(ts)
+    bps = sum(sweep_bytes(H.N, 13 * H.N, Rb, 8) for H in Hs)
+    out["batched"] = {"workload": f"{n} instances of 8^3 sites (sum N = {sum(H.N for H in Hs)}), gamma ~ U[0,4], "
+                                  f"R={Rb}, M={M}, complex64, one persistent launch",
+                      "working_set_MB": round(bps / 1e6, 1), "seconds": round(t, 5),
+                      "llc_GBps": round(bps * (M // 2) / t / 1e9, 1)}
+    kpm.reset_batch_tuning()
+    for H in Hs:
+        H.close()
+    return out
+
+
 def leg_spectral(M: int = 1000, K: int = 1024):
     """Local DOS of 16 sites and A(k, E) at 16 momenta on the 64^3 complex128 lattice (gamma = 1):
     the fused blocked sweep on deterministic start vectors (4 orbitals x 16 = R = 64 per run),
@@ -654,10 +728,11 @@ def main():
     ap.add_argument("--probe-sweeps", type=int, default=8)
     ap.add_argument("--batch-tuning", default=None,
                     help="waves,wg_per_cu,dynamic,slab for the batched leg instead of the tuning cache")
-    ap.add_argument("--legs", default="small,variants,ladder,precision,batched,spectral,slab,bounds,time_to_dos,"
-                                      "oracle_subsets",
+    ap.add_argument("--legs", default="small,variants,custom_roofline,ladder,precision,batched,spectral,slab,bounds,"
+                                      "time_to_dos,oracle_subsets",
                     help="extra measurements after the headline step (comma separated): any of small, variants, "
-                         "ladder, precision, batched, spectral, slab, bounds, time_to_dos, oracle_subsets; or none")
+                         "custom_roofline, ladder, precision, batched, spectral, slab, bounds, time_to_dos, "
+                         "oracle_subsets; or none")
     args = ap.parse_args()
     if args.batch_tuning:
         global BATCH_TUNING_OVERRIDE
@@ -796,7 +871,8 @@ def main():
     out["roofline"]["measured_b_copy_GBps"] = out["stream"]["b_copy_GBps"]
     out["pct_of_measured_b"] = round(100.0 * value / b_meas, 2)
     legs = [x for x in args.legs.split(",") if x and x != "none"]
-    for name, fn in (("small", leg_small), ("variants", leg_variants), ("ladder", leg_ladder),
+    for name, fn in (("small", leg_small), ("variants", leg_variants), ("custom_roofline", leg_custom_roofline),
+                     ("ladder", leg_ladder),
                      ("precision", leg_precision), ("batched", leg_batched), ("spectral", leg_spectral),
                      ("slab", leg_slab), ("bounds", leg_bounds), ("time_to_dos", leg_time_to_dos)):
         if name in legs:
@@ -804,6 +880,22 @@ def main():
             out[name] = fn()
             torch.cuda.synchronize()
             torch.cuda.empty_cache()
+    # custom roofline: P* = min(b, P*_LLC) per R against the full-size measurement of the same kernel
+    if "custom_roofline" in out and "variants" in out:
+        full = {(p["R"], p["kernel"]): p for p in out["variants"]["points"] if p["variant"] == "full"}
+        for p in out["custom_roofline"]["points"]:
+            q = full.get((p["R"], p["kernel"]))
+            p["mem_bound_GBps"] = b_meas
+            p["p_star_GBps"] = round(min(b_meas, p["llc_GBps"]), 1)
+            if q:
+                p["full_size_GBps"] = q["GBps"]
+                p["full_size_frac_of_p_star"] = round(q["GBps"] / p["p_star_GBps"], 3)
+        if "batched" in out:
+            cb = out["custom_roofline"]["batched"]
+            cb["mem_bound_GBps"] = b_meas
+            cb["p_star_GBps"] = round(min(b_meas, cb["llc_GBps"]), 1)
+            cb["family512_GBps"] = out["batched"]["GBps"]
+            cb["family512_frac_of_p_star"] = round(out["batched"]["GBps"] / cb["p_star_GBps"], 3)
     # fractions of the measured bandwidth b beside those of the 8 TB/s peak
     for rec in [out.get("precision", {}).get(d, {}) for d in ("c128", "c64")] + [out.get("batched", {})] + \
             out.get("slab", {}).get("points", []):
