@@ -44,6 +44,7 @@ KERNEL_SOURCES = {
     "lattice_kernel": ["kpm_lattice.hip", "kpm_sweep.h"],
     "aug_spmmv_kernel": ["kpm_sweep.h", "kpm_sweep_c128_large.hip", "kpm_sweep_c64_large.hip"],
     "gather_sweep_kernel": ["kpm_gather.h", "kpm_batched.h", "kpm_gather_c128.hip", "kpm_gather_c64.hip"],
+    "window_sweep_kernel": ["kpm_gather.h", "kpm_batched.h", "kpm_gather_c128.hip", "kpm_gather_c64.hip"],
 }
 
 

@@ -337,9 +337,21 @@ kpm_status kpm_moment_features(const double* mu, int32_t n_inst, int32_t R, int3
  *   gather       which generic sweep runs where the lattice sweep does not:
  *                0 the staged-gather sweep for R != 32 and the
  *                scalar-operand sweep for R = 32; 1 (default) the
- *                staged-gather sweep for every R (at R = 32 on 64^3 it takes
- *                568 us per sweep against 676 us); 2 the scalar-operand
- *                sweep for every R.  The
+ *                staged-gather sweep for every R, as its LDS-window variant
+ *                where that exists (complex128 R >= 16, complex64 R >= 32)
+ *                and the lattice gives at least one run of z-planes of a
+ *                tile per CU; 2 the scalar-operand sweep for every R; 3 the
+ *                window variant wherever it exists (any lattice size); 4
+ *                the staged-gather sweep without the window variant.  The
+ *                window variant walks the lattice in pencils (one
+ *                workgroup per run of z-planes of a 4 x 4-site tile, 2 x 2
+ *                at complex128 R = 64), keeps the tile's planes z - 1, z,
+ *                z + 1 of V in an LDS ring and gathers only the other
+ *                neighbours from memory; it still reads the column indices
+ *                (each is decoded once, when the matrix rows of a pass are
+ *                staged), so any matrix over the lattice's rows gives the
+ *                staged-gather result (on 64^3 at R = 32: 426 us per sweep
+ *                against 580 us).  The
  *                staged-gather sweep (one lane per 16 bytes of a block row,
  *                matrix rows copied into LDS a pass ahead) uses only
  *                wg_per_cu and xcd_ways of the fields above, and needs the
@@ -362,6 +374,17 @@ kpm_status kpm_moment_features(const double* mu, int32_t n_inst, int32_t R, int3
  *                the index arithmetic costs more occupancy than it saves,
  *                and the natural order runs); 0 = natural row order;
  *                default 4
+ *   gather_tile  staged-gather sweep with passes of at most one site (R >= 16
+ *                in complex128, R >= 32 in complex64) on a lattice: pencil
+ *                order, one workgroup per run of z-planes of a tile of
+ *                gather_tile x gather_tile sites, its waves sharing each
+ *                plane of the tile, so that the V rows a pass gathers were
+ *                fetched at most a plane earlier by the same workgroup or by
+ *                the adjacent tile's on the same die (tiles dealt to the
+ *                dies in 2-D blocks where the tile grid allows); the matrix
+ *                and W streams then carry the non-temporal hint when
+ *                `stream` is nonzero.  0: the natural (or slab) order;
+ *                default 0
  * kpm_set_sweep_tuning(NULL) restores the defaults.  Errors: KPM_EINVAL
  * (negative field). */
 typedef struct kpm_sweep_tuning {
@@ -376,13 +399,15 @@ typedef struct kpm_sweep_tuning {
     int32_t gather;
     int32_t tile_order;
     int32_t slab;
+    int32_t gather_tile;
 } kpm_sweep_tuning;
 kpm_status kpm_set_sweep_tuning(const kpm_sweep_tuning* tuning);
 kpm_status kpm_get_sweep_tuning(kpm_sweep_tuning* tuning);
 
 /* Which sweep kernel kpm_moments / kpm_aug_spmmv launch for H at block
  * width R under the current tuning: *kernel = 0 scalar-operand gather
- * sweep, 1 cache-blocked lattice sweep, 2 staged-gather sweep.
+ * sweep, 1 cache-blocked lattice sweep, 2 staged-gather sweep, 3 its
+ * LDS-window variant.
  * Errors: KPM_EINVAL. */
 kpm_status kpm_sweep_kernel(const kpm_hamiltonian* H, int32_t R, int32_t* kernel);
 

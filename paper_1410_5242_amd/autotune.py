@@ -35,7 +35,7 @@ DEFAULT_CACHE = os.environ.get(
 DTYPE_NAMES = {0: "c128", 1: "c64"}
 
 SWEEP_FIELDS = ("wg_per_cu", "xcd_ways", "chunk_tiles", "pencil", "dynamic", "prefetch", "stream", "lattice",
-                "gather", "tile_order", "slab")
+                "gather", "tile_order", "slab", "gather_tile")
 BATCH_FIELDS = ("waves", "wg_per_cu", "dynamic", "slab")
 
 
@@ -60,13 +60,23 @@ def width_key(dtype: int, S: int, N: int) -> str:
 def sweep_candidates(R: int, lattice_ok: bool) -> list[dict]:
     """Launch shapes of the fused sweep worth timing at block width R."""
     base = dict(wg_per_cu=0, xcd_ways=8, chunk_tiles=8, pencil=16, dynamic=0, prefetch=2, stream=3, lattice=0,
-                gather=1, tile_order=0, slab=4)
+                gather=1, tile_order=0, slab=4, gather_tile=0)
     out = []
-    # staged-gather sweep: workgroups per CU and die-aware ranges
-    for wg in (0, 1, 2, 4):
-        for xcd in (8, 1):
-            for slab in (0, 2, 4, 8):
-                out.append(dict(base, wg_per_cu=wg, xcd_ways=xcd, slab=slab))
+    # staged-gather sweep: workgroups per CU and die-aware ranges (from R = 16 on,
+    # gather 1 runs its window variant on large lattices; gather 4 keeps the
+    # plain staged gather, alone or in pencil order)
+    for g in ((1, 4) if R >= 16 else (1,)):
+        for wg in (0, 1, 2, 4):
+            for xcd in (8, 1):
+                for slab in (0, 2, 4, 8):
+                    out.append(dict(base, gather=g, wg_per_cu=wg, xcd_ways=xcd, slab=slab))
+    if R >= 16:
+        for wg in (1, 2):
+            out.append(dict(base, gather=4, wg_per_cu=wg, gather_tile=4))
+        # window variant: tiles dealt to the dies in blocks or not, streams
+        # cached or not (blocks with non-temporal streams is the base above)
+        for order, stream in ((2, 3), (0, 0), (2, 0)):
+            out.append(dict(base, gather=1, tile_order=order, stream=stream))
     # scalar-operand sweep
     for wg in (4, 8):
         for chunk in (4, 8, 16):

@@ -273,6 +273,105 @@ template <> struct PassOrder<false> {
     __device__ void advance() { w.advance(); }
 };
 
+// Work item k of the pencil order (TileGeom) for die `die`, whose items are
+// k_lo .. : tile origin (x0, y0), extent ex x ey sites, planes [z0, z1).
+__host__ __device__ inline void tile_item(const TileGeom& g, uint32_t k, uint32_t k_lo, uint32_t die, uint32_t& x0,
+                                          uint32_t& y0, uint32_t& ex, uint32_t& ey, uint32_t& z0, uint32_t& z1) {
+    uint32_t tx, ty, piece;
+    if (g.bw) {
+        const uint32_t tpd = g.bw * g.bh, i = k - k_lo, t = i % tpd;
+        piece = i / tpd;
+        tx = (die % 2) * g.bw + t % g.bw;
+        ty = (die / 2) * g.bh + t / g.bw;
+    } else {
+        const uint32_t nt = g.ntiles(), t = k % nt;
+        piece = k / nt;
+        tx = t % g.ntx;
+        ty = t / g.ntx;
+    }
+    z0 = piece * g.Lz / g.npieces;
+    z1 = (piece + 1) * g.Lz / g.npieces;
+    x0 = tx * g.side;
+    y0 = ty * g.side;
+    ex = g.Lx - x0 < g.side ? g.Lx - x0 : g.side;
+    ey = g.Ly - y0 < g.side ? g.Ly - y0 : g.side;
+}
+
+// Pencil order walked by one wave of the staged-gather sweep (TileGeom):
+// workgroup `block` of `grid` works for die block % dies and takes that
+// die's items k, k + per, ... (per = grid / dies workgroups per die); inside
+// an item the waves of the workgroup take its passes wave, wave + waves, ...
+// The pass is kept as digits (plane, line, piece of line) and the stride is
+// added digit by digit; an item a wave has no pass in is skipped.
+struct TileWalk {
+    TileGeom g;
+    uint32_t die = 0, X = 1, k = 0, k_lo = 0, k_hi = 0, per = 1, first = 0, step = 1;
+    uint32_t nz = 0, ey = 0, ppl = 1;       // planes, lines, passes per line of the item
+    uint32_t sz = 0, sl = 0, so = 0;        // stride as digits
+    uint32_t z = 0, line = 0, o = 0;        // current pass as digits
+    int64_t base = 0;                       // first row of the item (plane z0, line y0, site x0)
+
+    // set up item k; false past the die's last item
+    __host__ __device__ bool load() {
+        if (k >= k_hi) return false;
+        uint32_t x0, y0, ex, z0, z1;
+        tile_item(g, k, k_lo, die, x0, y0, ex, ey, z0, z1);
+        nz = z1 - z0;
+        ppl = 4 * ex / g.rpw;
+        const uint32_t ppp = ey * ppl;
+        sz = step / ppp;
+        sl = (step % ppp) / ppl;
+        so = (step % ppp) % ppl;
+        z = first / ppp;
+        line = (first % ppp) / ppl;
+        o = (first % ppp) % ppl;
+        base = static_cast<int64_t>(z0) * g.plane_rows + static_cast<int64_t>(y0) * g.line_rows + 4 * x0;
+        return true;
+    }
+    // move to the first item (from k on) that has a pass for this wave
+    __host__ __device__ void settle() {
+        while (load() && z >= nz) k += per;
+    }
+    __host__ __device__ void init(const TileGeom& geom, uint32_t block, uint32_t grid, uint32_t dies,
+                                  uint32_t wave, uint32_t waves) {
+        g = geom;
+        X = (dies > 1 && grid % dies == 0) ? dies : 1;
+        if (X != 8) g.bw = g.bh = 0;
+        die = block % X;
+        per = grid / X;
+        const uint32_t n = g.nitems();
+        k_lo = static_cast<uint32_t>(static_cast<uint64_t>(n) * die / X);
+        k_hi = static_cast<uint32_t>(static_cast<uint64_t>(n) * (die + 1) / X);
+        k = k_lo + block / X;
+        first = wave;
+        step = waves;
+        settle();
+    }
+    __host__ __device__ void cur(int64_t& row0, int64_t& nr) const {
+        if (k >= k_hi) {
+            row0 = g.nrows;
+            nr = 0;
+            return;
+        }
+        row0 = base + static_cast<int64_t>(z) * g.plane_rows + static_cast<int64_t>(line) * g.line_rows + o * g.rpw;
+        nr = g.rpw;
+    }
+    __host__ __device__ void advance() {
+        if (k >= k_hi) return;
+        o += so;
+        uint32_t c = o >= ppl ? 1u : 0u;
+        o -= c * ppl;
+        line += sl + c;
+        c = line >= ey ? 1u : 0u;
+        line -= c * ey;
+        z += sz + c;
+        if (z >= nz) {
+            k += per;
+            settle();
+        }
+    }
+};
+
 template <typename T, int R, int WAVES>
 constexpr int lds_bytes() {
     using S = ValShape<T, R>;

@@ -102,6 +102,9 @@ struct SweepArgs {
     int stream = 0;
     int L[3] = {0, 0, 0};   // lattice sides of H (rows 4 (x + Lx (y + Ly z)) + o)
     int slab = 0;           // staged-gather sweep: y-lines per block of the pass order
+    int tile = 0;           // staged-gather sweep: tile side of the pencil order (0: off)
+    int window = 0;         // staged-gather sweep: run its LDS-window variant (on a lattice)
+    int order = 0;          // window sweep: 2 = no die mapping of its tiles (tuning tile_order)
 };
 
 // Cache-blocked sweep for the library's lattice Hamiltonians at R = 32 k.
@@ -181,6 +184,52 @@ struct SlabGeom {
     }
 };
 
+// Geometry of the pencil order of one lattice (staged-gather sweep), built
+// on the host.  The x-y plane is cut into tiles of side x side sites (tiles
+// at the lattice edge may be narrower), and each tile's column of sites into
+// npieces runs of consecutive z-planes; a work item is one run of one tile,
+// walked plane by plane, line by line, in passes of rpw rows (rpw divides
+// the 4 rows of a site, so no pass straddles two lines).  Items go to the
+// dies as 2-D blocks of bw x bh tiles where the tile grid splits that way
+// (most rows a tile gathers across its edge then belong to tiles whose
+// planes the same L2 holds), else as runs of consecutive items.
+struct TileGeom {
+    uint32_t Lx = 1, Ly = 1, Lz = 1, side = 1, ntx = 1, nty = 1, npieces = 1, rpw = 1;
+    uint32_t bw = 0, bh = 0;
+    uint32_t dies = 1;                  // dies the items are split over (1: no die mapping)
+    uint32_t line_rows = 0, plane_rows = 0;
+    int64_t nrows = 0;
+
+    __host__ __device__ uint32_t ntiles() const { return ntx * nty; }
+    __host__ __device__ uint32_t nitems() const { return ntx * nty * npieces; }
+
+    // npieces: enough items for `grid` workgroups, at least 4 planes per run
+    static TileGeom make(int Lx, int Ly, int Lz, int side, int rpw, int grid, int dies) {   // host
+        TileGeom g;
+        g.Lx = static_cast<uint32_t>(Lx);
+        g.Ly = static_cast<uint32_t>(Ly);
+        g.Lz = static_cast<uint32_t>(Lz);
+        const int s = side < 1 ? 1 : side;
+        g.side = static_cast<uint32_t>(s);
+        g.ntx = static_cast<uint32_t>((Lx + s - 1) / s);
+        g.nty = static_cast<uint32_t>((Ly + s - 1) / s);
+        g.rpw = static_cast<uint32_t>(rpw);
+        const uint32_t nt = g.ntiles();
+        uint32_t np = grid > 0 ? (static_cast<uint32_t>(grid) + nt - 1) / nt : 1;
+        const uint32_t cap = Lz >= 8 ? static_cast<uint32_t>(Lz / 4) : 1;
+        g.npieces = np < 1 ? 1 : (np > cap ? cap : np);
+        g.dies = dies > 1 ? static_cast<uint32_t>(dies) : 1u;
+        if (dies == 8 && g.ntx % 2 == 0 && g.nty % 4 == 0) {
+            g.bw = g.ntx / 2;
+            g.bh = g.nty / 4;
+        }
+        g.line_rows = 4u * g.Lx;
+        g.plane_rows = g.line_rows * g.Ly;
+        g.nrows = static_cast<int64_t>(g.plane_rows) * g.Lz;
+        return g;
+    }
+};
+
 // One instance of the batched solver (device-side descriptor).
 struct BatchInst {
     const void* val;        // H: [N][kWidth] complex, diagonal in slot 0 (the builder's slot order:
@@ -245,10 +294,13 @@ kpm_status check_tuning(const kpm_sweep_tuning& t);
 // true = the staged-gather sweep, false = the scalar-operand sweep.
 bool use_gather(int dtype, int R, int64_t nrows);
 // Grid size (workgroups) of the generic sweep kernel for this dtype / R / N.
-int sweep_grid(int dtype, int R, int64_t nrows);
+// (window: the LDS-window variant of the staged-gather sweep runs)
+int sweep_grid(int dtype, int R, int64_t nrows, bool window = false);
 hipError_t launch_gather(int dtype, int R, int variant, const SweepArgs& a, hipStream_t s);
 int gather_waves(int dtype, int R);
 int gather_lds(int dtype, int R);
+int gather_window_lds(int dtype, int R);    // 0 where the window sweep does not exist
+int gather_window_side(int dtype, int R);   // its tile side in sites (0: none)
 hipError_t launch_sweep(int dtype, int R, int variant, const SweepArgs& a, hipStream_t s);
 // per-precision instantiations of the sweep kernel (R <= 16 and R >= 32)
 hipError_t launch_sweep_c128_small(int R, int variant, const SweepArgs& a, hipStream_t s);

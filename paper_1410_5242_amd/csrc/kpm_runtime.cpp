@@ -103,8 +103,33 @@ bool sweep_uses_queue(const kpm_hamiltonian* H, int R) {
     return !use_lattice(H, R) && !use_gather(H->dtype, R, H->nrows) && get_tuning().dynamic != 0;
 }
 
+// The LDS-window variant of the staged-gather sweep (tuning gather 1:
+// where it exists and the lattice gives at least one run of z-planes of a
+// tile per CU; 3: wherever it exists).
+bool use_window(const kpm_hamiltonian* H, int R) {
+    const int g = get_tuning().gather;
+    if ((g != 1 && g != 3) || use_lattice(H, R) || !use_gather(H->dtype, R, H->nrows)) return false;
+    const int side = gather_window_side(H->dtype, R);
+    if (side <= 0 || H->L[0] <= 0) return false;
+    if (g == 3) return true;
+    const int64_t ntiles = static_cast<int64_t>((H->L[0] + side - 1) / side) * ((H->L[1] + side - 1) / side);
+    const int64_t cus = device_cus();
+    const int64_t cap = H->L[2] >= 8 ? H->L[2] / 4 : 1;
+    int64_t np = (cus + ntiles - 1) / ntiles;
+    np = np < 1 ? 1 : (np > cap ? cap : np);
+    return ntiles * np >= cus;
+}
+
 int launch_grid(const kpm_hamiltonian* H, int R) {
-    return use_lattice(H, R) ? lattice_grid(H) : sweep_grid(H->dtype, R, H->nrows);
+    return use_lattice(H, R) ? lattice_grid(H) : sweep_grid(H->dtype, R, H->nrows, use_window(H, R));
+}
+
+// Sweep kernel kind (kpm_sweep_kernel): 1 lattice, 3 window, 2 staged
+// gather, 0 scalar operand.
+int sweep_kind(const kpm_hamiltonian* H, int R) {
+    if (use_lattice(H, R)) return 1;
+    if (!use_gather(H->dtype, R, H->nrows)) return 0;
+    return use_window(H, R) ? 3 : 2;
 }
 
 kpm_status ensure_partials(Workspace& w, const kpm_hamiltonian* H, int R, int slots) {
@@ -240,7 +265,9 @@ hipError_t launch_any_sweep(kpm_hamiltonian* H, int R, int variant, const SweepA
                        t.prefetch, t.stream, lattice_order(H, a.grid), R};
         return profiled(s, capturing, [&] { return launch_lattice(H->dtype, variant, la, s); });
     }
-    return profiled(s, capturing, [&] { return launch_sweep(H->dtype, R, variant, a, s); });
+    SweepArgs g = a;
+    g.window = use_window(H, R) ? 1 : 0;
+    return profiled(s, capturing, [&] { return launch_sweep(H->dtype, R, variant, g, s); });
 }
 
 // ---- batched solver: launch shape (process-wide) and state per (device, stream) ----
@@ -982,7 +1009,7 @@ kpm_status kpm_sweep_kernel(const kpm_hamiltonian* Hc, int32_t R, int32_t* kerne
     g_error.clear();
     if (!Hc || !kernel) return fail(KPM_EINVAL, "H or kernel is NULL");
     TuningScope scope(nullptr);
-    *kernel = use_lattice(Hc, R) ? 1 : (use_gather(Hc->dtype, R, Hc->nrows) ? 2 : 0);
+    *kernel = sweep_kind(Hc, R);
     return KPM_OK;
 }
 
@@ -995,7 +1022,7 @@ kpm_status kpm_sweep_plan(const kpm_hamiltonian* Hc, int32_t R, const kpm_sweep_
     if (tuning && (st = check_tuning(*tuning)) != KPM_OK) return st;
     TuningScope scope(tuning);
     const bool lat = use_lattice(Hc, R);
-    out->kernel = lat ? 1 : (use_gather(Hc->dtype, R, Hc->nrows) ? 2 : 0);
+    out->kernel = sweep_kind(Hc, R);
     out->grid = launch_grid(Hc, R);
     out->tile_order = lat ? lattice_order(Hc, out->grid) : -1;
     out->pieces = lat ? lattice_pieces(Hc, R, out->grid, get_tuning().prefetch) : -1;

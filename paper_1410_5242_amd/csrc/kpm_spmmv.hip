@@ -88,8 +88,8 @@ check_moments_kernel(const double* __restrict__ mu, int R, int M, int* __restric
 
 namespace {
 // wg_per_cu, xcd_ways, chunk_tiles, pencil, dynamic, prefetch, stream,
-// lattice, gather, tile_order, slab
-constexpr kpm_sweep_tuning kDefaultTuning = {0, kXcds, 8, 16, 0, 2, 3, 1, 1, 3, 4};
+// lattice, gather, tile_order, slab, gather_tile
+constexpr kpm_sweep_tuning kDefaultTuning = {0, kXcds, 8, 16, 0, 2, 3, 1, 1, 3, 4, 0};
 std::mutex g_tuning_lock;
 kpm_sweep_tuning g_tuning = kDefaultTuning;
 thread_local const kpm_sweep_tuning* t_call = nullptr;   // snapshot of the running call
@@ -116,11 +116,12 @@ TuningScope::~TuningScope() { t_call = prev_; }
 kpm_status check_tuning(const kpm_sweep_tuning& t) {
     if (t.wg_per_cu < 0 || t.xcd_ways < 0 || t.chunk_tiles < 0 || t.pencil < 0 || t.dynamic < 0 ||
         t.prefetch < 0 || t.prefetch > 2 || t.stream < 0 || t.stream > 3 || t.lattice < 0 || t.lattice > 2 ||
-        t.gather < 0 || t.gather > 2 || t.tile_order < 0 || t.tile_order > 3 || t.slab < 0) {
+        t.gather < 0 || t.gather > 4 || t.tile_order < 0 || t.tile_order > 3 || t.slab < 0 || t.gather_tile < 0) {
         set_error("tuning field out of range (negative, or above its largest option)");
         return KPM_EINVAL;
     }
-    if (t.wg_per_cu > 64 || t.xcd_ways > 64 || t.chunk_tiles > (1 << 20) || t.pencil > 4096 || t.slab > 65536) {
+    if (t.wg_per_cu > 64 || t.xcd_ways > 64 || t.chunk_tiles > (1 << 20) || t.pencil > 4096 || t.slab > 65536 ||
+        t.gather_tile > 4096) {
         set_error("tuning field out of range");
         return KPM_EINVAL;
     }
@@ -149,16 +150,18 @@ bool use_gather(int dtype, int R, int64_t nrows) {
     const uint64_t lim = (1ull << 32) - (1ull << 24);
     const uint64_t n = static_cast<uint64_t>(nrows);
     if (n * R * 2 * rs >= lim || n * kWidth * 2 * rs >= lim) return false;
-    return g_tuning.gather == 1 || R != 32;
+    return g_tuning.gather == 1 || g_tuning.gather >= 3 || R != 32;
 }
 
-int sweep_grid(int dtype, int R, int64_t nrows) {
+int sweep_grid(int dtype, int R, int64_t nrows, bool window) {
     const kpm_sweep_tuning g_tuning = get_tuning();
     int per_cu;
     if (use_gather(dtype, R, nrows)) {
         // 16 waves per CU by default, no more workgroups than the LDS holds
-        const int w = gather_waves(dtype, R);
-        const int fit = (160 * 1024) / gather_lds(dtype, R);
+        // (the window sweep's ring: one workgroup of 8 waves per CU)
+        const int wl = window ? gather_window_lds(dtype, R) : 0;
+        const int w = wl ? 16 : gather_waves(dtype, R);
+        const int fit = (160 * 1024) / (wl ? wl : gather_lds(dtype, R));
         per_cu = g_tuning.wg_per_cu > 0 ? g_tuning.wg_per_cu : 16 / w;
         if (per_cu > fit) per_cu = fit > 0 ? fit : 1;
     } else {
@@ -173,11 +176,13 @@ hipError_t launch_sweep(int dtype, int R, int variant, const SweepArgs& a_in, hi
     SweepArgs a = a_in;
     a.xcd_ways = g_tuning.xcd_ways > 0 ? g_tuning.xcd_ways : 1;
     a.slab = g_tuning.slab;
+    a.tile = g_tuning.gather_tile;
+    a.order = g_tuning.tile_order;
+    a.stream = g_tuning.stream;
     if (use_gather(dtype, R, a.nrows)) return launch_gather(dtype, R, variant, a, s);
     a.chunk = g_tuning.chunk_tiles > 0 ? g_tuning.chunk_tiles : 1;
     if (!g_tuning.dynamic) a.queue = nullptr;
     a.prefetch = g_tuning.prefetch == 1 ? 1 : 0;   // the touch pass is option 1 only
-    a.stream = g_tuning.stream;
     if (dtype == KPM_C128) return R >= 32 ? launch_sweep_c128_large(R, variant, a, s)
                                           : launch_sweep_c128_small(R, variant, a, s);
     return R >= 32 ? launch_sweep_c64_large(R, variant, a, s) : launch_sweep_c64_small(R, variant, a, s);

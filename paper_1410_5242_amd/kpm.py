@@ -38,7 +38,7 @@ class SweepTuning(ctypes.Structure):
     _fields_ = [("wg_per_cu", ctypes.c_int32), ("xcd_ways", ctypes.c_int32), ("chunk_tiles", ctypes.c_int32),
                 ("pencil", ctypes.c_int32), ("dynamic", ctypes.c_int32), ("prefetch", ctypes.c_int32),
                 ("stream", ctypes.c_int32), ("lattice", ctypes.c_int32), ("gather", ctypes.c_int32),
-                ("tile_order", ctypes.c_int32), ("slab", ctypes.c_int32)]
+                ("tile_order", ctypes.c_int32), ("slab", ctypes.c_int32), ("gather_tile", ctypes.c_int32)]
 
 
 class BatchTuning(ctypes.Structure):
@@ -516,16 +516,17 @@ def moment_features(mu: torch.Tensor, n_mom: int, extra: torch.Tensor | None = N
 
 
 DEFAULT_SWEEP_TUNING = {"wg_per_cu": 0, "xcd_ways": 8, "chunk_tiles": 8, "pencil": 16, "dynamic": 0,
-                        "prefetch": 2, "stream": 3, "lattice": 1, "gather": 1, "tile_order": 3, "slab": 4}
+                        "prefetch": 2, "stream": 3, "lattice": 1, "gather": 1, "tile_order": 3, "slab": 4,
+                        "gather_tile": 0}
 
 
 def set_sweep_tuning(wg_per_cu: int = 0, xcd_ways: int = 8, chunk_tiles: int = 8, pencil: int = 16,
                      dynamic: int = 0, prefetch: int = 2, stream: int = 3, lattice: int = 1, gather: int = 1,
-                     tile_order: int = 3, slab: int = 4):
+                     tile_order: int = 3, slab: int = 4, gather_tile: int = 0):
     """kpm_set_sweep_tuning: launch shape and site order of the sweep kernel (process-wide)."""
     _check(lib().kpm_set_sweep_tuning(ctypes.byref(SweepTuning(wg_per_cu, xcd_ways, chunk_tiles, pencil,
                                                                dynamic, prefetch, stream, lattice, gather,
-                                                               tile_order, slab))))
+                                                               tile_order, slab, gather_tile))))
 
 
 def reset_sweep_tuning():
@@ -537,14 +538,18 @@ def get_sweep_tuning():
     _check(lib().kpm_get_sweep_tuning(ctypes.byref(t)))
     return {"wg_per_cu": t.wg_per_cu, "xcd_ways": t.xcd_ways, "chunk_tiles": t.chunk_tiles, "pencil": t.pencil,
             "dynamic": t.dynamic, "prefetch": t.prefetch, "stream": t.stream,
-            "lattice": t.lattice, "gather": t.gather, "tile_order": t.tile_order, "slab": t.slab}
+            "lattice": t.lattice, "gather": t.gather, "tile_order": t.tile_order, "slab": t.slab,
+            "gather_tile": t.gather_tile}
+
+
+SWEEP_KERNELS = {0: "aug_spmmv_kernel", 1: "lattice_kernel", 2: "gather_sweep_kernel", 3: "window_sweep_kernel"}
 
 
 def sweep_kernel(H: Hamiltonian, R: int) -> str:
     """kpm_sweep_kernel: name of the sweep kernel used for H at block width R."""
     k = ctypes.c_int32()
     _check(lib().kpm_sweep_kernel(H.handle, int(R), ctypes.byref(k)))
-    return {0: "aug_spmmv_kernel", 1: "lattice_kernel", 2: "gather_sweep_kernel"}[k.value]
+    return SWEEP_KERNELS[k.value]
 
 
 def sweep_plan(H: Hamiltonian, R: int, tuning: dict | None = None) -> dict:
@@ -552,8 +557,7 @@ def sweep_plan(H: Hamiltonian, R: int, tuning: dict | None = None) -> dict:
     p = SweepPlan()
     t = _tuning_struct(tuning)
     _check(lib().kpm_sweep_plan(H.handle, int(R), ctypes.byref(t) if t is not None else None, ctypes.byref(p)))
-    names = {0: "aug_spmmv_kernel", 1: "lattice_kernel", 2: "gather_sweep_kernel"}
-    return {"kernel": names[p.kernel], "grid": p.grid, "tile_order": p.tile_order, "pieces": p.pieces,
+    return {"kernel": SWEEP_KERNELS[p.kernel], "grid": p.grid, "tile_order": p.tile_order, "pieces": p.pieces,
             "halves": p.halves}
 
 

@@ -67,7 +67,7 @@ def test_argument_validation_without_device(L):
     assert L.kpm_moments(fake, fake, 1, 7, fake, ctypes.byref(opts), None) == kpm.KPM_EINVAL      # odd M
     assert L.kpm_moments(fake, fake, 3, 8, fake, ctypes.byref(opts), None) == kpm.KPM_ENOTSUP     # R
     assert L.kpm_moments(fake, ctypes.c_void_p(0x1008), 1, 8, fake, ctypes.byref(opts), None) == kpm.KPM_EINVAL
-    bad = kpm.SweepTuning(*[0] * 11)
+    bad = kpm.SweepTuning(*[0] * 12)
     bad.prefetch = 9
     opts.tuning = ctypes.pointer(bad)   # a per-call tuning is validated like kpm_set_sweep_tuning
     assert L.kpm_moments(fake, fake, 1, 8, fake, ctypes.byref(opts), None) == kpm.KPM_EINVAL

@@ -176,7 +176,8 @@ def test_sweep_plan_of_the_headline_lattice():
     assert K.sweep_plan(H, 64)["halves"] == 2
     g = K.sweep_plan(H, 8)
     assert g["kernel"] == "gather_sweep_kernel" and g["pieces"] == -1
-    assert K.sweep_plan(H, 32, tuning={"lattice": 0})["kernel"] == "gather_sweep_kernel"
+    assert K.sweep_plan(H, 32, tuning={"lattice": 0})["kernel"] == "window_sweep_kernel"
+    assert K.sweep_plan(H, 32, tuning={"lattice": 0, "gather": 4})["kernel"] == "gather_sweep_kernel"
     H.close()
 
 

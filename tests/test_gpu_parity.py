@@ -437,7 +437,8 @@ def test_dos_matches_oracle(kernel, kparam):
     v0 = inputs.phase_block(Ho.n, R, 3)
     mu = O.kpm_moments(Ho, a, b, v0, M)
     E = np.concatenate([O.midpoint_grid(777, a, b), [b - a, b + a, b + 2 * a, b - 3 * a]])
-    g = {"jackson": O.jackson(M), "dirichlet": O.dirichlet(M), "lorentz": O.lorentz(M, kparam)}[kernel]
+    g = {"jackson": lambda: O.jackson(M), "dirichlet": lambda: O.dirichlet(M),
+         "lorentz": lambda: O.lorentz(M, kparam)}[kernel]()
     ref = O.dos(mu, g, a, b, E)
     rho = K.dos(torch.from_numpy(mu).cuda(), a, b, torch.from_numpy(E).cuda(), kernel=kernel, kparam=kparam)
     got = rho.cpu().numpy()
@@ -634,6 +635,127 @@ def test_gather_slab_order_matches_oracle(slab, R):
     finally:
         K.reset_sweep_tuning()
     assert np.abs(mu - ref).max() <= TOL_C128
+
+
+# The LDS-window variant of the staged-gather sweep (tuning gather 3 forces it on
+# any lattice): pencils of 4 x 4-site tiles (2 x 2 at complex128 R = 64), tiles cut
+# by the lattice edge (sides 9, 7 and 6 are not multiples of 4), open and periodic
+# sides, one and several runs of z-planes per tile, both tile-to-die mappings.
+WINDOW_CASES = [((9, 7, 5), (1, 1, 0)), ((6, 9, 8), (0, 1, 1)), ((4, 4, 12), (1, 1, 1)), ((3, 5, 2), (1, 0, 0))]
+
+
+@pytest.mark.parametrize("L,periodic", WINDOW_CASES)
+@pytest.mark.parametrize("R", [16, 32, 64])
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_window_sweep_matches_oracle(L, periodic, R, dtype):
+    K = kpm()
+    M = 40
+    say("window sweep", L, periodic, R, dtype)
+    pot, Ho, a, b = oracle_problem(L, 1.0, 25, periodic=periodic)
+    v0 = inputs.phase_block(Ho.n, R, 26)
+    ref = O.kpm_moments(Ho, a, b, v0, M)
+    exists = not (dtype == "c64" and R == 16)   # complex64 R = 16: passes span more than one site
+    try:
+        K.set_sweep_tuning(lattice=0, gather=3)
+        H = K.build_hamiltonian(L, pot, periodic=periodic, dtype=dtype)
+        assert K.sweep_kernel(H, R) == ("window_sweep_kernel" if exists else "gather_sweep_kernel")
+        H.close()
+        mu, _ = gpu_moments(L, pot, v0, M, dtype=dtype, periodic=periodic)
+    finally:
+        K.reset_sweep_tuning()
+    assert np.abs(mu - ref).max() <= (TOL_C128 if dtype == "c128" else TOL_C64)
+
+
+@pytest.mark.parametrize("R,dtype", [(16, "c128"), (32, "c128"), (64, "c128"), (32, "c64"), (64, "c64")])
+@pytest.mark.parametrize("order", [0, 2])
+def test_window_sweep_writes_the_staged_gather_result(R, dtype, order):
+    # every row's products are formed in the same order from the same values, so
+    # the window sweep's W equals the plain staged-gather sweep's bit for bit; the
+    # scalar products differ only by summation order.  16 x 16 x 12: 16 tiles in a
+    # 2 x 4 split for the dies (tile order 0) or none (2); three z-runs per tile.
+    K = kpm()
+    L = (16, 16, 12)
+    say("window vs staged gather", R, dtype, order)
+    H = K.build_hamiltonian(L, inputs.potential(L, 1.0, 27), dtype=dtype)
+    V = K.random_phase_block(H.N, R, 1, dtype)
+    W0 = K.random_phase_block(H.N, R, 2, dtype)
+    out = {}
+    try:
+        for g in (4, 3):
+            K.set_sweep_tuning(lattice=0, gather=g, tile_order=order)
+            assert K.sweep_kernel(H, R) == ("window_sweep_kernel" if g == 3 else "gather_sweep_kernel")
+            for var in ("full", "nodot", "plain"):
+                W = W0.clone()
+                eta = torch.zeros((2, R, 2), dtype=torch.float64, device="cuda") if var == "full" else None
+                K.aug_spmmv(H, V, W, 2.0 / H.a, -2.0 * H.b / H.a, -1.0, var, eta)
+                torch.cuda.synchronize()
+                out[(g, var)] = (W.cpu(), None if eta is None else eta.cpu())
+    finally:
+        K.reset_sweep_tuning()
+        H.close()
+    for var in ("full", "nodot", "plain"):
+        assert torch.equal(out[(3, var)][0], out[(4, var)][0]), var
+    e3, e4 = out[(3, "full")][1], out[(4, "full")][1]
+    assert (e3 - e4).abs().max().item() <= 1e-13 * max(1.0, e4.abs().max().item())
+
+
+@pytest.mark.parametrize("R", [16, 32, 64])
+def test_window_sweep_single_sweep_variants(R):
+    # FULL, NODOT, PLAIN of the window sweep against H X from the oracle's dense matrix
+    K = kpm()
+    L = (9, 6, 7)
+    say("window sweep variants", R)
+    pot, Ho, a, b = oracle_problem(L, 1.0, 28, periodic=(1, 0, 1))
+    Hd = Ho.dense()
+    rng = np.random.default_rng(R + 5)
+    X = rng.standard_normal((Ho.n, R)) + 1j * rng.standard_normal((Ho.n, R))
+    Y = rng.standard_normal((Ho.n, R)) + 1j * rng.standard_normal((Ho.n, R))
+    Hx = Hd @ X
+    alpha, beta, gamma = 0.3, -0.7, -1.0
+    ref = alpha * Hx + beta * X + gamma * Y
+    try:
+        K.set_sweep_tuning(lattice=0, gather=3)
+        H = K.build_hamiltonian(L, pot, periodic=(1, 0, 1))
+        assert K.sweep_kernel(H, R) == "window_sweep_kernel"
+        Vt = torch.from_numpy(X).cuda()
+        Wt = torch.from_numpy(Y.copy()).cuda()
+        K.aug_spmmv(H, Vt, Wt, 1.0, 0.0, 0.0, variant="plain")
+        assert np.abs(Wt.cpu().numpy() - Hx).max() <= 1e-12 * max(1.0, np.abs(Hx).max())
+        Wt = torch.from_numpy(Y.copy()).cuda()
+        K.aug_spmmv(H, Vt, Wt, alpha, beta, gamma, variant="nodot")
+        assert np.abs(Wt.cpu().numpy() - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max())
+        Wt = torch.from_numpy(Y.copy()).cuda()
+        eta = torch.zeros((2, R, 2), dtype=torch.float64, device="cuda")
+        K.aug_spmmv(H, Vt, Wt, alpha, beta, gamma, variant="full", eta=eta)
+        Wn = Wt.cpu().numpy()
+        assert np.abs(Wn - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max())
+        e = eta.cpu().numpy()
+        vv = np.sum(np.abs(X) ** 2, axis=0)
+        wv = np.sum(Wn.conj() * X, axis=0)
+        assert np.abs(e[0, :, 0] - vv).max() <= 1e-12 * vv.max()
+        assert np.abs(e[1, :, 0] + 1j * e[1, :, 1] - wv).max() <= 1e-12 * np.abs(wv).max() * 10
+        H.close()
+    finally:
+        K.reset_sweep_tuning()
+
+
+def test_window_sweep_is_the_default_generic_sweep_on_large_lattices():
+    # gather 1 (default): the window variant where the lattice gives a run of
+    # z-planes of a tile per CU, the plain staged gather on small lattices
+    K = kpm()
+    say("window default selection")
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    big = K.build_hamiltonian((64, 64, 64), None, gamma=1.0, seed=0)
+    small = K.build_hamiltonian((8, 8, 8), None, gamma=1.0, seed=0)
+    try:
+        assert K.sweep_kernel(big, 16) == "window_sweep_kernel"
+        assert K.sweep_kernel(big, 8) == "gather_sweep_kernel"
+        assert K.sweep_kernel(small, 16) == "gather_sweep_kernel"
+        p = K.sweep_plan(big, 16)
+        assert p["kernel"] == "window_sweep_kernel" and p["grid"] == cus - cus % 8
+    finally:
+        big.close()
+        small.close()
 
 
 @pytest.mark.parametrize("order", [0, 1, 2, 3])
