@@ -365,7 +365,8 @@ def leg_variants(sweeps: int = 10):
     """Single fused sweeps on the 64^3 complex128 lattice for every block width R and the three
     variants (the paper's split of the sweep into plain SpMMV, the update without scalar
     products, and the full fused sweep): GB/s from the library's per-launch HIP events.  At
-    R = 32 and 64 the index-reading staged-gather sweep runs as well, forced by the tuning."""
+    R = 32 and 64 the index-reading sweeps run as well, forced by the tuning: the plain staged
+    gather and its LDS-window variant."""
     import torch
     from paper_1410_5242_amd import autotune, inputs, kpm
     L = (64, 64, 64)
@@ -373,14 +374,15 @@ def leg_variants(sweeps: int = 10):
     N, Sd = H.N, 16
     out = {"workload": f"TI {L[0]}x{L[1]}x{L[2]} periodic, complex128, {sweeps} sweeps per point", "points": []}
     cache = autotune.TuningCache()
-    for R, force_gather in [(R, False) for R in kpm.SUPPORTED_R] + [(32, True), (64, True)]:
+    for R, forced in [(R, None) for R in kpm.SUPPORTED_R] + [(R, g) for R in (32, 64) for g in (4, 3)]:
         kpm.reset_sweep_tuning()
         tuned = autotune.apply_sweep(cache, H, R, L)
-        if force_gather:
-            # the index-reading staged-gather sweep at the widths the lattice sweep takes, in its
-            # best measured shape (two workgroups per CU, no die split, natural row order)
+        if forced is not None:
+            # the index-reading sweeps at the widths the lattice sweep takes: the plain staged
+            # gather (gather 4) in its best measured shape (two workgroups per CU, no die split,
+            # natural row order) and its LDS-window variant (gather 3)
             t = kpm.get_sweep_tuning()
-            t.update(lattice=0, gather=1, wg_per_cu=2, xcd_ways=1, slab=0)
+            t.update(lattice=0, gather=forced, wg_per_cu=2, xcd_ways=1, slab=0)
             kpm.set_sweep_tuning(**t)
             tuned = False
         V = kpm.random_phase_block(N, R, 1, "c128")
