@@ -311,9 +311,11 @@ kpm_status kpm_moment_features(const double* mu, int32_t n_inst, int32_t R, int3
  *                tiles it touches every line of their matrix rows and old
  *                W rows (0 and 2: no touch pass).  Lattice sweep: how the
  *                matrix rows of a site reach the FMAs: 2 one vector load a
- *                step ahead, handed over lane by lane; 1 scalar loads whose
- *                lines a vector load pulled into L2 a step ahead; 0 scalar
- *                loads when the row is computed; default 2
+ *                step ahead, handed over lane by lane (complex128) or
+ *                written to the wave's slot in LDS and read back by all
+ *                lanes at once (complex64); 1 scalar loads whose lines a
+ *                vector load pulled into L2 a step ahead; 0 scalar loads
+ *                when the row is computed; default 2
  *   lattice      1 (default): at R = 32 and 64, on lattices with at least
  *                128 4 x 4-site pencils, use the cache-blocked sweep that
  *                keeps a ring of z-planes of V in LDS (of the other fields

@@ -112,6 +112,9 @@ template <> struct SiteRec<double> {
     static __device__ double im(const V& v, int l) {
         return __hiloint2double(__builtin_amdgcn_readlane(v.w, l), __builtin_amdgcn_readlane(v.z, l));
     }
+    // an entry already in every lane (read back from LDS)
+    static __device__ double re(const V& v) { return __hiloint2double(v.y, v.x); }
+    static __device__ double im(const V& v) { return __hiloint2double(v.w, v.z); }
 };
 template <> struct SiteRec<float> {
     using V = int2;
@@ -121,6 +124,8 @@ template <> struct SiteRec<float> {
     }
     static __device__ float re(const V& v, int l) { return __int_as_float(__builtin_amdgcn_readlane(v.x, l)); }
     static __device__ float im(const V& v, int l) { return __int_as_float(__builtin_amdgcn_readlane(v.y, l)); }
+    static __device__ float re(const V& v) { return __int_as_float(v.x); }
+    static __device__ float im(const V& v) { return __int_as_float(v.y); }
 };
 
 // Exchange with lane ^ 1 (DPP quad_perm [1, 0, 3, 2]); every lane of the wave
@@ -140,7 +145,7 @@ __device__ inline float swap_lanes(float x) {
 template <typename T> struct StepRegs {
     T h[2][4];
     T w[4];
-    typename SiteRec<T>::V hv;   // VALS 1
+    typename SiteRec<T>::V hv;   // VALS 1 and 3
     unsigned warm;               // VALS 2
 };
 
@@ -187,6 +192,10 @@ __device__ inline Nb xy_neighbour(int nx, int ny, int Lx, int Ly, int px, int py
 //   1  one vector load per site a step ahead, v_readlane per entry
 //   2  scalar loads, with the site's rows pulled into L2 by a vector load a
 //      step ahead (the scalar loads then wait on L2, not on HBM)
+//   3  the vector load of 1, written to the wave's slot in LDS at the start
+//      of the step and read back per entry with every lane at the same
+//      address (a broadcast): no v_readlane and none of the wait states a
+//      VALU read of its scalar result needs, at the cost of LDS reads
 
 // NSL: 32-column slices per block row (0: run-time value nsl, for R > 32).
 // SPLIT: pencils are cut into npc z-pieces (run-time npc); otherwise a work
@@ -199,6 +208,12 @@ lattice_kernel(const T* __restrict__ val, const T* __restrict__ V, T* __restrict
     __shared__ T ring[4][kNW][4][kE];
     __shared__ T zrow[4][kE];          // rows of zeros: neighbours beyond an open side
     __shared__ double red[kNW][3][kR];
+    // VALS 3: the step's matrix record of every wave, in the space of the
+    // partial sums (those are written only after a slice's last step, which
+    // ends with a workgroup barrier, and read before the next slice starts)
+    using Rec = typename SiteRec<T>::V;
+    static_assert(VALS != 3 || sizeof(Rec) * kNW * 64 <= sizeof(red), "record slots exceed the partial sums");
+    Rec (*recs)[64] = reinterpret_cast<Rec (*)[64]>(&red[0][0][0]);
 
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -254,7 +269,7 @@ lattice_kernel(const T* __restrict__ val, const T* __restrict__ V, T* __restrict
     // takes a contiguous run of tile rows; order 2: no die mapping
     const bool blocks = order == 0 && X == kXcds && ntx % 2 == 0 && nty % 4 == 0 && !SPLIT;
 
-    constexpr bool VEC_VALS = VALS == 1;
+    constexpr bool VEC_VALS = VALS == 1 || VALS == 3;
     unsigned sink = 0;   // keeps the L2 warm-up loads of VALS == 2
 
     // Blocks wider than 32 columns: every workgroup sweeps its tiles once per
@@ -309,7 +324,7 @@ lattice_kernel(const T* __restrict__ val, const T* __restrict__ V, T* __restrict
         // (product order: slot 0, outer x pair, inner x pair, outer y pair,
         // inner y pair, slots 9..12), so every hand-over reads a fixed lane
         unsigned rec_off = 0;
-        if constexpr (VALS == 1) {
+        if constexpr (VEC_VALS) {
             const int e = min(lane, 4 * kWidth - 1), r = e / kWidth, j = e % kWidth;
             int sl = j;
             if (j >= 1 && j <= 4) sl = (j <= 2) ? j + 2 * dox : j - 2 * dox;
@@ -337,7 +352,7 @@ lattice_kernel(const T* __restrict__ val, const T* __restrict__ V, T* __restrict
 #pragma unroll
             for (int o = 0; o < 4; ++o) r.h[1][o] = gload<T>(hy, voff, roff(4 * (hys + plane_sites * z) + o));
             const int64_t base = 4 * (sxy + plane_sites * z);
-            if constexpr (VALS == 1) r.hv = SiteRec<T>::load(mrs(on && active), rec_off, base / 4);
+            if constexpr (VEC_VALS) r.hv = SiteRec<T>::load(mrs(on && active), rec_off, base / 4);
         };
         // this site's rows of V in plane zp (zeros when off)
         auto load_wold = [&](bool on, int zp, StepRegs<T>& r) {
@@ -386,6 +401,17 @@ lattice_kernel(const T* __restrict__ val, const T* __restrict__ V, T* __restrict
             const T* zdn = plane_of(s - 1) >= 0 ? &ring[(s - 1) & 3][wave][0][lane] : &zrow[0][lane];
             const T* zup = plane_of(s + 1) >= 0 ? &ring[(s + 1) & 3][wave][0][lane] : &zrow[0][lane];
             const int64_t site = sxy + plane_sites * s;
+            if constexpr (VALS == 3) {
+                // this step's record into the wave's LDS slot (the previous
+                // step's reads of the slot come first: LDS executes a wave's
+                // accesses in order, the fences only stop the compiler)
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                recs[wave][lane] = cur.hv;
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            }
 #pragma unroll
             for (int o = 0; o < 4; ++o) {
                 const int64_t row = 4 * site + o;
@@ -420,7 +446,14 @@ lattice_kernel(const T* __restrict__ val, const T* __restrict__ V, T* __restrict
                 v[11] = zup[o * kE];
                 v[12] = zup[(o ^ 2) * kE];
                 T A = T(0), B = T(0);
-                if constexpr (VEC_VALS) {
+                if constexpr (VALS == 3) {
+#pragma unroll
+                    for (int j = 0; j < kWidth; ++j) {
+                        const typename SiteRec<T>::V e = recs[wave][kWidth * o + j];
+                        A = fma(SiteRec<T>::re(e), v[j], A);
+                        B = fma(SiteRec<T>::im(e), v[j], B);
+                    }
+                } else if constexpr (VEC_VALS) {
 #pragma unroll
                     for (int j = 0; j < kWidth; ++j) {
                         A = fma(SiteRec<T>::re(cur.hv, kWidth * o + j), v[j], A);
@@ -538,16 +571,21 @@ hipError_t launch_ts(int variant, const LatticeArgs& a, hipStream_t s) {
         a.L[0], a.L[1], a.L[2], a.periodic[0], a.periodic[1], a.periodic[2], ntx, ntiles, a.order, \
         a.R / kR, npc)
 // tuning `prefetch`: 2 (default) the site's matrix record a step ahead in
-// registers (VALS 1), 1 scalar loads after an L2 warm-up (VALS 2), 0 plain
+// registers (VALS 1 in complex128; VALS 3 in complex64, where the
+// v_readlane hand-over and its wait states made the sweep VALU-bound, and
+// the record's 8-byte entries leave room for the LDS reads: 0.57 -> 0.73 of
+// peak on 128 x 128 x 64; in complex128 the 16-byte entries read from LDS
+// spill registers), 1 scalar loads after an L2 warm-up (VALS 2), 0 plain
 // scalar loads.  Blocks wider than 32 columns always take the record path.
+    constexpr int REC = sizeof(T) == 4 ? 3 : 1;
 #define KPM_LAUNCH_V(VAR)                          \
     if (a.R > kR) {                                \
-        KPM_LAUNCH(VAR, 1, 0);                     \
+        KPM_LAUNCH(VAR, REC, 0);                   \
     } else if (npc > 1) {                          \
-        KPM_LAUNCH_S(VAR, 1, 1, true);             \
+        KPM_LAUNCH_S(VAR, REC, 1, true);           \
     } else {                                       \
         switch (a.prefetch) {                      \
-        case 2: KPM_LAUNCH(VAR, 1, 1); break;      \
+        case 2: KPM_LAUNCH(VAR, REC, 1); break;    \
         case 1: KPM_LAUNCH(VAR, 2, 1); break;      \
         default: KPM_LAUNCH(VAR, 0, 1); break;     \
         }                                          \
