@@ -291,18 +291,21 @@ bool pencil_order(const SweepArgs& a, TileGeom& tg) {
 // result of the staged-gather sweep; only how many neighbours come from the
 // ring depends on it.
 
-// Tile side: the ring of four tile planes must fit in LDS beside the
+// Tile side: the ring of three tile planes must fit in LDS beside the
 // matrix staging.
 template <typename T, int R>
 constexpr int win_side() {
     return R * 2 * static_cast<int>(sizeof(T)) <= 512 ? 4 : 2;
 }
 
-template <typename T, int R, int WAVES_ = 16, int RING_ = 3>
+// One workgroup of 16 waves per CU (its LDS): measured against 8 waves with
+// a ring of four planes (one barrier per plane) and 12 waves, 16 hide the
+// latency of a pass best.
+template <typename T, int R>
 struct Win {
     using S = Shape<T, R>;
-    static constexpr int kWaves = WAVES_;
-    static constexpr int kRing = RING_;                          // tile planes in the ring
+    static constexpr int kWaves = 16;
+    static constexpr int kRing = 3;                              // tile planes in the ring
     static constexpr int kThreads = 64 * kWaves;
     static constexpr unsigned kCB = 2 * sizeof(T);
     static constexpr unsigned kRB = R * kCB;                   // bytes per block row
@@ -311,8 +314,7 @@ struct Win {
     static constexpr unsigned kPlaneBytes = kTileRows * kRB;
     static constexpr int kLoadsP = (kPlaneBytes / 16 + kThreads - 1) / kThreads;   // 16-byte loads per thread
     static constexpr unsigned kRingBytes = kRing * kPlaneBytes;   // then one zero row
-    // passes a wave takes in a tile plane; two staging slots per wave
-    static constexpr int kMaxP = (kTileRows / S::RPW + kWaves - 1) / kWaves;
+    // two staging slots per wave (the pass being computed, the next one)
     static constexpr int kStageBytes = kWaves * 2 * S::kStageWords * 4;
     static constexpr int kLds = static_cast<int>(kRingBytes + kRB) + kStageBytes;
     static constexpr bool ok = S::RPW <= 4 && S::kAhead && kLds <= batch::kLdsMax &&
@@ -350,7 +352,6 @@ window_sweep_kernel(const T* __restrict__ val, const int32_t* __restrict__ col, 
     constexpr unsigned kOut = 0xFFFFFFF0u;   // offset past every buffer: loads read 0, stores are dropped
     constexpr uint32_t NR = C::kRing;
     __shared__ __attribute__((aligned(16))) char ring[C::kRingBytes + RB];
-    constexpr int kMaxP = C::kMaxP;
     __shared__ __attribute__((aligned(16))) int stage[WAVES][2][S::kStageWords];
 
     const int tid = threadIdx.x;
@@ -561,7 +562,7 @@ window_sweep_kernel(const T* __restrict__ val, const int32_t* __restrict__ col, 
                 ln = nln;
                 o = no;
             }
-            if constexpr (NR == 3) __syncthreads();   // plane z - 1's slot is free
+            __syncthreads();   // plane z - 1's slot is free
             if (pre) pstore(z + 2, nx);
             __syncthreads();
         }

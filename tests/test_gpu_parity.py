@@ -302,14 +302,14 @@ def test_quantum_dot_slab_matches_oracle(lattice):
     assert np.abs(mu - ref).max() <= TOL_C128
 
 
-@pytest.mark.parametrize("pz", [1, 0])
-def test_lattice_pencils_split_in_z_match_oracle(pz):
+@pytest.mark.parametrize("pz,dtype", [(1, "c128"), (0, "c128"), (1, "c64")])
+def test_lattice_pencils_split_in_z_match_oracle(pz, dtype):
     # 17 x 16 = 272 pencils of 9 planes on 256 workgroups: the launch cuts
     # every pencil into two z-pieces (planes 0-3 and 4-8), each with its own
-    # prologue; periodic and open z
+    # prologue; periodic and open z; complex64 (entries through LDS)
     K = kpm()
     L, per, M, R = (68, 64, 9), (1, 1, pz), 16, 32
-    say("split pencils, pz", pz)
+    say("split pencils, pz", pz, dtype)
     pot = inputs.potential(L, 1.0, 6)
     Ho = O.ti_hamiltonian(L, pot, periodic=per)
     a, b = O.scaling(*O.gershgorin(Ho))
@@ -317,22 +317,23 @@ def test_lattice_pencils_split_in_z_match_oracle(pz):
     ref = O.kpm_moments(Ho, a, b, v0, M)
     try:
         K.set_sweep_tuning(lattice=2, wg_per_cu=1)
-        H = K.build_hamiltonian(L, pot, periodic=per)
+        H = K.build_hamiltonian(L, pot, periodic=per, dtype=dtype)
         plan = K.sweep_plan(H, R)
         H.close()
         say("split pencils plan", plan)
         assert plan["kernel"] == "lattice_kernel"
         if plan["grid"] < 272:        # 272 pencils on fewer workgroups: the split applies
             assert plan["pieces"] == 2, plan
-        mu, _ = gpu_moments(L, pot, v0, M, periodic=per)
+        mu, _ = gpu_moments(L, pot, v0, M, periodic=per, dtype=dtype)
         # the same sweep without the split (prefetch 1 never splits pencils)
         K.set_sweep_tuning(lattice=2, wg_per_cu=1, prefetch=1)
-        whole, _ = gpu_moments(L, pot, v0, M, periodic=per)
+        whole, _ = gpu_moments(L, pot, v0, M, periodic=per, dtype=dtype)
     finally:
         K.reset_sweep_tuning()
-    # both GPU runs reduce in tree order: they agree to rounding
+    # both GPU runs form every row's products alike and reduce in tree order:
+    # they agree to rounding
     assert np.abs(mu - whole).max() <= 1e-13
-    assert np.abs(mu - ref).max() <= TOL_C128
+    assert np.abs(mu - ref).max() <= (TOL_C128 if dtype == "c128" else TOL_C64)
 
 
 @pytest.mark.parametrize("L", [(5, 4, 4), (4, 9, 3), (1, 1, 7)])
