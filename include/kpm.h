@@ -353,7 +353,8 @@ kpm_status kpm_moment_features(const double* mu, int32_t n_inst, int32_t R, int3
  *                (each is decoded once, when the matrix rows of a pass are
  *                staged), so any matrix over the lattice's rows gives the
  *                staged-gather result (on 64^3 at R = 32: 426 us per sweep
- *                against 580 us).  The
+ *                against 573 us; its matrix and W streams ignore `stream`
+ *                and go through L2 with the default policy).  The
  *                staged-gather sweep (one lane per 16 bytes of a block row,
  *                matrix rows copied into LDS a pass ahead) uses only
  *                wg_per_cu and xcd_ways of the fields above, and needs the
