@@ -550,6 +550,34 @@ def test_full_size_benchmark_workload():
 
 
 @pytest.mark.slow
+@pytest.mark.parametrize("gather", [3, 4])
+def test_full_size_workload_index_reading_sweeps(gather):
+    # the benchmark workload (64^3, R = 32, M = 2000) through the index-reading
+    # sweeps instead of the lattice sweep: the window sweep (gather 3: its full
+    # die mapping, one 4 x 4 pencil per workgroup) and the plain staged gather
+    # (gather 4), every one of the 64,000 moments against the oracle's
+    K = kpm()
+    ref, rec = golden_moments("ti64_r32_m2000_c128")
+    L, R, M = (64, 64, 64), 32, 2000
+    say("full size, index-reading sweep", gather)
+    pot = inputs.potential(L, rec["gamma"], rec["pot_seed"])
+    H = K.build_hamiltonian(L, pot)
+    V0 = torch.from_numpy(inputs.phase_block(H.N, R, rec["phase_seed"])).cuda()
+    try:
+        K.set_sweep_tuning(lattice=0, gather=gather)
+        plan = K.sweep_plan(H, R)
+        say("plan", plan)
+        assert plan["kernel"] == ("window_sweep_kernel" if gather == 3 else "gather_sweep_kernel")
+        mu = K.moments(H, V0, M).cpu().numpy()
+    finally:
+        K.reset_sweep_tuning()
+        H.close()
+    err = np.abs(mu - ref)
+    say(f"max |dmu| = {err.max():.3e}")
+    assert err.max() <= TOL_C128
+
+
+@pytest.mark.slow
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 def test_precision_workload_prefix_against_oracle(dtype):
     # 128 x 128 x 64 lattice, gamma = 2, R = 32, start block from the device generator
