@@ -127,13 +127,26 @@ def cpu_baseline(L, gamma, R, dtype, target_s=15.0):
 
 
 def cpu_oracle_subsets(target_s=8.0):
-    """The oracle on bounded subsets of the other workloads, extrapolated linearly (stated per entry):
-    the 128 x 128 x 64 precision lattice (complex128, per sweep), the batched family (R = 8, M = 512,
-    per instance) and the learned family's truth runs (R = 16, M = 2048, per instance)."""
+    """The oracle on the small configuration in full (8^3, R = 1, M = 128) and on bounded subsets of the
+    other workloads, extrapolated linearly (stated per entry): the 128 x 128 x 64 precision lattice
+    (complex128, per sweep), the batched family (R = 8, M = 512, per instance) and the learned family's
+    truth runs (R = 16, M = 4096, per instance)."""
     import numpy as np
     import oracle as O
     from paper_1410_5242_amd import inputs, learned
     out = {"threads": O.lib_threads()}
+    L1, M1 = (8, 8, 8), 128
+    t0 = time.perf_counter()
+    H1 = O.ti_hamiltonian(L1, inputs.potential(L1, 1.0, 0))
+    a1, b1 = O.scaling(*O.gershgorin(H1))
+    v1 = inputs.phase_block(H1.n, 1, 0)
+    build1 = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    O.kpm_moments(H1, a1, b1, v1, M1)
+    run1 = time.perf_counter() - t0
+    out["small_8x8x8_r1_m128"] = {"sample": "the full run", "seconds": round(run1, 4), "build_s": round(build1, 3),
+                                  "GBps": round(sweep_bytes(H1.n, 13 * H1.n, 1, 16) * (M1 // 2) / run1 / 1e9, 2)}
+    del H1, v1
     L, R = (128, 128, 64), 32
     pot = inputs.potential(L, 2.0, 0)
     t0 = time.perf_counter()

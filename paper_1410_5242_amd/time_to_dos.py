@@ -23,6 +23,10 @@ on every instance:
 Every variant reports its mean L1 error and the fraction of instances whose
 own error exceeds eps (the KPM variants meet eps on the mean, not on every
 instance, and so does the learned one by its calibration).
+
+The whole time-vs-L1 curve over the candidate M is reported too: the
+batched solver on every instance, plain complex128 timed on a stated subset
+(scaled to all instances), and the network without fallback as one point.
 """
 from __future__ import annotations
 
@@ -138,6 +142,48 @@ def run(n_inst: int = 1000, eps_list=LN.EPS_TARGETS, seed: int = LN.TEST_SEED + 
         out["targets"][str(eps)] = res
         log(f"[time-to-dos] eps {eps}: M={M} " + " ".join(
             f"{k}={v['seconds']}s/L1 {v['mean_l1']}" for k, v in res.items() if isinstance(v, dict) and "seconds" in v))
+    # the time-vs-L1 curve over the candidate M: the batched solver on every instance, plain
+    # complex128 on the first n_curve instances (its time scaled by n_inst / n_curve), and the
+    # network without fallback (batched M = 128 run plus inference, every instance)
+    n_curve = min(100, n_inst)
+    curve = []
+    mu = None
+    for M in LN.M_CHOICES:
+        K.moments_batched(H64[:8], V64[:8], M)
+        _sync()
+        t0 = time.perf_counter()
+        mu_b = K.moments_batched(H64, V64, M, check=False)
+        q_b = K.dos_batched(mu_b, a, b, E, masses=True)
+        host = q_b.cpu()
+        dt_b = time.perf_counter() - t0
+        mu = torch.empty((R, M), dtype=torch.float64, device="cuda")
+        K.moments(H128[0], V128[0], M, mu=mu)
+        _sync()
+        t0 = time.perf_counter()
+        for i in range(n_curve):
+            K.moments(H128[i], V128[i], M, mu=mu, check=False)
+            K.dos(mu, LN.A_FAMILY, LN.B_FAMILY, E, rho=rho[i])
+        host = rho[:n_curve].cpu()
+        dt_p = time.perf_counter() - t0
+        del host
+        curve.append({"M": M, "kpm_c128_mean_l1": round(float(err_M[M].mean()), 5),
+                      "batched_c64": {"seconds": round(dt_b, 3), "mean_l1": round(float(LN.l1(q_b, p).mean()), 5)},
+                      "plain_c128": {"seconds": round(dt_p * n_inst / n_curve, 3),
+                                     "timed_instances": n_curve}})
+    mu_s = torch.empty((n_inst, R, LN.N_MOM), dtype=torch.float64, device="cuda")
+    K.moments_batched(H64, V64, LN.N_MOM, mu=mu_s, check=False)
+    _sync()
+    t0 = time.perf_counter()
+    K.moments_batched(H64, V64, LN.N_MOM, mu=mu_s, check=False)
+    q, _ = LN.predict(net, LN.features(mu_s, fam))
+    host = q.cpu()
+    dt_l = time.perf_counter() - t0
+    out["curve"] = {"points": curve,
+                    "learned_no_fallback": {"M": LN.N_MOM, "seconds": round(dt_l, 3),
+                                            "mean_l1": round(float(LN.l1(q.double(), p).mean()), 5)},
+                    "note": f"plain complex128 timed on the first {n_curve} of {n_inst} instances, scaled"}
+    log(f"[time-to-dos] curve: " + " ".join(f"M={c['M']}:L1 {c['kpm_c128_mean_l1']} batched {c['batched_c64']['seconds']}s "
+                                             f"plain {c['plain_c128']['seconds']}s" for c in curve))
     K.reset_batch_tuning()
     for H in H128 + H64:
         H.close()
