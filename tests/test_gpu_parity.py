@@ -728,6 +728,30 @@ def test_window_sweep_writes_the_staged_gather_result(R, dtype, order):
     assert (e3 - e4).abs().max().item() <= 1e-13 * max(1.0, e4.abs().max().item())
 
 
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_window_sweep_several_items_per_workgroup(dtype):
+    # 90 x 94 x 6 (open z): 23 x 24 = 552 tiles, some cut by the lattice edge, more
+    # work items than the workgroups of one per CU, so a workgroup walks several
+    # tiles one after the other (a fresh ring prologue each)
+    K = kpm()
+    L, per, M, R = (90, 94, 6), (1, 1, 0), 12, 32
+    say("window sweep, several items per workgroup", dtype)
+    pot, Ho, a, b = oracle_problem(L, 1.0, 29, periodic=per)
+    v0 = inputs.phase_block(Ho.n, R, 30)
+    ref = O.kpm_moments(Ho, a, b, v0, M)
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    try:
+        K.set_sweep_tuning(lattice=0, gather=3)
+        H = K.build_hamiltonian(L, pot, periodic=per, dtype=dtype)
+        plan = K.sweep_plan(H, R)
+        H.close()
+        assert plan["kernel"] == "window_sweep_kernel" and plan["grid"] < 23 * 24, (plan, cus)
+        mu, _ = gpu_moments(L, pot, v0, M, dtype=dtype, periodic=per)
+    finally:
+        K.reset_sweep_tuning()
+    assert np.abs(mu - ref).max() <= (TOL_C128 if dtype == "c128" else TOL_C64)
+
+
 @pytest.mark.parametrize("R", [16, 32, 64])
 def test_window_sweep_single_sweep_variants(R):
     # FULL, NODOT, PLAIN of the window sweep against H X from the oracle's dense matrix
