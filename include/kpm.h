@@ -111,6 +111,63 @@ kpm_status kpm_export_csr(const kpm_hamiltonian* H, int64_t* rowptr, int32_t* co
 /* Release H and its workspaces (synchronises the device).  NULL is a no-op. */
 void kpm_destroy_hamiltonian(kpm_hamiltonian* H);
 
+/* A general sparse Hermitian matrix in host CRS, for kpm_import_csr. */
+typedef struct {
+    int64_t N;               /* rows = columns, >= 1 */
+    const int64_t* rowptr;   /* host [N+1]: rowptr[0] = 0, non-decreasing; row i is entries
+                                rowptr[i] .. rowptr[i+1]-1 */
+    const int32_t* col;      /* host [nnz], 0 <= col < N, any order (repeated columns add up) */
+    const double* val;       /* host [2*nnz] (re, im) */
+    int32_t dtype;           /* kpm_dtype of the stored values and of the vector blocks */
+    int32_t sell_C;          /* chunk height C: 1, 2, 4, 8, 16, 32 or 64; 0 = 8 */
+    int32_t sell_sigma;      /* sorting window sigma in rows: 1 (no sorting) or a multiple of C
+                                (>= N sorts globally); 0 = 128 C */
+    double margin;           /* as in kpm_lattice_desc */
+    int32_t fixed_scale;
+    double a, b;
+} kpm_csr_desc;
+
+/* Layout of a CRS sparsity pattern in SELL-C-sigma (the unified storage
+ * format the paper builds on, section "Related Work"; C = 1 without sorting
+ * is CRS, the format of section "Testbed and Implementation").  Rows are
+ * sorted by decreasing length (stable) inside consecutive windows of sigma
+ * rows; sorted position p holds row perm[p] and lies in chunk p / C of
+ * nchunks = ceil(N / C); chunk c is stored column-major, width[c] (its
+ * longest row) entries deep, from entry start[c] (start[nchunks] = stored
+ * entries, padding included), so entry j of position p sits at
+ * start[p / C] + j*C + p mod C.  Host only (no device, no stream).
+ * perm [N], width [nchunks], start [nchunks+1]: host, any may be NULL.
+ * Errors: KPM_EINVAL (N < 1, a NULL rowptr, a decreasing rowptr or one not
+ * starting at 0, C not a power of two in 1..64, sigma neither 1 nor a
+ * multiple of C), KPM_ENOMEM (more than 2^31 - 1 rows). */
+kpm_status kpm_sell_layout(int64_t N, const int64_t* rowptr, int32_t C, int32_t sigma, int32_t* perm,
+                           int32_t* width, int64_t* start);
+
+/* H from a general sparse Hermitian matrix in host CRS, stored on the
+ * device in SELL-C-sigma (layout of kpm_sell_layout; padding entries hold
+ * value 0 and column N), with the Gershgorin scaling of kpm_build_hamiltonian
+ * computed on the device from the stored values (section "Problem
+ * Description").  The vector blocks keep the matrix's own row order: the
+ * sorting only reorders the work of a sweep.  kpm_aug_spmmv, kpm_moments,
+ * kpm_moments_naive and kpm_lanczos_bounds accept the result; the lattice
+ * entry points (kpm_moments_batched) do not.  H must be Hermitian for the
+ * moments to mean anything; the library does not check it (kpm_moments
+ * with check reports KPM_ESPECTRUM when moments leave [-mu_0, mu_0]).
+ * Synchronises `stream`.  Errors: KPM_EINVAL (a NULL desc, out, col or val
+ * with nnz > 0, a bad layout argument, a column out of range, a
+ * non-finite value, margin < 1, a zero-width Gershgorin interval),
+ * KPM_ENOMEM (stored values reaching 4 GiB: the sweep addresses them with
+ * 32-bit offsets), KPM_EDEVICE.  *out is NULL on error.  The sweeps over
+ * this storage take blocks of up to 4 GiB as well: kpm_aug_spmmv and
+ * kpm_moments return KPM_ENOTSUP for an [N+1][R] block that reaches it. */
+kpm_status kpm_import_csr(const kpm_csr_desc* desc, void* stream, kpm_hamiltonian** out);
+
+/* SELL-C-sigma parameters of H: C and sigma (0 and 0 for a lattice H built
+ * by kpm_build_hamiltonian), chunks, stored entries (padding included) and
+ * the imported nonzero count.  Any output may be NULL.  Errors: KPM_EINVAL. */
+kpm_status kpm_sell_info(const kpm_hamiltonian* H, int32_t* C, int32_t* sigma, int64_t* nchunks,
+                         int64_t* stored, int64_t* nnz);
+
 /* One augmented sweep (Alg. "kpm_improved_blocked", the fused body):
  *   W <- alpha * H V + beta * V + gamma * W            (variant FULL / NODOT)
  *   eta[0][r] = <V_r|V_r>,  eta[1][r] = <W_r|V_r>     (FULL only, new W)
@@ -410,7 +467,7 @@ kpm_status kpm_get_sweep_tuning(kpm_sweep_tuning* tuning);
 /* Which sweep kernel kpm_moments / kpm_aug_spmmv launch for H at block
  * width R under the current tuning: *kernel = 0 scalar-operand gather
  * sweep, 1 cache-blocked lattice sweep, 2 staged-gather sweep, 3 its
- * LDS-window variant.
+ * LDS-window variant, 4 the SELL-C-sigma sweep (H from kpm_import_csr).
  * Errors: KPM_EINVAL. */
 kpm_status kpm_sweep_kernel(const kpm_hamiltonian* H, int32_t R, int32_t* kernel);
 

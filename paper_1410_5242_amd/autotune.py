@@ -12,7 +12,10 @@ time is their launch shape and the block width itself:
 * the batched persistent solver (``kpm_set_batch_tuning``): workgroup size,
   workgroups per CU, dynamic or static instance mapping;
 * the block width R for a given number of random vectors S (S/R passes of
-  kpm_moments at width R; the matrix is read once per pass and sweep).
+  kpm_moments at width R; the matrix is read once per pass and sweep);
+* for a general matrix handed over as CRS (``kpm_import_csr``), its
+  SELL-C-sigma layout: the chunk height C and the sorting window sigma,
+  which trade padding against how the entries of a pass are laid out.
 
 Candidates are timed on the caller's problem with HIP events around the
 library calls; every candidate produces the same moments up to the order of
@@ -55,6 +58,24 @@ def batch_key(dtype: int, R: int, n_inst: int, total_rows: int) -> str:
 
 def width_key(dtype: int, S: int, N: int) -> str:
     return f"width:{DTYPE_NAMES[dtype]}:S{S}:N{size_bucket(N)}"
+
+
+def sell_key(dtype: int, R: int, N: int, nnz: int) -> str:
+    return f"sell:{DTYPE_NAMES[dtype]}:R{R}:N{size_bucket(N)}:nnz{size_bucket(nnz)}"
+
+
+def sell_candidates() -> list[dict]:
+    """SELL-C-sigma layouts to time: the library default first, then chunk heights from CRS
+    (C = 1) to one chunk per wave of single-row passes (C = 64), unsorted and sorted."""
+    out = [{"C": 8, "sigma": 1024}]
+    for C in (1, 2, 4, 8, 16, 32, 64):
+        for sigma in (1, 32 * C, 1024 * C):
+            if sigma == 1 and C > 1 and C != 32:
+                continue
+            c = {"C": C, "sigma": sigma}
+            if c not in out:
+                out.append(c)
+    return out
 
 
 def sweep_candidates(R: int, lattice_ok: bool) -> list[dict]:
@@ -306,6 +327,51 @@ def tune_block_width(H, S: int, cache: TuningCache | None = None, sweeps: int = 
         del V, W
     best = pick_best(trials)
     res = TuneResult(width_key(H.dtype, S, H.N), best.params, best.seconds, trials)
+    if cache is not None:
+        cache.put(res)
+    return res
+
+
+def tune_sell_layout(rowptr, col, val, R: int, dtype: str = "c128", cache: TuningCache | None = None,
+                     sweeps: int = 8, candidates=None, repeats: int = 3, margin: float = 0.02) -> TuneResult:
+    """Import the CRS matrix under each candidate SELL-C-sigma layout and time its fused sweep at
+    block width R (the library's HIP events around every sweep).  The first candidate is the
+    library default, kept unless another layout is faster by more than `margin`.  Returns the
+    best {"C", "sigma"} (pass them to kpm.import_csr)."""
+    import numpy as np
+    import torch
+    from . import kpm as K
+
+    N = len(rowptr) - 1
+    trials = []
+    for c in candidates or sell_candidates():
+        H = K.import_csr(rowptr, col, val, dtype=dtype, C=c["C"], sigma=c["sigma"])
+        try:
+            V = torch.full((N, R), 1.0 / math.sqrt(N), dtype=H.torch_dtype, device="cuda")
+            W = torch.zeros_like(V)
+            eta = torch.zeros((2, R, 2), dtype=torch.float64, device="cuda")
+            K.aug_spmmv(H, V, W, 2.0 / H.a, -2.0 * H.b / H.a, -1.0, "full", eta)   # warm-up
+            torch.cuda.synchronize()
+            best = math.inf
+            for _ in range(repeats):
+                K.sweep_profile_read()
+                K.sweep_profile_enable(True)
+                for _ in range(sweeps):
+                    K.aug_spmmv(H, V, W, 2.0 / H.a, -2.0 * H.b / H.a, -1.0, "full", eta)
+                torch.cuda.synchronize()
+                K.sweep_profile_enable(False)
+                n, tot_ms, _, _ = K.sweep_profile_read()
+                best = min(best, tot_ms * 1e-3 / max(n, 1))
+            info = K.sell_info(H)
+            trials.append(Trial({"C": c["C"], "sigma": c["sigma"], "stored": info["stored"]}, best))
+            del V, W
+        finally:
+            K.sweep_profile_enable(False)
+            H.close()
+    best = pick_best(trials, margin)
+    res = TuneResult(sell_key(K._DTYPES[dtype] if isinstance(dtype, str) else int(dtype), R, N,
+                              int(np.asarray(rowptr)[-1])),
+                     {"C": best.params["C"], "sigma": best.params["sigma"]}, best.seconds, trials)
     if cache is not None:
         cache.put(res)
     return res

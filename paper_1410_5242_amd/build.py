@@ -19,7 +19,7 @@ SOURCES = ["kpm_runtime.cpp", "kpm_build.hip", "kpm_spmmv.hip", "kpm_dos.hip",
            "kpm_sweep_c128_large.hip", "kpm_sweep_c128_small.hip",
            "kpm_sweep_c64_large.hip", "kpm_sweep_c64_small.hip", "kpm_lattice.hip",
            "kpm_batched_c64.hip", "kpm_batched_c128.hip", "kpm_mlp.hip", "kpm_start.hip", "kpm_gather_c64.hip", "kpm_gather_c128.hip",
-           "kpm_naive.hip", "kpm_lanczos.hip", "kpm_stream.hip"]
+           "kpm_naive.hip", "kpm_lanczos.hip", "kpm_stream.hip", "kpm_sell.hip"]
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

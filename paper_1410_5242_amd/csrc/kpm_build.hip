@@ -136,7 +136,67 @@ bounds_reduce_kernel(const double* __restrict__ block_bounds, int nblocks, doubl
     }
 }
 
+// Gershgorin discs of SELL-C-sigma storage, one sorted position per
+// thread: centre Re h_ii (every entry in the row's own column), radius the
+// sum of |h_ij| over the other columns (padding, column N, is skipped).
+// Values are read in the storage precision and summed in FP64.
+template <typename T>
+__global__ void __launch_bounds__(kBuildThreads)
+sell_bounds_kernel(const T* __restrict__ val, const int32_t* __restrict__ col, const int64_t* __restrict__ start,
+                   const int32_t* __restrict__ width, const int32_t* __restrict__ perm, int64_t nrows, int clog,
+                   double* __restrict__ block_bounds) {
+    __shared__ double s_lo[kBuildThreads];
+    __shared__ double s_hi[kBuildThreads];
+    const int64_t p = static_cast<int64_t>(blockIdx.x) * kBuildThreads + threadIdx.x;
+    double lo = DBL_MAX, hi = -DBL_MAX;
+    if (p < nrows) {
+        const int64_t ch = p >> clog;
+        const int64_t C = int64_t{1} << clog;
+        const int64_t row = perm ? perm[p] : p;
+        const int w = width[ch];
+        int64_t e = start[ch] + (p & (C - 1));
+        double centre = 0.0, radius = 0.0;
+        for (int j = 0; j < w; ++j, e += C) {
+            const int64_t c = col[e];
+            if (c == row) centre += static_cast<double>(val[2 * e]);
+            else if (c < nrows) radius += hypot(static_cast<double>(val[2 * e]), static_cast<double>(val[2 * e + 1]));
+        }
+        lo = centre - radius;
+        hi = centre + radius;
+    }
+    s_lo[threadIdx.x] = lo;
+    s_hi[threadIdx.x] = hi;
+    __syncthreads();
+    for (int w = kBuildThreads / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            s_lo[threadIdx.x] = fmin(s_lo[threadIdx.x], s_lo[threadIdx.x + w]);
+            s_hi[threadIdx.x] = fmax(s_hi[threadIdx.x], s_hi[threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        block_bounds[2 * blockIdx.x] = s_lo[0];
+        block_bounds[2 * blockIdx.x + 1] = s_hi[0];
+    }
+}
+
 }  // namespace
+
+hipError_t launch_sell_bounds(int dtype, const void* val, const int32_t* col, const int64_t* start,
+                              const int32_t* width, const int32_t* perm, int64_t nrows, int clog,
+                              double* block_bounds, double* bounds_out, hipStream_t s) {
+    const int nblocks = build_blocks(nrows);
+    if (dtype == KPM_C128)
+        sell_bounds_kernel<double><<<nblocks, kBuildThreads, 0, s>>>(static_cast<const double*>(val), col, start,
+                                                                     width, perm, nrows, clog, block_bounds);
+    else
+        sell_bounds_kernel<float><<<nblocks, kBuildThreads, 0, s>>>(static_cast<const float*>(val), col, start,
+                                                                    width, perm, nrows, clog, block_bounds);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    bounds_reduce_kernel<<<1, kBuildThreads, 0, s>>>(block_bounds, nblocks, bounds_out);
+    return hipGetLastError();
+}
 
 int build_blocks(int64_t nrows) {
     return static_cast<int>((nrows + kBuildThreads - 1) / kBuildThreads);

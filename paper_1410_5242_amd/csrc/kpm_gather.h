@@ -399,7 +399,6 @@ window_sweep_kernel(const T* __restrict__ val, const int32_t* __restrict__ col, 
         uint32_t x0, y0, ex, ey, z0, z1;
         batch::tile_item(tg, k, k_lo, die, x0, y0, ex, ey, z0, z1);
         const uint32_t ppl = 4 * ex / RPW;                 // passes per line of the tile
-        const uint32_t ppp = ey * ppl;                     // passes per tile plane
         const uint32_t base = y0 * line_rows + 4 * x0;     // first row of the tile in a plane
         // column -> ring row (flag bit 31) for a pass in plane zp, whose plane
         // zp - 1 sits in ring slot sm, or the column itself

@@ -51,14 +51,33 @@ struct Workspace {
     std::vector<unsigned char> graph_key;
 };
 
+
+// SELL-C-sigma storage of an imported matrix (kpm_import_csr): sorted
+// position p holds row perm[p] (no perm: p itself) and lies in chunk p / C,
+// stored column-major from entry start[p / C], width[p / C] entries deep.
+struct SellStore {
+    int C = 0;                      // chunk height (a power of two, 1..64); 0: not SELL storage
+    int clog = 0;                   // log2 C
+    int sigma = 1;                  // sorting window in rows (1: unsorted)
+    int64_t nchunks = 0;
+    int64_t stored = 0;             // stored entries, padding included
+    int64_t nnz = 0;                // entries of the imported matrix
+    int64_t* start = nullptr;       // device [nchunks + 1]
+    int32_t* width = nullptr;       // device [nchunks]
+    int32_t* perm = nullptr;        // device [N], or nullptr when sigma == 1
+    std::vector<int32_t> len;       // host row lengths by sorted position (for export)
+    std::vector<int32_t> perm_host; // host copy of perm (empty when sigma == 1)
+    std::vector<int64_t> start_host;
+};
 }  // namespace kpm
 
 struct kpm_hamiltonian {
     int dtype = KPM_C128;           // storage precision of val and of vector blocks
     int64_t nrows = 0;              // N
-    int width = kpm::kWidth;        // slots per row (row-major, diagonal first)
-    void* val = nullptr;            // [N][width] complex (re, im) in dtype
-    int32_t* col = nullptr;         // [N][width]
+    int width = kpm::kWidth;        // slots per row (row-major, diagonal first); SELL: longest row
+    void* val = nullptr;            // [N][width] complex (re, im) in dtype; SELL: [stored]
+    int32_t* col = nullptr;         // [N][width]; SELL: [stored]
+    kpm::SellStore sell;            // SELL-C-sigma storage (sell.C > 0) instead of the lattice layout
     int L[3] = {0, 0, 0};           // lattice sides
     int periodic[3] = {0, 0, 0};
     double a = 1.0, b = 0.0;        // Htilde = (H - b)/a
@@ -106,6 +125,31 @@ struct SweepArgs {
     int window = 0;         // staged-gather sweep: run its LDS-window variant (on a lattice)
     int order = 0;          // window sweep: 2 = no die mapping of its tiles (tuning tile_order)
 };
+
+// Fused sweep over SELL-C-sigma storage (kpm_sell.hip).
+struct SellArgs {
+    const void* val;
+    const int32_t* col;
+    const int64_t* start;
+    const int32_t* width;
+    const int32_t* perm;    // or nullptr (no sorting)
+    int64_t nrows;
+    int64_t stored;
+    int clog;
+    const void* V;
+    void* W;
+    double alpha, beta, gamma;
+    double* partials;       // this sweep's [grid][3][R] slot (FULL only)
+    int grid;
+};
+hipError_t launch_sell(int dtype, int R, int variant, const SellArgs& a, hipStream_t s);
+int sell_grid(int dtype, int R, int64_t nrows);
+int sell_rows_per_pass(int dtype, int R);
+// Per-block Gershgorin bounds of SELL storage, then their reduction into
+// bounds_out[2] (block_bounds holds build_blocks(nrows) pairs).
+hipError_t launch_sell_bounds(int dtype, const void* val, const int32_t* col, const int64_t* start,
+                              const int32_t* width, const int32_t* perm, int64_t nrows, int clog,
+                              double* block_bounds, double* bounds_out, hipStream_t s);
 
 // Cache-blocked sweep for the library's lattice Hamiltonians at R = 32 k.
 struct LatticeArgs {
@@ -313,7 +357,7 @@ hipError_t launch_reduce_partials(const double* partials, int nslots, int grid, 
                                   int sweep0, double* eta, hipStream_t s);
 hipError_t launch_eta_to_mu(const double* eta, int R, int M, double* mu, hipStream_t s);
 hipError_t launch_zero_ints(int* p, int n, hipStream_t s);
-// dst[0 .. bytes) = src[0 .. bytes) (16-byte aligned, bytes a multiple of 16):
+// dst[0 .. bytes) = src[0 .. bytes) (16-byte aligned, bytes a multiple of 8):
 // a kernel rather than a copy node, so that it can sit in a captured graph
 hipError_t launch_copy16(void* dst, const void* src, size_t bytes, hipStream_t s);
 hipError_t launch_check_moments(const double* mu, int R, int M, int* flag, hipStream_t s);

@@ -52,6 +52,15 @@ kpm_status check_device(const kpm_hamiltonian* H) {
     return KPM_OK;
 }
 
+// The SELL-C-sigma sweep addresses a block with 32-bit offsets, the padding
+// column N included.
+kpm_status check_sell_block(const kpm_hamiltonian* H, int R) {
+    if (H->sell.C == 0) return KPM_OK;
+    const uint64_t bytes = (static_cast<uint64_t>(H->nrows) + 1) * R * 2 * real_size(H->dtype);
+    if (bytes >= (1ull << 32) - 64) return fail(KPM_ENOTSUP, "an [N+1][R] block over SELL storage reaches 4 GiB");
+    return KPM_OK;
+}
+
 template <typename P>
 kpm_status grow(P** ptr, size_t* have, size_t need, const char* what) {
     if (*have >= need && *ptr) return KPM_OK;
@@ -100,7 +109,7 @@ bool use_lattice(const kpm_hamiltonian* H, int R) {
 // The per-die tile counters are read only by the scalar-operand sweep with
 // dynamic tile mapping; the other sweeps need no cleared queue.
 bool sweep_uses_queue(const kpm_hamiltonian* H, int R) {
-    return !use_lattice(H, R) && !use_gather(H->dtype, R, H->nrows) && get_tuning().dynamic != 0;
+    return H->sell.C == 0 && !use_lattice(H, R) && !use_gather(H->dtype, R, H->nrows) && get_tuning().dynamic != 0;
 }
 
 // The LDS-window variant of the staged-gather sweep (tuning gather 1:
@@ -121,12 +130,14 @@ bool use_window(const kpm_hamiltonian* H, int R) {
 }
 
 int launch_grid(const kpm_hamiltonian* H, int R) {
+    if (H->sell.C > 0) return sell_grid(H->dtype, R, H->nrows);
     return use_lattice(H, R) ? lattice_grid(H) : sweep_grid(H->dtype, R, H->nrows, use_window(H, R));
 }
 
 // Sweep kernel kind (kpm_sweep_kernel): 1 lattice, 3 window, 2 staged
-// gather, 0 scalar operand.
+// gather, 0 scalar operand, 4 SELL-C-sigma.
 int sweep_kind(const kpm_hamiltonian* H, int R) {
+    if (H->sell.C > 0) return 4;
     if (use_lattice(H, R)) return 1;
     if (!use_gather(H->dtype, R, H->nrows)) return 0;
     return use_window(H, R) ? 3 : 2;
@@ -158,7 +169,7 @@ std::vector<int32_t> pencil_schedule(const int L[3], int P) {
 kpm_status schedule_for(kpm_hamiltonian* H, const int32_t** out) {
     *out = nullptr;
     const int P = get_tuning().pencil;
-    if (P <= 0) return KPM_OK;
+    if (P <= 0 || H->sell.C > 0) return KPM_OK;
     std::lock_guard<std::mutex> g(H->lock);
     auto it = H->sched.find(P);
     if (it != H->sched.end()) {
@@ -258,6 +269,12 @@ int lattice_order(const kpm_hamiltonian* H, int grid) {
 // generic gather kernel otherwise.
 hipError_t launch_any_sweep(kpm_hamiltonian* H, int R, int variant, const SweepArgs& a, hipStream_t s,
                             bool capturing = false) {
+    if (H->sell.C > 0) {
+        const SellStore& c = H->sell;
+        SellArgs sa{H->val, H->col, c.start, c.width, c.perm, H->nrows, c.stored, c.clog,
+                    a.V, a.W, a.alpha, a.beta, a.gamma, a.partials, a.grid};
+        return profiled(s, capturing, [&] { return launch_sell(H->dtype, R, variant, sa, s); });
+    }
     if (use_lattice(H, R)) {
         const kpm_sweep_tuning t = get_tuning();
         LatticeArgs la{H->val, a.V, a.W, a.alpha, a.beta, a.gamma, a.partials,
@@ -339,6 +356,80 @@ void drop_moments_graph(Workspace& w) {
     w.graph = nullptr;
     w.graph_key.clear();
 }
+
+// SELL-C-sigma layout of a CRS pattern (kpm_sell_layout): validation, the
+// stable sort by decreasing row length inside windows of sigma rows, chunk
+// widths and starts.  len_sorted: row lengths by sorted position.
+kpm_status sell_layout(int64_t N, const int64_t* rowptr, int C, int sigma, std::vector<int32_t>& perm,
+                       std::vector<int32_t>& width, std::vector<int64_t>& start, std::vector<int32_t>& len_sorted) {
+    if (N < 1) return fail(KPM_EINVAL, "N must be >= 1");
+    if (N > INT32_MAX - 1) return fail(KPM_ENOMEM, "more than 2^31 - 2 rows");
+    if (!rowptr) return fail(KPM_EINVAL, "rowptr is NULL");
+    if (C < 1 || C > 64 || (C & (C - 1)) != 0) return fail(KPM_EINVAL, "C must be a power of two in 1..64");
+    if (sigma < 1 || (sigma != 1 && sigma % C != 0)) return fail(KPM_EINVAL, "sigma must be 1 or a multiple of C");
+    if (rowptr[0] != 0) return fail(KPM_EINVAL, "rowptr[0] must be 0");
+    std::vector<int32_t> len(static_cast<size_t>(N));
+    for (int64_t i = 0; i < N; ++i) {
+        const int64_t l = rowptr[i + 1] - rowptr[i];
+        if (l < 0) return fail(KPM_EINVAL, "rowptr decreases at row " + std::to_string(i));
+        if (l > INT32_MAX / 64) return fail(KPM_ENOMEM, "a row has too many entries");
+        len[i] = static_cast<int32_t>(l);
+    }
+    perm.resize(static_cast<size_t>(N));
+    std::iota(perm.begin(), perm.end(), 0);
+    if (sigma > 1) {
+        for (int64_t w0 = 0; w0 < N; w0 += sigma) {
+            const int64_t w1 = std::min<int64_t>(N, w0 + sigma);
+            std::stable_sort(perm.begin() + w0, perm.begin() + w1,
+                             [&](int32_t x, int32_t y) { return len[x] > len[y]; });
+        }
+    }
+    const int64_t nch = (N + C - 1) / C;
+    width.assign(static_cast<size_t>(nch), 0);
+    start.assign(static_cast<size_t>(nch) + 1, 0);
+    len_sorted.resize(static_cast<size_t>(N));
+    for (int64_t p = 0; p < N; ++p) {
+        len_sorted[p] = len[perm[p]];
+        width[p / C] = std::max(width[p / C], len_sorted[p]);
+    }
+    for (int64_t c = 0; c < nch; ++c) start[c + 1] = start[c] + static_cast<int64_t>(width[c]) * C;
+    return KPM_OK;
+}
+
+// kpm_export_csr of SELL storage: each row's entries in the order they were
+// imported (padding dropped, explicit zeros of the input kept).
+kpm_status export_sell(const kpm_hamiltonian* H, int64_t* rowptr, int32_t* col, double* val) {
+    const SellStore& c = H->sell;
+    const int64_t N = H->nrows;
+    std::vector<int64_t> pos(static_cast<size_t>(N));   // sorted position of each row
+    for (int64_t p = 0; p < N; ++p) pos[c.perm_host.empty() ? p : c.perm_host[p]] = p;
+    rowptr[0] = 0;
+    for (int64_t i = 0; i < N; ++i) rowptr[i + 1] = rowptr[i] + c.len[pos[i]];
+    if (!col) return KPM_OK;
+    const size_t n = static_cast<size_t>(c.stored);
+    std::vector<int32_t> cc(n);
+    std::vector<double> v(2 * n);
+    KPM_HIP(hipMemcpy(cc.data(), H->col, n * sizeof(int32_t), hipMemcpyDeviceToHost), "copy col");
+    if (H->dtype == KPM_C128) {
+        KPM_HIP(hipMemcpy(v.data(), H->val, 2 * n * sizeof(double), hipMemcpyDeviceToHost), "copy val");
+    } else {
+        std::vector<float> f(2 * n);
+        KPM_HIP(hipMemcpy(f.data(), H->val, 2 * n * sizeof(float), hipMemcpyDeviceToHost), "copy val");
+        for (size_t i = 0; i < 2 * n; ++i) v[i] = f[i];
+    }
+    for (int64_t i = 0; i < N; ++i) {
+        const int64_t p = pos[i];
+        const int64_t e0 = c.start_host[p >> c.clog] + (p & (c.C - 1));
+        for (int64_t j = 0, k = rowptr[i]; k < rowptr[i + 1]; ++j, ++k) {
+            const int64_t e = e0 + j * c.C;
+            col[k] = cc[e];
+            val[2 * k] = v[2 * e];
+            val[2 * k + 1] = v[2 * e + 1];
+        }
+    }
+    return KPM_OK;
+}
+
 }  // namespace
 
 void set_error(const std::string& msg) { g_error = msg; }
@@ -446,7 +537,7 @@ kpm_status kpm_hamiltonian_info(const kpm_hamiltonian* H, int64_t* N, int64_t* n
     g_error.clear();
     if (!H) return fail(KPM_EINVAL, "H is NULL");
     if (N) *N = H->nrows;
-    if (nnz) *nnz = H->nrows * H->width;
+    if (nnz) *nnz = H->sell.C > 0 ? H->sell.stored : H->nrows * H->width;
     if (width) *width = H->width;
     if (dtype) *dtype = H->dtype;
     if (a) *a = H->a;
@@ -462,6 +553,7 @@ kpm_status kpm_export_csr(const kpm_hamiltonian* H, int64_t* rowptr, int32_t* co
     if ((col == nullptr) != (val == nullptr)) return fail(KPM_EINVAL, "col and val must both be set or both NULL");
     kpm_status st = check_device(H);
     if (st != KPM_OK) return st;
+    if (H->sell.C > 0) return export_sell(H, rowptr, col, val);
     const size_t slots = static_cast<size_t>(H->nrows) * H->width;
     std::vector<int32_t> c(slots);
     std::vector<double> v(2 * slots);
@@ -496,9 +588,169 @@ void kpm_destroy_hamiltonian(kpm_hamiltonian* H) {
     (void)hipDeviceSynchronize();
     if (H->val) (void)hipFree(H->val);
     if (H->col) (void)hipFree(H->col);
+    if (H->sell.start) (void)hipFree(H->sell.start);
+    if (H->sell.width) (void)hipFree(H->sell.width);
+    if (H->sell.perm) (void)hipFree(H->sell.perm);
     for (auto& kv : H->ws) free_workspace(kv.second);
     for (auto& kv : H->sched) (void)hipFree(kv.second);
     delete H;
+}
+
+kpm_status kpm_sell_layout(int64_t N, const int64_t* rowptr, int32_t C, int32_t sigma, int32_t* perm,
+                           int32_t* width, int64_t* start) {
+    g_error.clear();
+    std::vector<int32_t> pm, wd, ln;
+    std::vector<int64_t> st;
+    const kpm_status e = sell_layout(N, rowptr, C, sigma, pm, wd, st, ln);
+    if (e != KPM_OK) return e;
+    if (perm) std::copy(pm.begin(), pm.end(), perm);
+    if (width) std::copy(wd.begin(), wd.end(), width);
+    if (start) std::copy(st.begin(), st.end(), start);
+    return KPM_OK;
+}
+
+kpm_status kpm_import_csr(const kpm_csr_desc* d, void* stream, kpm_hamiltonian** out) {
+    g_error.clear();
+    if (!out) return fail(KPM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!d) return fail(KPM_EINVAL, "desc is NULL");
+    if (d->dtype != KPM_C128 && d->dtype != KPM_C64) return fail(KPM_EINVAL, "unknown dtype");
+    if (d->fixed_scale) {
+        if (!(d->a > 0.0) || !std::isfinite(d->a) || !std::isfinite(d->b))
+            return fail(KPM_EINVAL, "fixed scale needs a finite a > 0 and a finite b");
+    } else if (!(d->margin >= 1.0) || !std::isfinite(d->margin)) {
+        return fail(KPM_EINVAL, "margin must be a finite number >= 1");
+    }
+    const int C = d->sell_C == 0 ? 8 : d->sell_C;
+    const int sigma = d->sell_sigma == 0 ? 128 * C : d->sell_sigma;
+    std::vector<int32_t> perm, width, len;
+    std::vector<int64_t> start;
+    kpm_status st = sell_layout(d->N, d->rowptr, C, sigma, perm, width, start, len);
+    if (st != KPM_OK) return st;
+    const int64_t N = d->N;
+    const int64_t nnz = d->rowptr[N];
+    if (nnz > 0 && (!d->col || !d->val)) return fail(KPM_EINVAL, "col or val is NULL");
+    for (int64_t k = 0; k < nnz; ++k)
+        if (d->col[k] < 0 || d->col[k] >= N) return fail(KPM_EINVAL, "column out of range at entry " + std::to_string(k));
+    for (int64_t k = 0; k < 2 * nnz; ++k)
+        if (!std::isfinite(d->val[k])) return fail(KPM_EINVAL, "non-finite value at entry " + std::to_string(k / 2));
+    const int64_t nch = static_cast<int64_t>(width.size());
+    const int64_t stored = start[nch];
+    const size_t rs = real_size(d->dtype);
+    if (static_cast<uint64_t>(stored) * 2 * rs >= (1ull << 32) - 64)
+        return fail(KPM_ENOMEM, "SELL storage reaches 4 GiB of values");
+
+    // the padded arrays: value 0 and column N wherever a row ends early
+    const size_t ns = static_cast<size_t>(stored > 0 ? stored : 1);
+    std::vector<int32_t> hcol(ns, static_cast<int32_t>(N));
+    std::vector<double> hval(d->dtype == KPM_C128 ? 2 * ns : 0, 0.0);
+    std::vector<float> fval(d->dtype == KPM_C64 ? 2 * ns : 0, 0.0f);
+    for (int64_t p = 0; p < N; ++p) {
+        const int64_t row = perm[p];
+        const int64_t e0 = start[p / C] + (p % C);
+        for (int64_t k = d->rowptr[row], j = 0; k < d->rowptr[row + 1]; ++k, ++j) {
+            const int64_t e = e0 + j * C;
+            hcol[e] = d->col[k];
+            if (d->dtype == KPM_C128) {
+                hval[2 * e] = d->val[2 * k];
+                hval[2 * e + 1] = d->val[2 * k + 1];
+            } else {
+                fval[2 * e] = static_cast<float>(d->val[2 * k]);
+                fval[2 * e + 1] = static_cast<float>(d->val[2 * k + 1]);
+            }
+        }
+    }
+
+    auto* H = new kpm_hamiltonian();
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    H->dtype = d->dtype;
+    H->nrows = N;
+    H->width = nch > 0 ? *std::max_element(width.begin(), width.end()) : 0;
+    SellStore& c = H->sell;
+    c.C = C;
+    c.clog = 0;
+    while ((1 << c.clog) < C) ++c.clog;
+    c.sigma = sigma;
+    c.nchunks = nch;
+    c.stored = stored;
+    c.nnz = nnz;
+    c.len = std::move(len);
+    c.start_host = start;
+    if (sigma > 1) c.perm_host = perm;
+    if (hipGetDevice(&H->device) != hipSuccess) {
+        delete H;
+        return fail(KPM_EDEVICE, "hipGetDevice failed");
+    }
+    const int nblocks = build_blocks(N);
+    double* bb = nullptr;
+    double* bounds = nullptr;
+    double host_bounds[2] = {0.0, 0.0};
+    hipError_t e;
+    const size_t vbytes = ns * 2 * rs;
+    if ((e = hipMalloc(&H->val, vbytes)) != hipSuccess) st = hip_fail(e, "hipMalloc(val)");
+    else if ((e = hipMalloc(&H->col, ns * sizeof(int32_t))) != hipSuccess) st = hip_fail(e, "hipMalloc(col)");
+    else if ((e = hipMalloc(&c.start, start.size() * sizeof(int64_t))) != hipSuccess) st = hip_fail(e, "hipMalloc(start)");
+    else if ((e = hipMalloc(&c.width, width.size() * sizeof(int32_t))) != hipSuccess) st = hip_fail(e, "hipMalloc(width)");
+    else if (sigma > 1 && (e = hipMalloc(&c.perm, perm.size() * sizeof(int32_t))) != hipSuccess)
+        st = hip_fail(e, "hipMalloc(perm)");
+    else if ((e = hipMalloc(&bb, static_cast<size_t>(nblocks) * 2 * sizeof(double))) != hipSuccess)
+        st = hip_fail(e, "hipMalloc(bounds)");
+    else if ((e = hipMalloc(&bounds, 2 * sizeof(double))) != hipSuccess) st = hip_fail(e, "hipMalloc(bounds)");
+    else if ((e = hipMemcpyAsync(H->val, d->dtype == KPM_C128 ? static_cast<const void*>(hval.data()) : fval.data(),
+                                 vbytes, hipMemcpyHostToDevice, s)) != hipSuccess)
+        st = hip_fail(e, "copy val");
+    else if ((e = hipMemcpyAsync(H->col, hcol.data(), ns * sizeof(int32_t), hipMemcpyHostToDevice, s)) != hipSuccess)
+        st = hip_fail(e, "copy col");
+    else if ((e = hipMemcpyAsync(c.start, start.data(), start.size() * sizeof(int64_t), hipMemcpyHostToDevice, s)) !=
+             hipSuccess)
+        st = hip_fail(e, "copy start");
+    else if ((e = hipMemcpyAsync(c.width, width.data(), width.size() * sizeof(int32_t), hipMemcpyHostToDevice, s)) !=
+             hipSuccess)
+        st = hip_fail(e, "copy width");
+    else if (sigma > 1 && (e = hipMemcpyAsync(c.perm, perm.data(), perm.size() * sizeof(int32_t),
+                                              hipMemcpyHostToDevice, s)) != hipSuccess)
+        st = hip_fail(e, "copy perm");
+    else if ((e = launch_sell_bounds(H->dtype, H->val, H->col, c.start, c.width, c.perm, N, c.clog, bb, bounds, s)) !=
+             hipSuccess)
+        st = hip_fail(e, "bounds kernel");
+    else if ((e = hipMemcpyAsync(host_bounds, bounds, 2 * sizeof(double), hipMemcpyDeviceToHost, s)) != hipSuccess)
+        st = hip_fail(e, "copy bounds");
+    else if ((e = hipStreamSynchronize(s)) != hipSuccess)
+        st = hip_fail(e, "synchronise");
+    if (bb) (void)hipFree(bb);
+    if (bounds) (void)hipFree(bounds);
+    if (st != KPM_OK) {
+        kpm_destroy_hamiltonian(H);
+        return st;
+    }
+    H->emin = host_bounds[0];
+    H->emax = host_bounds[1];
+    if (d->fixed_scale) {
+        H->a = d->a;
+        H->b = d->b;
+    } else {
+        H->b = 0.5 * (H->emax + H->emin);
+        H->a = d->margin * 0.5 * (H->emax - H->emin);
+        if (!(H->a > 0.0)) {
+            kpm_destroy_hamiltonian(H);
+            return fail(KPM_EINVAL, "Gershgorin interval has zero width");
+        }
+    }
+    *out = H;
+    return KPM_OK;
+}
+
+kpm_status kpm_sell_info(const kpm_hamiltonian* H, int32_t* C, int32_t* sigma, int64_t* nchunks, int64_t* stored,
+                         int64_t* nnz) {
+    g_error.clear();
+    if (!H) return fail(KPM_EINVAL, "H is NULL");
+    const SellStore& c = H->sell;
+    if (C) *C = c.C;
+    if (sigma) *sigma = c.C > 0 ? c.sigma : 0;
+    if (nchunks) *nchunks = c.nchunks;
+    if (stored) *stored = c.stored;
+    if (nnz) *nnz = c.nnz;
+    return KPM_OK;
 }
 
 kpm_status kpm_aug_spmmv(const kpm_hamiltonian* Hc, const void* V, void* W, int32_t R, double alpha,
@@ -513,6 +765,7 @@ kpm_status kpm_aug_spmmv(const kpm_hamiltonian* Hc, const void* V, void* W, int3
     auto* H = const_cast<kpm_hamiltonian*>(Hc);
     kpm_status st = check_device(H);
     if (st != KPM_OK) return st;
+    if ((st = check_sell_block(H, R)) != KPM_OK) return st;
     const size_t bytes = static_cast<size_t>(H->nrows) * 2 * R * real_size(H->dtype);
     const char* v0 = static_cast<const char*>(V);
     const char* w0 = static_cast<const char*>(W);
@@ -555,6 +808,7 @@ kpm_status kpm_moments(const kpm_hamiltonian* Hc, const void* V0, int32_t R, int
     if (opts.tuning && (st = check_tuning(*opts.tuning)) != KPM_OK) return st;
     auto* H = const_cast<kpm_hamiltonian*>(Hc);
     if ((st = check_device(H)) != KPM_OK) return st;
+    if ((st = check_sell_block(H, R)) != KPM_OK) return st;
     TuningScope scope(opts.tuning);
     hipStream_t s = static_cast<hipStream_t>(stream);
     Workspace& w = *workspace(H, s);
@@ -669,6 +923,7 @@ kpm_status kpm_moments_naive(const kpm_hamiltonian* Hc, const void* V0, int32_t 
     auto* H = const_cast<kpm_hamiltonian*>(Hc);
     kpm_status st = check_device(H);
     if (st != KPM_OK) return st;
+    if ((st = check_sell_block(H, 1)) != KPM_OK) return st;
     TuningScope scope(nullptr);
     hipStream_t s = static_cast<hipStream_t>(stream);
     Workspace& ws = *workspace(H, s);
@@ -745,6 +1000,7 @@ kpm_status kpm_lanczos_bounds(const kpm_hamiltonian* Hc, int32_t steps, uint64_t
     auto* H = const_cast<kpm_hamiltonian*>(Hc);
     kpm_status st = check_device(H);
     if (st != KPM_OK) return st;
+    if ((st = check_sell_block(H, 1)) != KPM_OK) return st;
     TuningScope scope(nullptr);
     hipStream_t s = static_cast<hipStream_t>(stream);
     Workspace& ws = *workspace(H, s);
@@ -1100,6 +1356,8 @@ kpm_status kpm_moments_batched(const kpm_hamiltonian* const* H, const void* cons
         if (H[i]->device != dev) return fail(KPM_EINVAL, "H[i] was built on another device");
         if (i == 0) dtype = H[i]->dtype;
         if (H[i]->dtype != dtype) return fail(KPM_EINVAL, "all instances must have one dtype");
+        if (H[i]->sell.C > 0)
+            return fail(KPM_ENOTSUP, "the batched solver derives its columns from a lattice; H[i] is an imported matrix");
         const uint64_t pair = 2 * real_size(dtype);
         const uint64_t n = static_cast<uint64_t>(H[i]->nrows);
         // 32-bit buffer offsets, with room for the read-ahead past the last pass

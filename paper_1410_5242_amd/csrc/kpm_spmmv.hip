@@ -54,10 +54,13 @@ __global__ void __launch_bounds__(256) zero_ints_kernel(int* __restrict__ p, int
 
 // dst[i] = src[i] over n 16-byte units, grid-stride
 __global__ void __launch_bounds__(256)
-copy16_kernel(const int4* __restrict__ src, int4* __restrict__ dst, int64_t n) {
+copy16_kernel(const int4* __restrict__ src, int4* __restrict__ dst, int64_t n, int tail8) {
     const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride)
         dst[i] = src[i];
+    // a block of complex64 with an odd element count ends in half a unit
+    if (tail8 && blockIdx.x == 0 && threadIdx.x == 0)
+        *reinterpret_cast<int2*>(dst + n) = *reinterpret_cast<const int2*>(src + n);
 }
 
 // mu_{2m} = 2 eta_{2m} - mu_0, mu_{2m+1} = 2 Re eta_{2m+1} - mu_1.
@@ -203,11 +206,14 @@ hipError_t launch_zero_ints(int* p, int n, hipStream_t s) {
 
 hipError_t launch_copy16(void* dst, const void* src, size_t bytes, hipStream_t s) {
     const int64_t n = static_cast<int64_t>(bytes / 16);
-    if (n <= 0) return hipSuccess;
+    const int tail8 = (bytes % 16) >= 8 ? 1 : 0;
+    if (n <= 0 && !tail8) return hipSuccess;
     int64_t blocks = (n + 255) / 256;
     const int64_t cap = static_cast<int64_t>(device_cus()) * 16;   // 16 workgroups of 256 per CU
     if (blocks > cap) blocks = cap;
-    copy16_kernel<<<static_cast<int>(blocks), 256, 0, s>>>(static_cast<const int4*>(src), static_cast<int4*>(dst), n);
+    if (blocks < 1) blocks = 1;
+    copy16_kernel<<<static_cast<int>(blocks), 256, 0, s>>>(static_cast<const int4*>(src), static_cast<int4*>(dst), n,
+                                                          tail8);
     return hipGetLastError();
 }
 

@@ -83,3 +83,53 @@ def instance_family(n: int, sides, gamma_max: float, seed: int):
     gammas = rng.uniform(0.0, gamma_max, size=n)
     return [dict(L=(int(L), int(L), int(L)), gamma=float(g), pot_seed=int(seed) * 1_000_003 + i,
                  vec_seed=int(seed) * 1_000_003 + n + i) for i, (L, g) in enumerate(zip(Ls, gammas))]
+
+
+_HERM_STREAM = 0x5EED_0004
+
+
+def random_hermitian_csr(N: int, mean_offdiag: float = 12.0, tail: float = 1.5, max_couplings: int = 256,
+                         local_frac: float = 0.5, band: int = 64, empty_frac: float = 0.02, seed: int = 0):
+    """Seeded sparse Hermitian matrix with an irregular row-length mix, as host CRS.
+
+    Returns (rowptr int64 [N+1], col int32 [nnz], val complex128 [nnz]), columns sorted per row.
+    A fraction `empty_frac` of the rows is empty (no diagonal, no couplings).  Every other row i
+    proposes k_i couplings, k_i = round(mean_offdiag / 2 * (1 + X) * (tail - 1) / tail) with X drawn
+    from a Lomax law of index `tail` (a power-law tail, mean k_i about mean_offdiag / 2), capped
+    at `max_couplings`; a share `local_frac` of the partners lies within `band` rows of i
+    (periodically), the rest is uniform over the non-empty rows.  A coupling (i, j) adds h to
+    (i, j) and conj(h) to (j, i), h = (g + i g') / 2 with g, g' standard normal, so the mean row
+    holds about mean_offdiag off-diagonal entries; repeated pairs add up (in the upper triangle,
+    which is then mirrored, so the result is Hermitian exactly).  The diagonal of a non-empty row
+    is real, standard normal.
+    """
+    import scipy.sparse as sp
+
+    N = int(N)
+    rng = np.random.default_rng([int(seed), _HERM_STREAM])
+    empty = rng.random(N) < empty_frac
+    live = np.flatnonzero(~empty)
+    if live.size == 0:
+        return np.zeros(N + 1, dtype=np.int64), np.zeros(0, dtype=np.int32), np.zeros(0, dtype=np.complex128)
+    x = rng.pareto(tail, size=live.size)
+    k = np.rint(0.5 * mean_offdiag * (1.0 + x) * (tail - 1.0) / tail).astype(np.int64)
+    k = np.minimum(k, min(max_couplings, max(live.size - 1, 0)))
+    src = np.repeat(live, k)
+    near = rng.random(src.size) < local_frac
+    off = rng.integers(-band, band + 1, size=src.size)
+    dst = np.where(near, (src + off) % N, live[rng.integers(0, live.size, size=src.size)])
+    keep = (dst != src) & ~empty[dst]
+    src, dst = src[keep], dst[keep]
+    h = 0.5 * (rng.standard_normal(src.size) + 1j * rng.standard_normal(src.size))
+    d = rng.standard_normal(live.size)
+    # the strict upper triangle (repeated pairs summed once), mirrored, so
+    # that the matrix is Hermitian exactly
+    lo, hi = np.minimum(src, dst), np.maximum(src, dst)
+    h = np.where(src < dst, h, np.conj(h))
+    U = sp.coo_matrix((h, (lo, hi)), shape=(N, N)).tocsr()
+    U.sum_duplicates()
+    D = sp.coo_matrix((d.astype(np.complex128), (live, live)), shape=(N, N)).tocsr()
+    A = (U + U.conj().T.tocsr() + D).tocsr()
+    A.sum_duplicates()
+    A.sort_indices()
+    return A.indptr.astype(np.int64), A.indices.astype(np.int32), A.data.astype(np.complex128)

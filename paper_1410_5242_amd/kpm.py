@@ -65,6 +65,22 @@ class LatticeDesc(ctypes.Structure):
     ]
 
 
+class CsrDesc(ctypes.Structure):
+    _fields_ = [
+        ("N", ctypes.c_int64),
+        ("rowptr", ctypes.c_void_p),
+        ("col", ctypes.c_void_p),
+        ("val", ctypes.c_void_p),
+        ("dtype", ctypes.c_int32),
+        ("sell_C", ctypes.c_int32),
+        ("sell_sigma", ctypes.c_int32),
+        ("margin", ctypes.c_double),
+        ("fixed_scale", ctypes.c_int32),
+        ("a", ctypes.c_double),
+        ("b", ctypes.c_double),
+    ]
+
+
 class RunOpts(ctypes.Structure):
     _fields_ = [("check", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("variant", ctypes.c_int32),
                 ("mu_on_host", ctypes.c_int32), ("tuning", ctypes.POINTER(SweepTuning)),
@@ -85,7 +101,7 @@ EXPORTS = ("kpm_build_hamiltonian", "kpm_hamiltonian_info", "kpm_export_csr",
            "kpm_mlp_forward", "kpm_mlp_backward", "kpm_mlp_adam_step", "kpm_mlp_train_step",
            "kpm_mlp_gemm_bf16", "kpm_dos_batched", "kpm_moment_features", "kpm_random_phase_block",
            "kpm_moments_naive", "kpm_axpy", "kpm_scal", "kpm_dot", "kpm_dot_noalloc", "kpm_site_block", "kpm_plane_wave_block",
-           "kpm_lanczos_bounds", "kpm_set_scaling", "kpm_stream",
+           "kpm_lanczos_bounds", "kpm_set_scaling", "kpm_stream", "kpm_sell_layout", "kpm_import_csr", "kpm_sell_info",
            "kpm_last_error", "kpm_version")
 
 
@@ -106,6 +122,13 @@ def lib():
                                        ctypes.POINTER(dbl), ctypes.POINTER(dbl)]
     L.kpm_export_csr.restype = ctypes.c_int
     L.kpm_export_csr.argtypes = [vp, vp, vp, vp]
+    L.kpm_sell_layout.restype = ctypes.c_int
+    L.kpm_sell_layout.argtypes = [i64, vp, i32, i32, vp, vp, vp]
+    L.kpm_import_csr.restype = ctypes.c_int
+    L.kpm_import_csr.argtypes = [ctypes.POINTER(CsrDesc), vp, ctypes.POINTER(vp)]
+    L.kpm_sell_info.restype = ctypes.c_int
+    L.kpm_sell_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i64),
+                                ctypes.POINTER(i64), ctypes.POINTER(i64)]
     L.kpm_destroy_hamiltonian.restype = None
     L.kpm_destroy_hamiltonian.argtypes = [vp]
     L.kpm_aug_spmmv.restype = ctypes.c_int
@@ -272,6 +295,57 @@ def export_csr(H: Hamiltonian):
     val = np.zeros(2 * nnz, dtype=np.float64)
     _check(lib().kpm_export_csr(H.handle, rowptr.ctypes.data, col.ctypes.data, val.ctypes.data))
     return rowptr, col, val.view(np.complex128)
+
+
+def _csr_arrays(rowptr, col, val):
+    rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    val = np.ascontiguousarray(val, dtype=np.complex128)
+    return rowptr, col, val
+
+
+def sell_layout(rowptr, C: int, sigma: int):
+    """kpm_sell_layout (host only): (perm [N], width [nchunks], start [nchunks + 1]) of the
+    SELL-C-sigma layout of a CRS pattern."""
+    rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
+    N = rowptr.size - 1
+    nch = (N + int(C) - 1) // int(C) if C > 0 else 0
+    perm = np.zeros(max(N, 1), dtype=np.int32)
+    width = np.zeros(max(nch, 1), dtype=np.int32)
+    start = np.zeros(nch + 1, dtype=np.int64)
+    _check(lib().kpm_sell_layout(N, rowptr.ctypes.data, int(C), int(sigma), perm.ctypes.data, width.ctypes.data,
+                                 start.ctypes.data))
+    return perm[:N], width[:nch], start
+
+
+def import_csr(rowptr, col, val, dtype: str = "c128", C: int = 0, sigma: int = 0, margin: float = 1.01,
+               fixed_scale=None, stream=None) -> Hamiltonian:
+    """kpm_import_csr: a general sparse Hermitian matrix (host CRS; val complex) stored on the
+    device in SELL-C-sigma, with its Gershgorin scaling.  C = 0 and sigma = 0 take the library's
+    defaults."""
+    rowptr, col, val = _csr_arrays(rowptr, col, val)
+    d = CsrDesc()
+    d.N = rowptr.size - 1
+    d.rowptr = rowptr.ctypes.data
+    d.col = col.ctypes.data if col.size else None
+    d.val = val.ctypes.data if val.size else None
+    d.dtype = _DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
+    d.sell_C, d.sell_sigma = int(C), int(sigma)
+    d.margin = float(margin)
+    if fixed_scale is not None:
+        d.fixed_scale = 1
+        d.a, d.b = float(fixed_scale[0]), float(fixed_scale[1])
+    h = ctypes.c_void_p()
+    _check(lib().kpm_import_csr(ctypes.byref(d), _stream(stream), ctypes.byref(h)))
+    return Hamiltonian(h)
+
+
+def sell_info(H: Hamiltonian) -> dict:
+    """kpm_sell_info: C, sigma, chunks, stored entries (padding included) and imported nonzeros."""
+    C, sigma = ctypes.c_int32(), ctypes.c_int32()
+    nch, stored, nnz = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().kpm_sell_info(H.handle, C, sigma, nch, stored, nnz))
+    return {"C": C.value, "sigma": sigma.value, "nchunks": nch.value, "stored": stored.value, "nnz": nnz.value}
 
 
 def aug_spmmv(H: Hamiltonian, V: torch.Tensor, W: torch.Tensor, alpha: float, beta: float, gamma: float,
@@ -542,7 +616,8 @@ def get_sweep_tuning():
             "gather_tile": t.gather_tile}
 
 
-SWEEP_KERNELS = {0: "aug_spmmv_kernel", 1: "lattice_kernel", 2: "gather_sweep_kernel", 3: "window_sweep_kernel"}
+SWEEP_KERNELS = {0: "aug_spmmv_kernel", 1: "lattice_kernel", 2: "gather_sweep_kernel", 3: "window_sweep_kernel",
+                 4: "sell_sweep_kernel"}
 
 
 def sweep_kernel(H: Hamiltonian, R: int) -> str:

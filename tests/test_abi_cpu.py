@@ -125,5 +125,5 @@ def test_struct_layouts_match_the_header():
 
     for cls, name in ((kpm.LatticeDesc, "kpm_lattice_desc"), (kpm.RunOpts, "kpm_run_opts"),
                       (kpm.SweepTuning, "kpm_sweep_tuning"), (kpm.BatchTuning, "kpm_batch_tuning"),
-                      (kpm.SweepPlan, "kpm_sweep_plan_info")):
+                      (kpm.SweepPlan, "kpm_sweep_plan_info"), (kpm.CsrDesc, "kpm_csr_desc")):
         assert [f[0] for f in cls._fields_] == fields(name), name

@@ -71,3 +71,14 @@ def test_pick_best_keeps_default_within_margin():
     assert A.pick_best(t, margin=0.0).params == {"a": 1}
     t.append(A.Trial({"c": 3}, 0.95))
     assert A.pick_best(t, margin=0.02).params == {"c": 3}
+
+
+def test_sell_candidates_are_valid_layouts():
+    cands = A.sell_candidates()
+    assert cands[0] == {"C": 8, "sigma": 1024}          # the library default first
+    assert len({(c["C"], c["sigma"]) for c in cands}) == len(cands)
+    for c in cands:
+        assert c["C"] in (1, 2, 4, 8, 16, 32, 64)
+        assert c["sigma"] == 1 or c["sigma"] % c["C"] == 0
+    assert {"C": 1, "sigma": 1} in cands                # CRS is always tried
+    assert A.sell_key(0, 32, 1000, 13000) == "sell:c128:R32:N512:nnz8192"

@@ -89,3 +89,27 @@ def test_tune_batched_and_block_width(tmp_path):
     say("tune block width")
     res = A.tune_block_width(Hs[-1], 16, cache=cache, sweeps=2, repeats=1)
     assert res.best["R"] in (1, 2, 4, 8, 16) and len(res.trials) == 5
+
+
+def test_tune_sell_layout_then_moments_match_oracle(tmp_path):
+    # the SELL-C-sigma layout of a general matrix as a tuning dimension
+    from paper_1410_5242_amd import autotune as A, kpm as K
+    N, R, M = 6000, 8, 48
+    say("tune sell layout", N, R)
+    rowptr, col, val = inputs.random_hermitian_csr(N, seed=12)
+    cands = [{"C": 8, "sigma": 1024}, {"C": 1, "sigma": 1}, {"C": 32, "sigma": 1}, {"C": 64, "sigma": 4096}]
+    cache = A.TuningCache(str(tmp_path / "s.json"))
+    res = A.tune_sell_layout(rowptr, col, val, R, cache=cache, candidates=cands, sweeps=4, repeats=2)
+    assert res.best in cands and len(res.trials) == len(cands)
+    _, _, start = K.sell_layout(rowptr, 32, 1)
+    assert [t.params["stored"] for t in res.trials][2] == int(start[-1])
+    cache.save()
+    assert A.TuningCache(cache.path).get(res.key) == res.best
+    H = K.import_csr(rowptr, col, val, **res.best)
+    Ho = O.CSR(rowptr, col, val)
+    a, b = O.scaling(*O.gershgorin(Ho))
+    K.set_scaling(H, a, b)
+    v0 = inputs.phase_block(N, R, 2)
+    mu = K.moments(H, torch.from_numpy(v0).cuda(), M).cpu().numpy()
+    assert np.abs(mu - O.kpm_moments(Ho, a, b, v0, M)).max() <= 1e-12
+    H.close()

@@ -150,6 +150,26 @@ def test_moments_match_dense_eigendecomposition_small():
     assert np.abs(mu[:, 0] - 1.0).max() <= 1e-14
 
 
+def test_moments_of_an_irregular_matrix_match_its_eigendecomposition():
+    # a general Hermitian matrix with empty rows and a long tail of row
+    # lengths (the SELL-C-sigma workloads): the oracle's recurrence against
+    # mu_n = sum_k |<k|v>|^2 cos(n arccos x_k) from eigh, and its Gershgorin
+    # interval against the spectrum
+    N, R, M = 120, 3, 96
+    rowptr, col, val = inputs.random_hermitian_csr(N, mean_offdiag=8.0, empty_frac=0.05, seed=9)
+    H = O.CSR(rowptr, col, val)
+    lam, U = np.linalg.eigh(H.dense())
+    emin, emax = O.gershgorin(H)
+    assert emin <= lam[0] and lam[-1] <= emax
+    a, b = O.scaling(emin, emax)
+    v0 = inputs.phase_block(N, R, 1)
+    mu = O.kpm_moments(H, a, b, v0, M)
+    x = np.clip((lam - b) / a, -1.0, 1.0)
+    w = np.abs(U.conj().T @ v0) ** 2                               # [N eigenvalues][R]
+    T = np.cos(np.arange(M)[:, None] * np.arccos(x)[None, :])      # [M][N]
+    assert np.abs(mu - (T @ w).T).max() <= 1e-12
+
+
 @pytest.mark.slow
 def test_moments_match_dense_eigendecomposition_8cubed():
     # 8^3 lattice, gamma = 1, seed 0, R = 1, M = 128 (N = 2048)
