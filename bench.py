@@ -428,6 +428,53 @@ def leg_variants(sweeps: int = 10):
     return out
 
 
+def leg_sell(sweeps: int = 10):
+    """The SELL-C-sigma path for general matrices (kpm_import_csr): single FULL sweeps at R = 1, 8
+    and 32 from the library's per-launch HIP events, on two matrices handed over as host CRS: the
+    64^3 complex128 lattice (the headline matrix, exported from the library's builder; 13 entries
+    in every row, so no padding) and a seeded irregular Hermitian matrix of 2^20 rows (a power-law
+    mix of row lengths, 2 % empty rows, half the couplings within 64 rows and half uniformly
+    random).  GB/s against the paper's model bytes Nnz (S_d + S_i) + 3 R S_d N, with Nnz the
+    imported nonzeros; stored/nnz is the layout's padding."""
+    import torch
+    from paper_1410_5242_amd import inputs, kpm
+    L = (64, 64, 64)
+    Hl = kpm.build_hamiltonian(L, inputs.potential(L, 1.0, 0))
+    lattice = kpm.export_csr(Hl)
+    Hl.close()
+    irregular = inputs.random_hermitian_csr(1 << 20, seed=1)
+    out = {"workload": f"FULL sweeps, {sweeps} per point, complex128; matrices as host CRS", "points": []}
+    for name, (rowptr, col, val), layouts in (
+            ("TI 64x64x64 periodic", lattice, ((8, 1024), (1, 1), (32, 32))),
+            ("irregular 2^20 rows", irregular, ((8, 1024), (1, 1), (32, 1), (32, 1024)))):
+        N, nnz = len(rowptr) - 1, int(rowptr[-1])
+        for C, sigma in layouts:
+            H = kpm.import_csr(rowptr, col, val, C=C, sigma=sigma)
+            stored = kpm.sell_info(H)["stored"]
+            for R in (1, 8, 32):
+                V = kpm.random_phase_block(N, R, 1, "c128")
+                W = kpm.random_phase_block(N, R, 2, "c128")
+                eta = torch.zeros((2, R, 2), dtype=torch.float64, device="cuda")
+                kpm.aug_spmmv(H, V, W, 2.0 / H.a, -2.0 * H.b / H.a, -1.0, "full", eta)
+                torch.cuda.synchronize()
+                kpm.sweep_profile_read()
+                kpm.sweep_profile_enable(True)
+                for _ in range(sweeps):
+                    kpm.aug_spmmv(H, V, W, 2.0 / H.a, -2.0 * H.b / H.a, -1.0, "full", eta)
+                torch.cuda.synchronize()
+                kpm.sweep_profile_enable(False)
+                n, tot, lo, hi = kpm.sweep_profile_read()
+                avg_s = tot / n * 1e-3
+                byts = nnz * (16 + 4) + 3 * R * 16 * N
+                out["points"].append({"matrix": name, "N": N, "nnz": nnz, "C": C, "sigma": sigma,
+                                      "stored_over_nnz": round(stored / nnz, 3), "R": R,
+                                      "kernel": kpm.sweep_kernel(H, R), "avg_us": round(avg_s * 1e6, 1),
+                                      "GBps": round(byts / avg_s / 1e9, 1), "bytes": byts})
+                del V, W
+            H.close()
+    return out
+
+
 def leg_ladder(steps: int = 200, repeats: int = 3):
     """The paper's optimisation ladder on the 64^3 complex128 lattice, per start vector and KPM
     step (one moment pair): the naive algorithm (one SpMV and five BLAS-1 calls per step, one
@@ -745,9 +792,9 @@ def main():
     ap.add_argument("--batch-tuning", default=None,
                     help="waves,wg_per_cu,dynamic,slab for the batched leg instead of the tuning cache")
     ap.add_argument("--legs", default="small,variants,custom_roofline,ladder,precision,batched,spectral,slab,bounds,"
-                                      "time_to_dos,oracle_subsets",
+                                      "sell,time_to_dos,oracle_subsets",
                     help="extra measurements after the headline step (comma separated): any of small, variants, "
-                         "custom_roofline, ladder, precision, batched, spectral, slab, bounds, time_to_dos, "
+                         "custom_roofline, ladder, precision, batched, spectral, slab, bounds, sell, time_to_dos, "
                          "oracle_subsets; or none")
     args = ap.parse_args()
     if args.batch_tuning:
@@ -890,7 +937,8 @@ def main():
     for name, fn in (("small", leg_small), ("variants", leg_variants), ("custom_roofline", leg_custom_roofline),
                      ("ladder", leg_ladder),
                      ("precision", leg_precision), ("batched", leg_batched), ("spectral", leg_spectral),
-                     ("slab", leg_slab), ("bounds", leg_bounds), ("time_to_dos", leg_time_to_dos)):
+                     ("slab", leg_slab), ("bounds", leg_bounds), ("sell", leg_sell),
+                     ("time_to_dos", leg_time_to_dos)):
         if name in legs:
             log(f"[bench] leg {name}")
             out[name] = fn()
