@@ -73,6 +73,10 @@ typedef struct {
     double margin;           /* half-width factor applied to the Gershgorin interval (e.g. 1.01) */
     int32_t fixed_scale;     /* nonzero: use a, b below instead of the Gershgorin bound */
     double a, b;             /* caller-fixed scaling when fixed_scale != 0 (a > 0) */
+    int32_t sell_C;          /* 0: the lattice layout (13 slots per row, the lattice sweeps);
+                                else store the built matrix in SELL-C-sigma with this chunk
+                                height, as kpm_import_csr would (padding slots dropped) */
+    int32_t sell_sigma;      /* sorting window for sell_C > 0 (0: 128 sell_C) */
 } kpm_lattice_desc;
 
 typedef struct kpm_hamiltonian kpm_hamiltonian; /* opaque, library-owned */
@@ -92,20 +96,25 @@ typedef struct kpm_hamiltonian kpm_hamiltonian; /* opaque, library-owned */
  * "Testbed and Implementation" reduces to chunk height 1 without sorting.
  * Errors: KPM_EINVAL (null desc/out, side <= 0, non-finite potential, t or
  * gamma, gamma < 0, margin < 1, a <= 0), KPM_ENOTSUP (a periodic side < 3),
- * KPM_ENOMEM, KPM_EDEVICE.  *out is NULL on error. */
+ * KPM_ENOMEM, KPM_EDEVICE; with sell_C > 0 also the layout errors of
+ * kpm_import_csr.  *out is NULL on error. */
 kpm_status kpm_build_hamiltonian(const kpm_lattice_desc* desc, void* stream,
                                  kpm_hamiltonian** out);
 
 /* Sizes and scaling of a built H.  Any output pointer may be NULL.
- * nnz_stored counts stored entries including padding (= width * N). */
+ * nnz_stored counts stored entries including padding (= width * N in the
+ * lattice layout; the SELL-C-sigma storage's entries for an imported H, whose
+ * width is its longest row). */
 kpm_status kpm_hamiltonian_info(const kpm_hamiltonian* H, int64_t* N, int64_t* nnz_stored,
                                 int32_t* width, int32_t* dtype, double* a, double* b,
                                 double* emin, double* emax);
 
 /* Copy H to host CRS for inspection: rowptr [N+1], col [nnz], val [2*nnz]
- * (re, im as double).  Explicit padding zeros are dropped; each row keeps
- * the library's slot order (diagonal first).  Pass col = val = NULL to get
- * only rowptr (and so the count).  Synchronous.  Errors: KPM_EINVAL. */
+ * (re, im as double).  Lattice layout: explicit padding zeros are dropped and
+ * each row keeps the library's slot order (diagonal first).  SELL-C-sigma
+ * storage: the rows as imported (their order of entries, explicit zeros of
+ * the input kept), padding dropped.  Pass col = val = NULL to get only
+ * rowptr (and so the count).  Synchronous.  Errors: KPM_EINVAL. */
 kpm_status kpm_export_csr(const kpm_hamiltonian* H, int64_t* rowptr, int32_t* col, double* val);
 
 /* Release H and its workspaces (synchronises the device).  NULL is a no-op. */

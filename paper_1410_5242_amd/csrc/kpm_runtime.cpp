@@ -444,6 +444,34 @@ const char* kpm_last_error(void) { return g_error.c_str(); }
 
 const char* kpm_version(void) { return "kpm-mi355x 0.1 (gfx950)"; }
 
+// A built H handed to SELL-C-sigma storage through host CRS, keeping its
+// bounds and scaling.
+static kpm_status to_sell(const kpm_hamiltonian* H, int C, int sigma, void* stream, kpm_hamiltonian** out) {
+    std::vector<int64_t> rowptr(static_cast<size_t>(H->nrows) + 1);
+    kpm_status st = kpm_export_csr(H, rowptr.data(), nullptr, nullptr);
+    if (st != KPM_OK) return st;
+    const size_t nnz = static_cast<size_t>(rowptr.back());
+    std::vector<int32_t> col(nnz > 0 ? nnz : 1);
+    std::vector<double> val(nnz > 0 ? 2 * nnz : 2);
+    if ((st = kpm_export_csr(H, rowptr.data(), col.data(), val.data())) != KPM_OK) return st;
+    kpm_csr_desc c{};
+    c.N = H->nrows;
+    c.rowptr = rowptr.data();
+    c.col = col.data();
+    c.val = val.data();
+    c.dtype = H->dtype;
+    c.sell_C = C;
+    c.sell_sigma = sigma;
+    c.margin = 1.0;
+    c.fixed_scale = 1;
+    c.a = H->a;
+    c.b = H->b;
+    if ((st = kpm_import_csr(&c, stream, out)) != KPM_OK) return st;
+    (*out)->emin = H->emin;
+    (*out)->emax = H->emax;
+    return KPM_OK;
+}
+
 kpm_status kpm_build_hamiltonian(const kpm_lattice_desc* d, void* stream, kpm_hamiltonian** out) {
     g_error.clear();
     if (!out) return fail(KPM_EINVAL, "out is NULL");
@@ -463,6 +491,12 @@ kpm_status kpm_build_hamiltonian(const kpm_lattice_desc* d, void* stream, kpm_ha
             return fail(KPM_EINVAL, "fixed scale needs a finite a > 0 and a finite b");
     } else if (!(d->margin >= 1.0) || !std::isfinite(d->margin)) {
         return fail(KPM_EINVAL, "margin must be a finite number >= 1");
+    }
+    if (d->sell_C != 0) {
+        if (d->sell_C < 1 || d->sell_C > 64 || (d->sell_C & (d->sell_C - 1)) != 0)
+            return fail(KPM_EINVAL, "sell_C must be 0 or a power of two in 1..64");
+        if (d->sell_sigma < 0 || (d->sell_sigma > 1 && d->sell_sigma % d->sell_C != 0))
+            return fail(KPM_EINVAL, "sell_sigma must be 0, 1 or a multiple of sell_C");
     }
     const int64_t nsite = static_cast<int64_t>(d->L[0]) * d->L[1] * d->L[2];
     if (nsite > (INT32_MAX / 4)) return fail(KPM_ENOMEM, "lattice too large for int32 column indices");
@@ -527,6 +561,15 @@ kpm_status kpm_build_hamiltonian(const kpm_lattice_desc* d, void* stream, kpm_ha
             kpm_destroy_hamiltonian(H);
             return fail(KPM_EINVAL, "Gershgorin interval has zero width");
         }
+    }
+    if (d->sell_C > 0) {
+        // the built matrix into SELL-C-sigma storage, with the lattice's
+        // bounds and scaling (those of the exact entries)
+        kpm_hamiltonian* S = nullptr;
+        st = to_sell(H, d->sell_C, d->sell_sigma, stream, &S);
+        kpm_destroy_hamiltonian(H);
+        if (st != KPM_OK) return st;
+        H = S;
     }
     *out = H;
     return KPM_OK;

@@ -62,6 +62,8 @@ class LatticeDesc(ctypes.Structure):
         ("fixed_scale", ctypes.c_int32),
         ("a", ctypes.c_double),
         ("b", ctypes.c_double),
+        ("sell_C", ctypes.c_int32),
+        ("sell_sigma", ctypes.c_int32),
     ]
 
 
@@ -260,11 +262,12 @@ class Hamiltonian:
 
 def build_hamiltonian(L, potential=None, t: float = 1.0, periodic=(1, 1, 1), dtype: str = "c128",
                       margin: float = 1.01, fixed_scale=None, gamma: float = 0.0, seed: int = 0,
-                      stream=None) -> Hamiltonian:
+                      sell_C: int = 0, sell_sigma: int = 0, stream=None) -> Hamiltonian:
     """kpm_build_hamiltonian: H of eq. "Ham" on the device plus its Gershgorin scaling.
 
     `potential` is the host array of V_n; None draws V_n ~ U[-gamma/2, gamma/2) on the device
-    from the library's counter generator keyed by `seed`."""
+    from the library's counter generator keyed by `seed`.  sell_C > 0 stores the built matrix in
+    SELL-C-sigma (chunk height sell_C, sorting window sell_sigma) instead of the lattice layout."""
     d = LatticeDesc()
     for j in range(3):
         d.L[j] = int(L[j])
@@ -281,6 +284,7 @@ def build_hamiltonian(L, potential=None, t: float = 1.0, periodic=(1, 1, 1), dty
     if fixed_scale is not None:
         d.fixed_scale = 1
         d.a, d.b = float(fixed_scale[0]), float(fixed_scale[1])
+    d.sell_C, d.sell_sigma = int(sell_C), int(sell_sigma)
     h = ctypes.c_void_p()
     _check(lib().kpm_build_hamiltonian(ctypes.byref(d), _stream(stream), ctypes.byref(h)))
     return Hamiltonian(h)

@@ -314,3 +314,36 @@ def test_default_layout_and_kernel_report():
     assert K.sell_info(Hl) == {"C": 0, "sigma": 0, "nchunks": 0, "stored": 0, "nnz": 0}
     Hl.close()
     H.close()
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_lattice_built_into_sell_storage(dtype):
+    # kpm_lattice_desc.sell_C: the builder's matrix stored in SELL-C-sigma
+    # (open z, so padding slots are dropped and chunks pad), with the
+    # lattice's exact bounds and scaling; moments against the oracle and the
+    # lattice layout
+    K = kpm()
+    L, R, M = (5, 6, 7), 8, 80
+    say("lattice into sell", dtype)
+    pot = inputs.potential(L, 1.0, 3)
+    Ho = O.ti_hamiltonian(L, pot, periodic=(1, 1, 0))
+    Hl = K.build_hamiltonian(L, pot, periodic=(1, 1, 0), dtype=dtype)
+    H = K.build_hamiltonian(L, pot, periodic=(1, 1, 0), dtype=dtype, sell_C=16, sell_sigma=256)
+    info = K.sell_info(H)
+    assert (info["C"], info["sigma"], info["nnz"]) == (16, 256, Ho.nnz)
+    assert (H.a, H.b, H.emin, H.emax) == (Hl.a, Hl.b, Hl.emin, Hl.emax)
+    rp, c, v = K.export_csr(H)
+    rl, cl, vl = K.export_csr(Hl)
+    assert np.array_equal(rp, rl) and np.array_equal(c, cl) and np.array_equal(v, vl)
+    assert K.sweep_kernel(H, R) == "sell_sweep_kernel"
+    a, b = O.scaling(*O.gershgorin(Ho))
+    v0 = inputs.phase_block(Ho.n, R, 6)
+    ref = O.kpm_moments(Ho, a, b, v0, M)
+    V0 = torch.from_numpy(v0.astype(np.complex128 if dtype == "c128" else np.complex64)).cuda()
+    mu = K.moments(H, V0, M).cpu().numpy()
+    mu_l = K.moments(Hl, V0, M).cpu().numpy()
+    tol = TOL_C128 if dtype == "c128" else TOL_C64
+    assert np.abs(mu - ref).max() <= tol
+    assert np.abs(mu - mu_l).max() <= (TOL_C128 if dtype == "c128" else 1e-6)
+    H.close()
+    Hl.close()

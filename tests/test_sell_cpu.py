@@ -157,3 +157,18 @@ def test_irregular_generator_is_hermitian_seeded_and_irregular():
     assert np.array_equal(r2, rowptr) and np.array_equal(c2, col) and np.array_equal(v2, val)
     r3, _, _ = inputs.random_hermitian_csr(N, seed=5)
     assert not np.array_equal(r3, rowptr)
+
+
+def test_lattice_desc_sell_fields_are_validated_before_any_device_call(kpm):
+    L = kpm.lib()
+    out = ctypes.c_void_p(1)
+    d = kpm.LatticeDesc()
+    d.L[0] = d.L[1] = d.L[2] = 4
+    d.periodic[0] = d.periodic[1] = d.periodic[2] = 1
+    d.t, d.margin = 1.0, 1.01
+    for C, sigma, msg in ((3, 0, b"sell_C"), (128, 0, b"sell_C"), (-1, 0, b"sell_C"), (8, 12, b"sell_sigma"),
+                          (8, -4, b"sell_sigma")):
+        d.sell_C, d.sell_sigma = C, sigma
+        assert L.kpm_build_hamiltonian(ctypes.byref(d), None, ctypes.byref(out)) == kpm.KPM_EINVAL, (C, sigma)
+        assert msg in L.kpm_last_error()
+        assert out.value is None
