@@ -434,8 +434,10 @@ def leg_sell(sweeps: int = 10):
     64^3 complex128 lattice (the headline matrix, exported from the library's builder; 13 entries
     in every row, so no padding) and a seeded irregular Hermitian matrix of 2^20 rows (a power-law
     mix of row lengths, 2 % empty rows, half the couplings within 64 rows and half uniformly
-    random).  GB/s against the paper's model bytes Nnz (S_d + S_i) + 3 R S_d N, with Nnz the
-    imported nonzeros; stored/nnz is the layout's padding."""
+    random); and the paper's 100 x 100 x 40 quantum-dot slab (open z, rows of 11 entries on its two
+    surfaces) built straight into SELL storage by the lattice builder.  GB/s against the paper's
+    model bytes Nnz (S_d + S_i) + 3 R S_d N, with Nnz the stored nonzeros without padding;
+    stored/nnz is the layout's padding."""
     import torch
     from paper_1410_5242_amd import inputs, kpm
     L = (64, 64, 64)
@@ -443,13 +445,23 @@ def leg_sell(sweeps: int = 10):
     lattice = kpm.export_csr(Hl)
     Hl.close()
     irregular = inputs.random_hermitian_csr(1 << 20, seed=1)
-    out = {"workload": f"FULL sweeps, {sweeps} per point, complex128; matrices as host CRS", "points": []}
-    for name, (rowptr, col, val), layouts in (
+    Ls = (100, 100, 40)
+    slab_pot = inputs.quantum_dot_potential(Ls)
+    out = {"workload": f"FULL sweeps, {sweeps} per point, complex128; matrices as host CRS, and the paper's "
+                       f"100x100x40 quantum-dot slab (open z: its two surfaces have rows of 11 entries) built "
+                       f"straight into SELL-C-sigma storage", "points": []}
+    for name, csr, layouts in (
             ("TI 64x64x64 periodic", lattice, ((8, 1024), (1, 1), (32, 32))),
-            ("irregular 2^20 rows", irregular, ((8, 1024), (1, 1), (32, 1), (32, 1024)))):
-        N, nnz = len(rowptr) - 1, int(rowptr[-1])
+            ("irregular 2^20 rows", irregular, ((8, 1024), (1, 1), (32, 1), (32, 1024))),
+            ("slab 100x100x40 quantum dots", None, ((8, 1024), (8, 1), (32, 1)))):
         for C, sigma in layouts:
-            H = kpm.import_csr(rowptr, col, val, C=C, sigma=sigma)
+            if csr is None:
+                H = kpm.build_hamiltonian(Ls, slab_pot, periodic=(1, 1, 0), sell_C=C, sell_sigma=sigma)
+                N, nnz = H.N, kpm.sell_info(H)["nnz"]
+            else:
+                rowptr, col, val = csr
+                N, nnz = len(rowptr) - 1, int(rowptr[-1])
+                H = kpm.import_csr(rowptr, col, val, C=C, sigma=sigma)
             stored = kpm.sell_info(H)["stored"]
             for R in (1, 8, 32):
                 V = kpm.random_phase_block(N, R, 1, "c128")
