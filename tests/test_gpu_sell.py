@@ -347,3 +347,18 @@ def test_lattice_built_into_sell_storage(dtype):
     assert np.abs(mu - mu_l).max() <= (TOL_C128 if dtype == "c128" else 1e-6)
     H.close()
     Hl.close()
+
+
+def test_sell_scaling_too_tight_reports_spectrum():
+    # an imported matrix under a half-width of 40 % of its spectral radius:
+    # the Chebyshev recurrence leaves [-1, 1] and the moment check refuses it
+    K = kpm()
+    N, R, M = 2000, 2, 64
+    rowptr, col, val, Ho = irregular(N, 14)
+    lam = np.linalg.eigvalsh(Ho.dense())
+    H = K.import_csr(rowptr, col, val, fixed_scale=(0.4 * max(abs(lam[0]), abs(lam[-1])), 0.0))
+    V0 = torch.from_numpy(inputs.phase_block(N, R, 1)).cuda()
+    with pytest.raises(K.KPMError) as e:
+        K.moments(H, V0, M, check=True)
+    assert e.value.status == K.KPM_ESPECTRUM
+    H.close()
