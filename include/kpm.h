@@ -205,6 +205,12 @@ typedef struct {
     const struct kpm_sweep_tuning* tuning;   /* launch shape for this call only (NULL: the process-wide
                                          kpm_set_sweep_tuning setting, read once at entry) */
     double* eta_out;     /* optional device [M][R] complex double: the raw products eta_n */
+    int32_t group;       /* column groups: 0 = the whole block in one recurrence, unless the sweeps
+                            could not address it (an [N+1][R] block of 4 GiB or more: then the
+                            widest supported width whose block fits); else a supported width
+                            dividing R: the R columns run as R / group independent recurrences of
+                            that width, one after the other, on work blocks of N x group (the
+                            matrix is read once per group and sweep).  Not with eta_out. */
 } kpm_run_opts;
 
 /* Chebyshev moments for R start vectors (eq. "eq:kpm_iter", scalar products
@@ -219,6 +225,9 @@ typedef struct {
  * Workspaces (two blocks, the partial sums, the graph) are cached on H per
  * stream: calls on one stream reuse them in order, calls on different
  * streams (also from different threads) use separate sets and may overlap.
+ * The start vectors' recurrences are independent (the columns of a block
+ * share only the matrix), so a block split into column groups (opts->group)
+ * gives the same moments up to the order of the scalar products' sums.
  * Errors: KPM_EINVAL, KPM_ENOTSUP, KPM_ENOMEM, KPM_ESPECTRUM, KPM_EDEVICE. */
 kpm_status kpm_moments(const kpm_hamiltonian* H, const void* V0, int32_t R, int32_t M, double* mu,
                        const kpm_run_opts* opts, void* stream);

@@ -378,6 +378,8 @@ hipError_t launch_axpy(int dtype, int64_t n, double alpha, const void* x, void* 
 hipError_t launch_scal(int dtype, int64_t n, double alpha, void* x, hipStream_t s);
 hipError_t launch_dot(int dtype, int64_t n, const void* x, const void* y, double* part, double* out, hipStream_t s);
 hipError_t launch_column(int dtype, int64_t n, int R, int r, const void* V, void* v, hipStream_t s);
+// columns c0 .. c0 + G - 1 of an [n][R] block into a contiguous [n][G] block
+hipError_t launch_columns(int dtype, int64_t n, int R, int c0, int G, const void* V, void* v, hipStream_t s);
 // Lanczos bounds: the recurrence's vector steps with alpha, beta read from
 // device memory, and the extreme eigenvalues of the tridiagonal matrix.
 int lanczos_max_steps();

@@ -156,6 +156,21 @@ column_kernel(int64_t n, int R, int r, const T* __restrict__ V, T* __restrict__ 
     }
 }
 
+// dst [n][G] <- columns c0 .. c0 + G - 1 of src [n][R] (a column group of a
+// block, 64-bit indexing: the block may exceed 4 GiB)
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+columns_kernel(int64_t n, int R, int c0, int G, const T* __restrict__ V, T* __restrict__ v) {
+    const int64_t total = n * G;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * kThreads;
+    for (int64_t k = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x; k < total; k += stride) {
+        const int64_t i = k / G;
+        const int64_t src = i * R + c0 + (k - i * G);
+        v[2 * k] = V[2 * src];
+        v[2 * k + 1] = V[2 * src + 1];
+    }
+}
+
 template <typename T>
 hipError_t axpy_t(int64_t n, double alpha, const void* x, void* y, hipStream_t s) {
     const int64_t nr = 2 * n;
@@ -233,6 +248,16 @@ hipError_t launch_dot(int dtype, int64_t n, const void* x, const void* y, double
 
 hipError_t launch_column(int dtype, int64_t n, int R, int r, const void* V, void* v, hipStream_t s) {
     return dtype == KPM_C128 ? column_t<double>(n, R, r, V, v, s) : column_t<float>(n, R, r, V, v, s);
+}
+
+hipError_t launch_columns(int dtype, int64_t n, int R, int c0, int G, const void* V, void* v, hipStream_t s) {
+    if (dtype == KPM_C128)
+        columns_kernel<double><<<blocks_for(n * G), kThreads, 0, s>>>(n, R, c0, G, static_cast<const double*>(V),
+                                                                      static_cast<double*>(v));
+    else
+        columns_kernel<float><<<blocks_for(n * G), kThreads, 0, s>>>(n, R, c0, G, static_cast<const float*>(V),
+                                                                     static_cast<float*>(v));
+    return hipGetLastError();
 }
 
 }  // namespace kpm

@@ -851,20 +851,37 @@ kpm_status kpm_moments(const kpm_hamiltonian* Hc, const void* V0, int32_t R, int
     if (opts.tuning && (st = check_tuning(*opts.tuning)) != KPM_OK) return st;
     auto* H = const_cast<kpm_hamiltonian*>(Hc);
     if ((st = check_device(H)) != KPM_OK) return st;
-    if ((st = check_sell_block(H, R)) != KPM_OK) return st;
+    // column groups: the caller's width, or the widest supported width whose
+    // block the sweeps can address (32-bit buffer offsets, the padding row
+    // of imported matrices included)
+    int G = R;
+    if (opts.group != 0) {
+        if (!r_supported(opts.group) || R % opts.group != 0)
+            return fail(KPM_EINVAL, "group must be one of 1, 2, 4, ..., 64 and divide R");
+        G = opts.group;
+    } else {
+        const uint64_t lim = (1ull << 32) - (1ull << 24);
+        auto fits = [&](int g) {
+            return (static_cast<uint64_t>(H->nrows) + 1) * g * 2 * real_size(H->dtype) < lim;
+        };
+        while (G > 1 && !fits(G)) G /= 2;
+    }
+    const bool grouped = G < R;
+    if (grouped && opts.eta_out) return fail(KPM_ENOTSUP, "eta_out needs the whole block in one recurrence");
+    if ((st = check_sell_block(H, G)) != KPM_OK) return st;
     TuningScope scope(opts.tuning);
     hipStream_t s = static_cast<hipStream_t>(stream);
     Workspace& w = *workspace(H, s);
     const int sweeps = M / 2;
     const int slots = sweeps < kReduceEvery ? sweeps : kReduceEvery;
     const int32_t* sched = nullptr;
-    if ((st = ensure_vectors(w, H, R)) != KPM_OK) return st;
+    if ((st = ensure_vectors(w, H, G)) != KPM_OK) return st;
     if ((st = schedule_for(H, &sched)) != KPM_OK) return st;
-    if (full && (st = ensure_partials(w, H, R, slots)) != KPM_OK) return st;
+    if (full && (st = ensure_partials(w, H, G, slots)) != KPM_OK) return st;
     if ((st = ensure_queue(w)) != KPM_OK) return st;
     double* eta = opts.eta_out;
     if (full && !eta) {
-        if ((st = grow(&w.eta, &w.etabytes, static_cast<size_t>(M) * R * 2 * sizeof(double), "hipMalloc(eta)")) !=
+        if ((st = grow(&w.eta, &w.etabytes, static_cast<size_t>(M) * G * 2 * sizeof(double), "hipMalloc(eta)")) !=
             KPM_OK)
             return st;
         eta = w.eta;
@@ -876,46 +893,51 @@ kpm_status kpm_moments(const kpm_hamiltonian* Hc, const void* V0, int32_t R, int
         mu_dev = w.mu;
     }
     if (full && opts.check && (st = ensure_flag(w)) != KPM_OK) return st;
-    const int grid = launch_grid(H, R);
-    const size_t slot_elems = static_cast<size_t>(grid) * 3 * R;
+    const int grid = launch_grid(H, G);
+    const size_t slot_elems = static_cast<size_t>(grid) * 3 * G;
     const size_t bytes = static_cast<size_t>(H->nrows) * 2 * R * real_size(H->dtype);
     void* A = w.vbuf[0];
     void* B = w.vbuf[1];
     const double inv_a = 1.0 / H->a, b = H->b;
     const int variant = opts.variant;
 
-    // the launch sequence of one call, on stream q
+    // the launch sequence of one call, on stream q: per column group, its
+    // start vectors into A, the M/2 sweeps, the reductions and eta -> mu
     auto enqueue = [&](hipStream_t q, bool capturing) -> kpm_status {
-        // nu_0 -> A (the caller's block stays untouched)
-        KPM_HIP(launch_copy16(A, V0, bytes, q), "copy V0");
-        for (int k = 0; k < sweeps; ++k) {
-            const int sl = k % kReduceEvery;
-            if (sl == 0)   // tile counters of the next kReduceEvery sweeps
-                KPM_HIP(launch_zero_ints(w.queue, kReduceEvery * kXcds, q), "zero kernel");
-            SweepArgs a{H->val, H->col, H->nrows, nullptr, nullptr, sched, 0.0, 0.0, 0.0,
-                        full ? w.partials + sl * slot_elems : nullptr, grid};
-            a.queue = w.queue + sl * kXcds;
-            for (int j = 0; j < 3; ++j) a.L[j] = H->L[j];
-            if (k == 0) {
-                // nu_1 = Htilde nu_0 = (1/a) H nu_0 - (b/a) nu_0
-                a.V = A; a.W = B; a.alpha = inv_a; a.beta = -b * inv_a; a.gamma = 0.0;
-            } else {
-                // swap roles: V = nu_k, W = nu_{k-1} -> nu_{k+1} = 2 Htilde nu_k - nu_{k-1}
-                if (k % 2 == 1) { a.V = B; a.W = A; } else { a.V = A; a.W = B; }
-                a.alpha = 2.0 * inv_a; a.beta = -2.0 * b * inv_a; a.gamma = -1.0;
+        for (int c0 = 0; c0 < R; c0 += G) {
+            // nu_0 -> A (the caller's block stays untouched)
+            if (grouped) KPM_HIP(launch_columns(H->dtype, H->nrows, R, c0, G, V0, A, q), "copy V0 columns");
+            else KPM_HIP(launch_copy16(A, V0, bytes, q), "copy V0");
+            for (int k = 0; k < sweeps; ++k) {
+                const int sl = k % kReduceEvery;
+                if (sl == 0)   // tile counters of the next kReduceEvery sweeps
+                    KPM_HIP(launch_zero_ints(w.queue, kReduceEvery * kXcds, q), "zero kernel");
+                SweepArgs a{H->val, H->col, H->nrows, nullptr, nullptr, sched, 0.0, 0.0, 0.0,
+                            full ? w.partials + sl * slot_elems : nullptr, grid};
+                a.queue = w.queue + sl * kXcds;
+                for (int j = 0; j < 3; ++j) a.L[j] = H->L[j];
+                if (k == 0) {
+                    // nu_1 = Htilde nu_0 = (1/a) H nu_0 - (b/a) nu_0
+                    a.V = A; a.W = B; a.alpha = inv_a; a.beta = -b * inv_a; a.gamma = 0.0;
+                } else {
+                    // swap roles: V = nu_k, W = nu_{k-1} -> nu_{k+1} = 2 Htilde nu_k - nu_{k-1}
+                    if (k % 2 == 1) { a.V = B; a.W = A; } else { a.V = A; a.W = B; }
+                    a.alpha = 2.0 * inv_a; a.beta = -2.0 * b * inv_a; a.gamma = -1.0;
+                }
+                KPM_HIP(launch_any_sweep(H, G, variant, a, q, capturing), "sweep kernel");
+                if (full && (sl == kReduceEvery - 1 || k == sweeps - 1))
+                    KPM_HIP(launch_reduce_partials(w.partials, sl + 1, grid, G, k - sl, eta, q), "reduce kernel");
             }
-            KPM_HIP(launch_any_sweep(H, R, variant, a, q, capturing), "sweep kernel");
-            if (full && (sl == kReduceEvery - 1 || k == sweeps - 1))
-                KPM_HIP(launch_reduce_partials(w.partials, sl + 1, grid, R, k - sl, eta, q), "reduce kernel");
+            if (full)
+                KPM_HIP(launch_eta_to_mu(eta, G, M, mu_dev + static_cast<size_t>(c0) * M, q), "eta_to_mu kernel");
         }
-        if (full) KPM_HIP(launch_eta_to_mu(eta, R, M, mu_dev, q), "eta_to_mu kernel");
         return KPM_OK;
     };
 
     if (opts.use_graph) {
         std::vector<unsigned char> key;
         const kpm_sweep_tuning t = get_tuning();
-        key_add(key, V0); key_add(key, mu_dev); key_add(key, eta); key_add(key, R); key_add(key, M);
+        key_add(key, V0); key_add(key, mu_dev); key_add(key, eta); key_add(key, R); key_add(key, G); key_add(key, M);
         key_add(key, H->a); key_add(key, H->b); key_add(key, variant); key_add(key, t); key_add(key, grid);
         key_add(key, A); key_add(key, B); key_add(key, w.partials); key_add(key, w.queue); key_add(key, sched);
         if (!w.exec || w.graph_key != key) {

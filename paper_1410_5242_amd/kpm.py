@@ -86,7 +86,7 @@ class CsrDesc(ctypes.Structure):
 class RunOpts(ctypes.Structure):
     _fields_ = [("check", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("variant", ctypes.c_int32),
                 ("mu_on_host", ctypes.c_int32), ("tuning", ctypes.POINTER(SweepTuning)),
-                ("eta_out", ctypes.c_void_p)]
+                ("eta_out", ctypes.c_void_p), ("group", ctypes.c_int32)]
 
 
 class SweepPlan(ctypes.Structure):
@@ -371,13 +371,15 @@ def _tuning_struct(tuning):
 
 def moments(H: Hamiltonian, V0: torch.Tensor, M: int, mu: torch.Tensor | None = None,
             eta: torch.Tensor | None = None, check: bool = True, graph: bool = False, variant: str = "full",
-            tuning: dict | None = None, stream=None):
+            tuning: dict | None = None, group: int = 0, stream=None):
     """kpm_moments: mu[R][M] (float64) for the [N][R] start block V0.
 
     mu may be a device tensor (default) or a host numpy array (filled in place, the call
     synchronises); graph=True captures the launch sequence once and replays it; variant
     "nodot" runs the recurrence without the scalar products (mu is not written); tuning is a
-    per-call launch shape (dict of kpm_sweep_tuning fields)."""
+    per-call launch shape (dict of kpm_sweep_tuning fields); group > 0 runs the columns as
+    independent groups of that width (0: only where the whole block exceeds what the sweeps
+    address)."""
     if V0.dim() != 2 or V0.shape[0] != H.N:
         raise ValueError("V0 must be [N][R]")
     if V0.dtype != H.torch_dtype:
@@ -393,6 +395,7 @@ def moments(H: Hamiltonian, V0: torch.Tensor, M: int, mu: torch.Tensor | None = 
     if t is not None:
         opts.tuning = ctypes.pointer(t)
     opts.eta_out = _dptr(eta).value if eta is not None else None
+    opts.group = int(group)
     if isinstance(mu, np.ndarray):
         if mu.dtype != np.float64 or mu.shape != (R, M) or not mu.flags.c_contiguous:
             raise ValueError("host mu must be a contiguous float64 [R][M] array")

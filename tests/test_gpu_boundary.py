@@ -248,3 +248,66 @@ def test_stream_read_kernel_sums_every_unit(n, wg, nt):
     assert float(part.sum().item()) == float(a.sum().item()) == float(n * (n - 1) // 2 - 7 * n)
     with pytest.raises(ValueError):       # c too small for the grid
         K.stream_kernel("read", part[:cus * wg - 1], a, wg_per_cu=wg)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_column_groups_give_the_whole_block_moments(dtype):
+    # kpm_run_opts.group: the R columns as independent recurrences of a
+    # narrower width (the matrix read once per group) give the moments of
+    # the whole block up to the order of the scalar products' sums
+    from paper_1410_5242_amd import kpm as K
+    L, R, M = (16, 16, 12), 64, 48
+    pot = inputs.potential(L, 1.0, 5)
+    H = K.build_hamiltonian(L, pot, dtype=dtype)
+    v0 = inputs.phase_block(H.N, R, 8)
+    V0 = torch.from_numpy(v0.astype(np.complex128 if dtype == "c128" else np.complex64)).cuda()
+    whole = K.moments(H, V0, M).cpu().numpy()
+    tol = 1e-13 if dtype == "c128" else 1e-6
+    for g in (32, 16, 1):
+        mu = K.moments(H, V0, M, group=g).cpu().numpy()
+        assert np.abs(mu - whole).max() <= tol, g
+    Ho = O.ti_hamiltonian(L, pot)
+    a, b = O.scaling(*O.gershgorin(Ho))
+    cols = [3, 40]
+    ref = O.kpm_moments(Ho, a, b, v0[:, cols], M)
+    mu = K.moments(H, V0, M, group=16).cpu().numpy()
+    assert np.abs(mu[cols] - ref).max() <= (1e-12 if dtype == "c128" else 1e-5)
+    # replayed from a graph: the whole grouped sequence, every replay equal
+    g1 = K.moments(H, V0, M, group=16, graph=True).cpu().numpy()
+    g2 = K.moments(H, V0, M, group=16, graph=True).cpu().numpy()
+    assert np.array_equal(g1, mu) and np.array_equal(g2, mu)
+    # a width that does not divide R, or a raw eta wanted from several groups
+    with pytest.raises(K.KPMError) as e:
+        K.moments(H, V0, M, group=3)
+    assert e.value.status == K.KPM_EINVAL
+    eta = torch.zeros((M, R, 2), dtype=torch.float64, device="cuda")
+    with pytest.raises(K.KPMError) as e:
+        K.moments(H, V0, M, group=32, eta=eta)
+    assert e.value.status == K.KPM_ENOTSUP
+    H.close()
+
+
+@pytest.mark.slow
+def test_block_beyond_4_gib_runs_in_column_groups_on_the_lattice_sweep():
+    # 128 x 128 x 64 lattice at R = 64 in complex128: the [N][64] block is
+    # 4 GiB, past the 32-bit offsets of the fast sweeps; kpm_moments splits it
+    # into two 32-column groups on the lattice sweep.  Two sampled columns
+    # against the oracle over the first 8 moments.
+    from paper_1410_5242_amd import kpm as K
+    L, R, M, seed = (128, 128, 64), 64, 8, 2
+    pot = inputs.potential(L, 2.0, 0)
+    H = K.build_hamiltonian(L, pot)
+    assert K.sweep_kernel(H, 32) == "lattice_kernel"
+    V0 = K.random_phase_block(H.N, R, seed, "c128")
+    assert V0.numel() * 16 >= 1 << 32
+    mu = K.moments(H, V0, M).cpu().numpy()
+    del V0
+    torch.cuda.empty_cache()
+    cols = [5, 40]
+    v0 = O.phase_block_counter(H.N, R, seed)[:, cols]
+    Ho = O.ti_hamiltonian(L, pot)
+    a, b = O.scaling(*O.gershgorin(Ho))
+    ref = O.kpm_moments(Ho, a, b, v0, M)
+    assert np.abs(mu[cols] - ref).max() <= 1e-12
+    assert np.abs(mu[:, 0] - 1.0).max() <= 1e-12
+    H.close()
