@@ -495,10 +495,12 @@ kpm_status kpm_sweep_kernel(const kpm_hamiltonian* H, int32_t R, int32_t* kernel
  * the automatic choice (0 2-D blocks per die, 1 runs of tile rows, 2
  * round-robin; -1 for the other kernels); pieces = z-pieces per pencil
  * (1 = whole pencils; -1 for the other kernels); halves = 32-column passes
- * of the lattice sweep over the block (-1 for the other kernels).
- * Errors: KPM_EINVAL. */
+ * of the lattice sweep over the block (-1 for the other kernels); group =
+ * the column-group width kpm_moments takes for this block by default (R:
+ * one recurrence; less where the block reaches 4 GiB), in which case the
+ * other fields describe a sweep of one group.  Errors: KPM_EINVAL. */
 typedef struct {
-    int32_t kernel, grid, tile_order, pieces, halves;
+    int32_t kernel, grid, tile_order, pieces, halves, group;
 } kpm_sweep_plan_info;
 kpm_status kpm_sweep_plan(const kpm_hamiltonian* H, int32_t R, const struct kpm_sweep_tuning* tuning,
                           kpm_sweep_plan_info* out);

@@ -52,6 +52,16 @@ kpm_status check_device(const kpm_hamiltonian* H) {
     return KPM_OK;
 }
 
+// Column-group width kpm_moments takes by default: the whole block, or the
+// widest supported width whose block the sweeps can address (32-bit buffer
+// offsets, the padding row of imported matrices included).
+int default_group(const kpm_hamiltonian* H, int R) {
+    const uint64_t lim = (1ull << 32) - (1ull << 24);
+    int G = R;
+    while (G > 1 && (static_cast<uint64_t>(H->nrows) + 1) * G * 2 * real_size(H->dtype) >= lim) G /= 2;
+    return G;
+}
+
 // The SELL-C-sigma sweep addresses a block with 32-bit offsets, the padding
 // column N included.
 kpm_status check_sell_block(const kpm_hamiltonian* H, int R) {
@@ -854,17 +864,11 @@ kpm_status kpm_moments(const kpm_hamiltonian* Hc, const void* V0, int32_t R, int
     // column groups: the caller's width, or the widest supported width whose
     // block the sweeps can address (32-bit buffer offsets, the padding row
     // of imported matrices included)
-    int G = R;
+    int G = default_group(H, R);
     if (opts.group != 0) {
         if (!r_supported(opts.group) || R % opts.group != 0)
             return fail(KPM_EINVAL, "group must be one of 1, 2, 4, ..., 64 and divide R");
         G = opts.group;
-    } else {
-        const uint64_t lim = (1ull << 32) - (1ull << 24);
-        auto fits = [&](int g) {
-            return (static_cast<uint64_t>(H->nrows) + 1) * g * 2 * real_size(H->dtype) < lim;
-        };
-        while (G > 1 && !fits(G)) G /= 2;
     }
     const bool grouped = G < R;
     if (grouped && opts.eta_out) return fail(KPM_ENOTSUP, "eta_out needs the whole block in one recurrence");
@@ -1342,12 +1346,14 @@ kpm_status kpm_sweep_plan(const kpm_hamiltonian* Hc, int32_t R, const kpm_sweep_
     kpm_status st;
     if (tuning && (st = check_tuning(*tuning)) != KPM_OK) return st;
     TuningScope scope(tuning);
-    const bool lat = use_lattice(Hc, R);
-    out->kernel = sweep_kind(Hc, R);
-    out->grid = launch_grid(Hc, R);
+    const int G = default_group(Hc, R);
+    const bool lat = use_lattice(Hc, G);
+    out->kernel = sweep_kind(Hc, G);
+    out->grid = launch_grid(Hc, G);
     out->tile_order = lat ? lattice_order(Hc, out->grid) : -1;
-    out->pieces = lat ? lattice_pieces(Hc, R, out->grid, get_tuning().prefetch) : -1;
-    out->halves = lat ? R / 32 : -1;
+    out->pieces = lat ? lattice_pieces(Hc, G, out->grid, get_tuning().prefetch) : -1;
+    out->halves = lat ? G / 32 : -1;
+    out->group = G;
     return KPM_OK;
 }
 

@@ -91,7 +91,7 @@ class RunOpts(ctypes.Structure):
 
 class SweepPlan(ctypes.Structure):
     _fields_ = [("kernel", ctypes.c_int32), ("grid", ctypes.c_int32), ("tile_order", ctypes.c_int32),
-                ("pieces", ctypes.c_int32), ("halves", ctypes.c_int32)]
+                ("pieces", ctypes.c_int32), ("halves", ctypes.c_int32), ("group", ctypes.c_int32)]
 
 
 _LIB = None
@@ -635,12 +635,13 @@ def sweep_kernel(H: Hamiltonian, R: int) -> str:
 
 
 def sweep_plan(H: Hamiltonian, R: int, tuning: dict | None = None) -> dict:
-    """kpm_sweep_plan: kernel, grid, resolved tile order, z-pieces and 32-column halves of a sweep."""
+    """kpm_sweep_plan: kernel, grid, resolved tile order, z-pieces and 32-column halves of a sweep, and the
+    column-group width kpm_moments takes for the block by default."""
     p = SweepPlan()
     t = _tuning_struct(tuning)
     _check(lib().kpm_sweep_plan(H.handle, int(R), ctypes.byref(t) if t is not None else None, ctypes.byref(p)))
     return {"kernel": SWEEP_KERNELS[p.kernel], "grid": p.grid, "tile_order": p.tile_order, "pieces": p.pieces,
-            "halves": p.halves}
+            "halves": p.halves, "group": p.group}
 
 
 def sweep_profile_enable(on=True):

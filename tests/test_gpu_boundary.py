@@ -298,6 +298,9 @@ def test_block_beyond_4_gib_runs_in_column_groups_on_the_lattice_sweep():
     pot = inputs.potential(L, 2.0, 0)
     H = K.build_hamiltonian(L, pot)
     assert K.sweep_kernel(H, 32) == "lattice_kernel"
+    plan = K.sweep_plan(H, R)
+    assert plan["group"] == 32 and plan["kernel"] == "lattice_kernel" and plan["halves"] == 1
+    assert K.sweep_plan(H, 32)["group"] == 32
     V0 = K.random_phase_block(H.N, R, seed, "c128")
     assert V0.numel() * 16 >= 1 << 32
     mu = K.moments(H, V0, M).cpu().numpy()

@@ -309,7 +309,7 @@ def test_default_layout_and_kernel_report():
     assert (info["C"], info["sigma"]) == (8, 1024)
     plan = K.sweep_plan(H, 32)
     assert plan["kernel"] == "sell_sweep_kernel" and plan["grid"] >= 1
-    assert plan["tile_order"] == -1 and plan["pieces"] == -1 and plan["halves"] == -1
+    assert plan["tile_order"] == -1 and plan["pieces"] == -1 and plan["halves"] == -1 and plan["group"] == 32
     Hl = K.build_hamiltonian((4, 4, 4), np.zeros(64))
     assert K.sell_info(Hl) == {"C": 0, "sigma": 0, "nchunks": 0, "stored": 0, "nnz": 0}
     Hl.close()
