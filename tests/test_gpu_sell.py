@@ -113,6 +113,9 @@ def test_sell_moments_every_block_width(R):
     ref = O.kpm_moments(Ho, a, b, v0, M)
     mu = K.moments(H, torch.from_numpy(v0).cuda(), M).cpu().numpy()
     assert np.abs(mu - ref).max() <= TOL_C128
+    if R >= 16:   # the same block as column groups (staged passes of a narrower width)
+        mu_g = K.moments(H, torch.from_numpy(v0).cuda(), M, group=R // 8).cpu().numpy()
+        assert np.abs(mu_g - ref).max() <= TOL_C128
     H.close()
 
 
