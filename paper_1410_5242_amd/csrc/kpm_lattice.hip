@@ -199,8 +199,10 @@ __device__ inline Nb xy_neighbour(int nx, int ny, int Lx, int Ly, int px, int py
 
 // NSL: 32-column slices per block row (0: run-time value nsl, for R > 32).
 // SPLIT: pencils are cut into npc z-pieces (run-time npc); otherwise a work
-// item is a whole pencil.
-template <typename T, int VARIANT, int VALS, int STREAM, int NSL, bool SPLIT>
+// item is a whole pencil.  BIG: V, W or the matrix reach 4 GiB; every
+// access then goes through a descriptor over the one z-plane it reads or
+// writes (32-bit offsets within a plane), built where it is used.
+template <typename T, int VARIANT, int VALS, int STREAM, int NSL, bool SPLIT, bool BIG = false>
 __global__ void __launch_bounds__(kThreadsL)
 lattice_kernel(const T* __restrict__ val, const T* __restrict__ V, T* __restrict__ W,
                T alpha, T beta, T gamma, double* __restrict__ partials,
@@ -249,6 +251,18 @@ lattice_kernel(const T* __restrict__ val, const T* __restrict__ V, T* __restrict
     auto vrs = [&](bool on) { return rsrc(V, on ? vbytes : 0u); };
     auto wrs = [&](bool on) { return rsrc(W, on ? vbytes : 0u); };
     auto mrs = [&](bool on) { return rsrc(val, on ? mbytes : 0u); };
+    // BIG: descriptors over plane z of V, W and the matrix (size 0 when off)
+    const uint64_t pvb = static_cast<uint64_t>(4 * plane_sites) * rowb;
+    const uint64_t pmb = static_cast<uint64_t>(4 * plane_sites) * 2 * kWidth * sizeof(T);
+    auto vrsp = [&](bool on, int64_t z) {
+        return rsrc(reinterpret_cast<const char*>(V) + (on ? z : 0) * pvb, on ? static_cast<unsigned>(pvb) : 0u);
+    };
+    auto wrsp = [&](bool on, int64_t z) {
+        return rsrc(reinterpret_cast<const char*>(W) + (on ? z : 0) * pvb, on ? static_cast<unsigned>(pvb) : 0u);
+    };
+    auto mrsp = [&](bool on, int64_t z) {
+        return rsrc(reinterpret_cast<const char*>(val) + (on ? z : 0) * pmb, on ? static_cast<unsigned>(pmb) : 0u);
+    };
 
     if (wave < 4) zrow[wave][lane] = T(0);
 
@@ -345,27 +359,49 @@ lattice_kernel(const T* __restrict__ val, const T* __restrict__ V, T* __restrict
         // plane zp (on = the step exists)
         auto load_step = [&](bool on, int zp, StepRegs<T>& r) {
             const int64_t z = on ? zp : 0;
-            const __amdgpu_buffer_rsrc_t hx = vrs(on && hx_on);
-            const __amdgpu_buffer_rsrc_t hy = vrs(on && hy_on);
+            if constexpr (BIG) {
+                const __amdgpu_buffer_rsrc_t hx = vrsp(on && hx_on, z);
+                const __amdgpu_buffer_rsrc_t hy = vrsp(on && hy_on, z);
 #pragma unroll
-            for (int o = 0; o < 4; ++o) r.h[0][o] = gload<T>(hx, voff, roff(4 * (hxs + plane_sites * z) + o));
+                for (int o = 0; o < 4; ++o) r.h[0][o] = gload<T>(hx, voff, roff(4 * hxs + o));
 #pragma unroll
-            for (int o = 0; o < 4; ++o) r.h[1][o] = gload<T>(hy, voff, roff(4 * (hys + plane_sites * z) + o));
-            const int64_t base = 4 * (sxy + plane_sites * z);
-            if constexpr (VEC_VALS) r.hv = SiteRec<T>::load(mrs(on && active), rec_off, base / 4);
+                for (int o = 0; o < 4; ++o) r.h[1][o] = gload<T>(hy, voff, roff(4 * hys + o));
+                r.hv = SiteRec<T>::load(mrsp(on && active, z), rec_off, sxy);
+            } else {
+                const __amdgpu_buffer_rsrc_t hx = vrs(on && hx_on);
+                const __amdgpu_buffer_rsrc_t hy = vrs(on && hy_on);
+#pragma unroll
+                for (int o = 0; o < 4; ++o) r.h[0][o] = gload<T>(hx, voff, roff(4 * (hxs + plane_sites * z) + o));
+#pragma unroll
+                for (int o = 0; o < 4; ++o) r.h[1][o] = gload<T>(hy, voff, roff(4 * (hys + plane_sites * z) + o));
+                const int64_t base = 4 * (sxy + plane_sites * z);
+                if constexpr (VEC_VALS) r.hv = SiteRec<T>::load(mrs(on && active), rec_off, base / 4);
+            }
         };
         // this site's rows of V in plane zp (zeros when off)
         auto load_wold = [&](bool on, int zp, StepRegs<T>& r) {
-            const __amdgpu_buffer_rsrc_t wl = wrs(on && active && need_w);
-            const int64_t base = 4 * (sxy + plane_sites * (on ? zp : 0));
+            if constexpr (BIG) {
+                const __amdgpu_buffer_rsrc_t wl = wrsp(on && active && need_w, zp);
 #pragma unroll
-            for (int o = 0; o < 4; ++o) r.w[o] = wload<T, (STREAM & 1) != 0>(wl, voff, roff(base + o));
+                for (int o = 0; o < 4; ++o) r.w[o] = wload<T, (STREAM & 1) != 0>(wl, voff, roff(4 * sxy + o));
+            } else {
+                const __amdgpu_buffer_rsrc_t wl = wrs(on && active && need_w);
+                const int64_t base = 4 * (sxy + plane_sites * (on ? zp : 0));
+#pragma unroll
+                for (int o = 0; o < 4; ++o) r.w[o] = wload<T, (STREAM & 1) != 0>(wl, voff, roff(base + o));
+            }
         };
         auto load_plane = [&](bool on, int zp, T (&p)[4]) {
-            const __amdgpu_buffer_rsrc_t rs = vrs(on && active);
-            const int64_t base = 4 * (sxy + plane_sites * (on ? zp : 0));
+            if constexpr (BIG) {
+                const __amdgpu_buffer_rsrc_t rs = vrsp(on && active, zp);
 #pragma unroll
-            for (int o = 0; o < 4; ++o) p[o] = gload<T>(rs, voff, roff(base + o));
+                for (int o = 0; o < 4; ++o) p[o] = gload<T>(rs, voff, roff(4 * sxy + o));
+            } else {
+                const __amdgpu_buffer_rsrc_t rs = vrs(on && active);
+                const int64_t base = 4 * (sxy + plane_sites * (on ? zp : 0));
+#pragma unroll
+                for (int o = 0; o < 4; ++o) p[o] = gload<T>(rs, voff, roff(base + o));
+            }
         };
 
         // One z-step.  Register sets alternate between even and odd steps,
@@ -401,6 +437,9 @@ lattice_kernel(const T* __restrict__ val, const T* __restrict__ V, T* __restrict
             const T* zdn = plane_of(s - 1) >= 0 ? &ring[(s - 1) & 3][wave][0][lane] : &zrow[0][lane];
             const T* zup = plane_of(s + 1) >= 0 ? &ring[(s + 1) & 3][wave][0][lane] : &zrow[0][lane];
             const int64_t site = sxy + plane_sites * s;
+            // new-W stores of this step (BIG: a descriptor over plane s)
+            __amdgpu_buffer_rsrc_t wss = wst;
+            if constexpr (BIG) wss = wrsp(active, s);
             if constexpr (VALS == 3) {
                 // this step's record into the wave's LDS slot (the previous
                 // step's reads of the slot come first: LDS executes a wave's
@@ -467,12 +506,13 @@ lattice_kernel(const T* __restrict__ val, const T* __restrict__ V, T* __restrict
                     }
                 }
                 const T hv = fma(sgn, swap_lanes(B), A);
+                const int64_t srow = BIG ? 4 * sxy + o : row;   // row within the stores' descriptor
                 if constexpr (VARIANT == KPM_PLAIN) {
-                    wstore<T, (STREAM & 2) != 0>(hv, wst, voff, roff(row));
+                    wstore<T, (STREAM & 2) != 0>(hv, wss, voff, roff(srow));
                 } else {
                     // cur.w holds zeros when no old W is read (need_w false)
                     const T w = fma(gamma, cur.w[o], fma(alpha, hv, beta * v[0]));
-                    wstore<T, (STREAM & 2) != 0>(w, wst, voff, roff(row));
+                    wstore<T, (STREAM & 2) != 0>(w, wss, voff, roff(srow));
                     if constexpr (VARIANT == KPM_FULL) {
                         const double vd = static_cast<double>(v[0]);
                         const double vsw = static_cast<double>(swap_lanes(v[0]));
@@ -557,15 +597,24 @@ int pieces(int ntiles, int grid, int Lz) {
     return cost(2) < cost(1) ? 2 : 1;
 }
 
+// V, W or the matrix reach 4 GiB: the per-plane descriptors of BIG
+bool big_arrays(const int L[3], int R, size_t real) {
+    const uint64_t n = 4ull * L[0] * L[1] * L[2];
+    return n * R * 2 * real >= (1ull << 32) || n * kWidth * 2 * real >= (1ull << 32);
+}
+
 template <typename T, int STREAM>
 hipError_t launch_ts(int variant, const LatticeArgs& a, hipStream_t s) {
     const int ntx = (a.L[0] + kP - 1) / kP, nty = (a.L[1] + kP - 1) / kP;
     const int ntiles = ntx * nty;
-    // pencils are split only at R = 32 on the record path (prefetch 2)
-    const int npc = (a.R == kR && a.prefetch == 2) ? pieces(ntiles, a.grid, a.L[2]) : 1;
+    const bool big = big_arrays(a.L, a.R, sizeof(T));
+    // pencils are split only at R = 32 on the record path (prefetch 2), and
+    // not with the per-plane descriptors
+    const int npc = (!big && a.R == kR && a.prefetch == 2) ? pieces(ntiles, a.grid, a.L[2]) : 1;
 #define KPM_LAUNCH(VAR, VALS, NSL) KPM_LAUNCH_S(VAR, VALS, NSL, false)
-#define KPM_LAUNCH_S(VAR, VALS, NSL, SPLIT)                                                      \
-    lattice_kernel<T, VAR, VALS, STREAM, NSL, SPLIT><<<a.grid, kThreadsL, 0, s>>>(               \
+#define KPM_LAUNCH_S(VAR, VALS, NSL, SPLIT) KPM_LAUNCH_B(VAR, VALS, NSL, SPLIT, false)
+#define KPM_LAUNCH_B(VAR, VALS, NSL, SPLIT, BIG)                                                 \
+    lattice_kernel<T, VAR, VALS, STREAM, NSL, SPLIT, BIG><<<a.grid, kThreadsL, 0, s>>>(          \
         static_cast<const T*>(a.val), static_cast<const T*>(a.V), static_cast<T*>(a.W),          \
         static_cast<T>(a.alpha), static_cast<T>(a.beta), static_cast<T>(a.gamma), a.partials,  \
         a.L[0], a.L[1], a.L[2], a.periodic[0], a.periodic[1], a.periodic[2], ntx, ntiles, a.order, \
@@ -579,7 +628,10 @@ hipError_t launch_ts(int variant, const LatticeArgs& a, hipStream_t s) {
 // scalar loads.  Blocks wider than 32 columns always take the record path.
     constexpr int REC = sizeof(T) == 4 ? 3 : 1;
 #define KPM_LAUNCH_V(VAR)                          \
-    if (a.R > kR) {                                \
+    if (big) {                                     \
+        if (a.R > kR) KPM_LAUNCH_B(VAR, REC, 0, false, true);  \
+        else KPM_LAUNCH_B(VAR, REC, 1, false, true);           \
+    } else if (a.R > kR) {                         \
         KPM_LAUNCH(VAR, REC, 0);                   \
     } else if (npc > 1) {                          \
         KPM_LAUNCH_S(VAR, REC, 1, true);           \
@@ -598,6 +650,7 @@ hipError_t launch_ts(int variant, const LatticeArgs& a, hipStream_t s) {
     default: return hipErrorInvalidValue;
     }
 #undef KPM_LAUNCH_V
+#undef KPM_LAUNCH_B
 #undef KPM_LAUNCH_S
 #undef KPM_LAUNCH
     return hipGetLastError();
@@ -625,9 +678,11 @@ bool lattice_supported(const kpm_hamiltonian* H, int R) {
     // every tile must be at least 2 sites wide in x and y (at most one
     // neighbour across each tile edge): no side with L mod 4 == 1
     if (H->L[0] % lattice::kP == 1 || H->L[1] % lattice::kP == 1) return false;
-    const uint64_t vbytes = static_cast<uint64_t>(H->nrows) * 2 * R *
-                            (H->dtype == KPM_C128 ? sizeof(double) : sizeof(float));
-    return vbytes < (1ull << 32) && H->L[0] > 0;
+    // arrays of 4 GiB or more take per-plane descriptors: one plane of the
+    // block and of the matrix must stay below 4 GiB
+    const size_t real = H->dtype == KPM_C128 ? sizeof(double) : sizeof(float);
+    const uint64_t plane_rows = 4ull * H->L[0] * H->L[1];
+    return H->L[0] > 0 && plane_rows * R * 2 * real < (1ull << 32) && plane_rows * kWidth * 2 * real < (1ull << 32);
 }
 
 int lattice_grid(const kpm_hamiltonian* H) {
@@ -649,7 +704,10 @@ int lattice_grid(const kpm_hamiltonian* H) {
 }
 
 int lattice_pieces(const kpm_hamiltonian* H, int R, int grid, int prefetch) {
-    // as launch_ts: pencils are split only at R = 32 on the record path
+    // as launch_ts: pencils are split only at R = 32 on the record path,
+    // with the whole-array descriptors
+    const size_t real = H->dtype == KPM_C128 ? sizeof(double) : sizeof(float);
+    if (lattice::big_arrays(H->L, R, real)) return 1;
     return (R == lattice::kR && prefetch == 2) ? lattice::pieces(lattice_tiles(H), grid, H->L[2]) : 1;
 }
 

@@ -288,29 +288,34 @@ def test_column_groups_give_the_whole_block_moments(dtype):
 
 
 @pytest.mark.slow
-def test_block_beyond_4_gib_runs_in_column_groups_on_the_lattice_sweep():
-    # 128 x 128 x 64 lattice at R = 64 in complex128: the [N][64] block is
-    # 4 GiB, past the 32-bit offsets of the fast sweeps; kpm_moments splits it
-    # into two 32-column groups on the lattice sweep.  Two sampled columns
-    # against the oracle over the first 8 moments.
+@pytest.mark.parametrize("L,R,dtype,group,auto", [
+    ((128, 128, 64), 64, "c128", 0, 32),     # 4 GiB block: two 32-column groups by default
+    ((128, 128, 64), 64, "c128", 64, 32),    # the whole block: per-plane descriptors, two slices
+    ((128, 128, 128), 32, "c128", 0, 32),    # 4 GiB even at 32 columns: per-plane descriptors
+    ((128, 128, 128), 64, "c64", 64, 32),    # the whole 4 GiB block in complex64, per plane
+])
+def test_blocks_of_4_gib_on_the_lattice_sweep(L, R, dtype, group, auto):
+    # blocks past the 32-bit offsets of one buffer descriptor: the lattice
+    # sweep addresses V, W and the matrix plane by plane; two sampled
+    # columns against the oracle over the first 8 moments
     from paper_1410_5242_amd import kpm as K
-    L, R, M, seed = (128, 128, 64), 64, 8, 2
+    M, seed = 8, 2
+    say("4 GiB block", L, R, dtype, group)
     pot = inputs.potential(L, 2.0, 0)
-    H = K.build_hamiltonian(L, pot)
-    assert K.sweep_kernel(H, 32) == "lattice_kernel"
+    H = K.build_hamiltonian(L, pot, dtype=dtype)
     plan = K.sweep_plan(H, R)
-    assert plan["group"] == 32 and plan["kernel"] == "lattice_kernel" and plan["halves"] == 1
-    assert K.sweep_plan(H, 32)["group"] == 32
-    V0 = K.random_phase_block(H.N, R, seed, "c128")
-    assert V0.numel() * 16 >= 1 << 32
-    mu = K.moments(H, V0, M).cpu().numpy()
+    assert plan["kernel"] == "lattice_kernel" and plan["group"] == auto and plan["pieces"] == 1
+    V0 = K.random_phase_block(H.N, R, seed, dtype)
+    assert V0.numel() * V0.element_size() >= 1 << 32
+    mu = K.moments(H, V0, M, group=group).cpu().numpy()
     del V0
     torch.cuda.empty_cache()
-    cols = [5, 40]
-    v0 = O.phase_block_counter(H.N, R, seed)[:, cols]
+    H.close()
+    cols = [5, R - 3]
+    v0 = O.phase_block_counter(4 * L[0] * L[1] * L[2], R, seed)[:, cols].copy()
     Ho = O.ti_hamiltonian(L, pot)
     a, b = O.scaling(*O.gershgorin(Ho))
     ref = O.kpm_moments(Ho, a, b, v0, M)
-    assert np.abs(mu[cols] - ref).max() <= 1e-12
-    assert np.abs(mu[:, 0] - 1.0).max() <= 1e-12
-    H.close()
+    tol = 1e-12 if dtype == "c128" else 1e-5
+    assert np.abs(mu[cols] - ref).max() <= tol
+    assert np.abs(mu[:, 0] - 1.0).max() <= (1e-12 if dtype == "c128" else 1e-6)
