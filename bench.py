@@ -487,6 +487,42 @@ def leg_sell(sweeps: int = 10):
     return out
 
 
+def leg_large(M: int = 200):
+    """Blocks of 4 GiB or more, past one buffer descriptor's 32-bit offsets: the 128^3 lattice at
+    R = 32 in complex128 (the lattice sweep addresses V, W and the matrix plane by plane) and the
+    128 x 128 x 64 lattice at R = 64 (kpm_moments runs it as two 32-column groups).  Kernel time
+    per sweep of the whole block from the library's HIP events over M/2 sweeps, GB/s of the model
+    bytes Nnz (S_d + S_i) + 3 R S_d N of the whole block."""
+    import torch
+    from paper_1410_5242_amd import inputs, kpm
+    out = {"workload": f"TI lattices gamma = 2 (seed 0), complex128, M = {M}, device random-phase blocks",
+           "points": []}
+    for L, R in (((128, 128, 128), 32), ((128, 128, 64), 64)):
+        H = kpm.build_hamiltonian(L, inputs.potential(L, 2.0, 0))
+        V0 = kpm.random_phase_block(H.N, R, 1, "c128")
+        kpm.moments(H, V0, 8)
+        torch.cuda.synchronize()
+        kpm.sweep_profile_read()
+        kpm.sweep_profile_enable(True)
+        t0 = time.perf_counter()
+        kpm.moments(H, V0, M)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        kpm.sweep_profile_enable(False)
+        n, tot, lo, hi = kpm.sweep_profile_read()
+        plan = kpm.sweep_plan(H, R)
+        per_sweep_s = tot * 1e-3 / (M // 2)
+        byts = sweep_bytes(H.N, 13 * H.N, R, 16)
+        out["points"].append({"L": list(L), "R": R, "N": H.N, "block_GiB": round(H.N * R * 16 / 2 ** 30, 2),
+                              "kernel": plan["kernel"], "group": plan["group"],
+                              "ms_per_sweep": round(per_sweep_s * 1e3, 3),
+                              "GBps": round(byts / per_sweep_s / 1e9, 1), "seconds": round(dt, 3)})
+        del V0
+        H.close()
+        torch.cuda.empty_cache()
+    return out
+
+
 def leg_ladder(steps: int = 200, repeats: int = 3):
     """The paper's optimisation ladder on the 64^3 complex128 lattice, per start vector and KPM
     step (one moment pair): the naive algorithm (one SpMV and five BLAS-1 calls per step, one
@@ -804,10 +840,10 @@ def main():
     ap.add_argument("--batch-tuning", default=None,
                     help="waves,wg_per_cu,dynamic,slab for the batched leg instead of the tuning cache")
     ap.add_argument("--legs", default="small,variants,custom_roofline,ladder,precision,batched,spectral,slab,bounds,"
-                                      "sell,time_to_dos,oracle_subsets",
+                                      "sell,large,time_to_dos,oracle_subsets",
                     help="extra measurements after the headline step (comma separated): any of small, variants, "
-                         "custom_roofline, ladder, precision, batched, spectral, slab, bounds, sell, time_to_dos, "
-                         "oracle_subsets; or none")
+                         "custom_roofline, ladder, precision, batched, spectral, slab, bounds, sell, large, "
+                         "time_to_dos, oracle_subsets; or none")
     args = ap.parse_args()
     if args.batch_tuning:
         global BATCH_TUNING_OVERRIDE
@@ -949,7 +985,7 @@ def main():
     for name, fn in (("small", leg_small), ("variants", leg_variants), ("custom_roofline", leg_custom_roofline),
                      ("ladder", leg_ladder),
                      ("precision", leg_precision), ("batched", leg_batched), ("spectral", leg_spectral),
-                     ("slab", leg_slab), ("bounds", leg_bounds), ("sell", leg_sell),
+                     ("slab", leg_slab), ("bounds", leg_bounds), ("sell", leg_sell), ("large", leg_large),
                      ("time_to_dos", leg_time_to_dos)):
         if name in legs:
             log(f"[bench] leg {name}")
