@@ -172,3 +172,41 @@ def test_lattice_desc_sell_fields_are_validated_before_any_device_call(kpm):
         assert L.kpm_build_hamiltonian(ctypes.byref(d), None, ctypes.byref(out)) == kpm.KPM_EINVAL, (C, sigma)
         assert msg in L.kpm_last_error()
         assert out.value is None
+
+
+def test_layout_properties_on_random_patterns(kpm):
+    # random row-length patterns (empty rows, long rows, N not a multiple of
+    # C or sigma) under every chunk height and several sorting windows
+    hyp = pytest.importorskip("hypothesis")
+    st = hyp.strategies
+
+    @hyp.settings(max_examples=60, deadline=None, derandomize=True)
+    @hyp.given(lens=st.lists(st.integers(0, 40), min_size=1, max_size=300),
+               logc=st.integers(0, 6), mult=st.sampled_from([0, 1, 2, 5, 1000]))
+    def check(lens, logc, mult):
+        C = 1 << logc
+        sigma = 1 if mult == 0 else C * mult
+        lens = np.asarray(lens, dtype=np.int64)
+        rowptr = np.concatenate([[0], np.cumsum(lens)])
+        perm, width, start = kpm.sell_layout(rowptr, C, sigma)
+        N = lens.size
+        assert sorted(perm.tolist()) == list(range(N))
+        nch = (N + C - 1) // C
+        assert width.size == nch and start[0] == 0 and start.size == nch + 1
+        for c in range(nch):
+            assert width[c] == lens[perm[c * C:(c + 1) * C]].max()
+            assert start[c + 1] - start[c] == C * width[c]
+        w = 1 if sigma == 1 else sigma
+        for w0 in range(0, N, w):
+            win = perm[w0:w0 + w]
+            assert set(win.tolist()) == set(range(w0, min(N, w0 + w)))
+            if sigma > 1:
+                assert np.all(lens[win][:-1] >= lens[win][1:])
+        # stored entries never below the nonzeros; sorting never pads more
+        # than leaving the rows in order
+        assert start[-1] >= lens.sum()
+        if sigma > 1:
+            _, _, s1 = kpm.sell_layout(rowptr, C, 1)
+            assert start[-1] <= s1[-1]
+
+    check()
