@@ -184,7 +184,11 @@ kpm_status kpm_sell_info(const kpm_hamiltonian* H, int32_t* C, int32_t* sigma, i
  * V, W: device [N][R] blocks of H's dtype, V read-only, W updated in place;
  * V and W must not overlap.  eta: device [2][R] complex double, written for
  * FULL when non-NULL (it is reduced on the device, deterministically).
- * R in {1, 2, 4, 8, 16, 32, 64}.  Errors: KPM_EINVAL, KPM_ENOTSUP. */
+ * R in {1, 2, 4, 8, 16, 32, 64}.  Blocks of any size on a lattice H (the
+ * lattice sweep addresses arrays of 4 GiB or more plane by plane; the
+ * index-reading sweeps fall back to 64-bit addressing there); on an
+ * imported H an [N+1][R] block must stay below 4 GiB (kpm_moments splits
+ * larger ones into column groups).  Errors: KPM_EINVAL, KPM_ENOTSUP. */
 kpm_status kpm_aug_spmmv(const kpm_hamiltonian* H, const void* V, void* W, int32_t R,
                          double alpha, double beta, double gamma, int32_t variant,
                          double* eta, void* stream);
