@@ -209,12 +209,15 @@ typedef struct {
     const struct kpm_sweep_tuning* tuning;   /* launch shape for this call only (NULL: the process-wide
                                          kpm_set_sweep_tuning setting, read once at entry) */
     double* eta_out;     /* optional device [M][R] complex double: the raw products eta_n */
-    int32_t group;       /* column groups: 0 = the whole block in one recurrence, unless the sweeps
-                            could not address it (an [N+1][R] block of 4 GiB or more: then the
-                            widest supported width whose block fits); else a supported width
-                            dividing R: the R columns run as R / group independent recurrences of
-                            that width, one after the other, on work blocks of N x group (the
-                            matrix is read once per group and sweep).  Not with eta_out. */
+    int32_t group;       /* column groups: 0 = the library's choice: on a lattice the lattice sweep
+                            takes 32 columns at a time (R = 64 runs as two 32-column recurrences,
+                            unless eta_out is set); otherwise the whole block in one recurrence,
+                            unless the sweeps could not address it (an [N+1][R] block of 4 GiB or
+                            more: then the widest supported width whose block fits, at least 32
+                            on a lattice); else a supported width dividing R: the R columns run as
+                            R / group independent recurrences of that width, one after the other,
+                            on work blocks of N x group (the matrix is read once per group and
+                            sweep).  Not with eta_out. */
 } kpm_run_opts;
 
 /* Chebyshev moments for R start vectors (eq. "eq:kpm_iter", scalar products

@@ -54,18 +54,23 @@ kpm_status check_device(const kpm_hamiltonian* H) {
 
 bool use_lattice(const kpm_hamiltonian* H, int R);
 
-// Column-group width kpm_moments takes by default: the whole block where it
-// fits the sweeps' 32-bit buffer offsets (the padding row of imported
-// matrices included), else the widest supported width that does, except
-// that the groups stop at 32 columns where the lattice sweep runs there:
-// it then addresses its arrays plane by plane (128^3 sites at R = 32 in
-// complex128: 2.69 ms per sweep against 3.75 ms as 16-column groups on the
-// window sweep; where 32-column groups fit they are 5-7 % faster than the
-// whole block plane by plane).
-int default_group(const kpm_hamiltonian* H, int R) {
+// Column-group width kpm_moments takes by default.  On a lattice the
+// lattice sweep runs 32 columns at a time: for R = 64 two 32-column
+// recurrences beat one recurrence whose sweeps take both halves (64^3 and
+// 128 x 128 x 64, both precisions: 3.5-3.8 % faster; 96 x 96 x 64: 15 %),
+// so the block is split when the caller wants no raw eta of the whole
+// block (split = true).  Otherwise the whole block where it fits the
+// sweeps' 32-bit buffer offsets (the padding row of imported matrices
+// included), else the widest supported width that does, except that the
+// groups stop at 32 columns where the lattice sweep runs there: it then
+// addresses its arrays plane by plane (128^3 sites at R = 32 in complex128:
+// 2.69 ms per sweep against 3.75 ms as 16-column groups on the window
+// sweep).
+int default_group(const kpm_hamiltonian* H, int R, bool split) {
     const uint64_t lim = (1ull << 32) - (1ull << 24);
     auto fits = [&](int g) { return (static_cast<uint64_t>(H->nrows) + 1) * g * 2 * real_size(H->dtype) < lim; };
     int G = R;
+    if (split && R > 32 && use_lattice(H, 32)) G = 32;
     while (G > 1 && !fits(G) && !(G == 32 && use_lattice(H, 32))) G /= 2;
     return G;
 }
@@ -872,7 +877,7 @@ kpm_status kpm_moments(const kpm_hamiltonian* Hc, const void* V0, int32_t R, int
     // column groups: the caller's width, or the widest supported width whose
     // block the sweeps can address (32-bit buffer offsets, the padding row
     // of imported matrices included)
-    int G = default_group(H, R);
+    int G = default_group(H, R, opts.eta_out == nullptr);
     if (opts.group != 0) {
         if (!r_supported(opts.group) || R % opts.group != 0)
             return fail(KPM_EINVAL, "group must be one of 1, 2, 4, ..., 64 and divide R");
@@ -1354,7 +1359,7 @@ kpm_status kpm_sweep_plan(const kpm_hamiltonian* Hc, int32_t R, const kpm_sweep_
     kpm_status st;
     if (tuning && (st = check_tuning(*tuning)) != KPM_OK) return st;
     TuningScope scope(tuning);
-    const int G = default_group(Hc, R);
+    const int G = default_group(Hc, R, true);
     const bool lat = use_lattice(Hc, G);
     out->kernel = sweep_kind(Hc, G);
     out->grid = launch_grid(Hc, G);

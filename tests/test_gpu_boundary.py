@@ -173,7 +173,9 @@ def test_sweep_plan_of_the_headline_lattice():
     assert p["grid"] == min(256, cus - cus % 8)
     if cus >= 256:
         assert p["tile_order"] == 0
-    assert K.sweep_plan(H, 64)["halves"] == 2
+    # R = 64: kpm_moments runs two 32-column recurrences on the lattice sweep
+    p64 = K.sweep_plan(H, 64)
+    assert p64["kernel"] == "lattice_kernel" and p64["group"] == 32 and p64["halves"] == 1
     g = K.sweep_plan(H, 8)
     assert g["kernel"] == "gather_sweep_kernel" and g["pieces"] == -1
     assert K.sweep_plan(H, 32, tuning={"lattice": 0})["kernel"] == "window_sweep_kernel"
