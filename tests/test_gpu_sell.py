@@ -101,21 +101,24 @@ def test_sell_moments_match_oracle(C, sigma, R, dtype):
 
 
 @pytest.mark.parametrize("R", [1, 2, 8, 16, 64])
-def test_sell_moments_every_block_width(R):
-    say("sell moments R", R)
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_sell_moments_every_block_width(R, dtype):
+    say("sell moments R", R, dtype)
     K = kpm()
     N, M = 2500, 64
     rowptr, col, val, Ho = irregular(N, 4, tail=1.3, max_couplings=400)
-    H = K.import_csr(rowptr, col, val, C=8, sigma=64)
+    H = K.import_csr(rowptr, col, val, C=8, sigma=64, dtype=dtype)
     a, b = O.scaling(*O.gershgorin(Ho))
     K.set_scaling(H, a, b)
     v0 = inputs.phase_block(N, R, 5)
     ref = O.kpm_moments(Ho, a, b, v0, M)
-    mu = K.moments(H, torch.from_numpy(v0).cuda(), M).cpu().numpy()
-    assert np.abs(mu - ref).max() <= TOL_C128
+    V0 = torch.from_numpy(v0.astype(np.complex128 if dtype == "c128" else np.complex64)).cuda()
+    tol = TOL_C128 if dtype == "c128" else TOL_C64
+    mu = K.moments(H, V0, M).cpu().numpy()
+    assert np.abs(mu - ref).max() <= tol
     if R >= 16:   # the same block as column groups (staged passes of a narrower width)
-        mu_g = K.moments(H, torch.from_numpy(v0).cuda(), M, group=R // 8).cpu().numpy()
-        assert np.abs(mu_g - ref).max() <= TOL_C128
+        mu_g = K.moments(H, V0, M, group=R // 8).cpu().numpy()
+        assert np.abs(mu_g - ref).max() <= tol
     H.close()
 
 
